@@ -1,0 +1,163 @@
+"""ctypes front end of the C oracle (oracle.c).  TEST INFRASTRUCTURE ONLY.
+
+Inputs are plain numpy arrays in the layouts of the paper's Table of mesh
+data (Section 2), 0-based and row-major: q is (d, nq) float64, me is
+(d+1, nme) int32.  Outputs are numpy CSR arrays with int64 indices.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+OP = {"MASS": 0, "MASS_W": 1, "STIFF": 2, "ELAS": 3}
+STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_INDEX", 3: "ERR_DEGENERATE",
+          4: "ERR_OVERFLOW", 5: "ERR_NOMEM"}
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        super().__init__(f"oracle {where}: {STATUS.get(code, code)}")
+        self.code = code
+        self.name = STATUS.get(code, str(code))
+
+
+def lib_path() -> str:
+    return _LIB
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c with gcc (plain IEEE double: no fused multiply-add)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        lib = C.CDLL(_LIB)
+        P = C.c_void_p
+        i64 = C.c_int64
+        lib.oracle_validate.argtypes = [C.c_int, i64, i64, P]
+        lib.oracle_assemble.argtypes = [C.c_int, i64, i64, P, P, C.c_int, P, C.c_double,
+                                        C.c_double, i64, P, P, P, P, P]
+        lib.oracle_assemble_rows.argtypes = [C.c_int, i64, i64, P, P, C.c_int, P, C.c_double,
+                                             C.c_double, i64, P, i64, P, P, P, P, P]
+        lib.oracle_grad.argtypes = [C.c_int, i64, i64, P, P, P, P, P, P, P, P]
+        lib.oracle_element_matrix.argtypes = [C.c_int, C.c_int, P, P, C.c_double, C.c_double, P]
+        for f in (lib.oracle_validate, lib.oracle_assemble, lib.oracle_assemble_rows,
+                  lib.oracle_grad, lib.oracle_element_matrix):
+            f.restype = C.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _mesh_arrays(q, me):
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    me = np.ascontiguousarray(me, dtype=np.int32)
+    d = me.shape[0] - 1
+    return d, q, me
+
+
+def validate(d: int, nq: int, me) -> int:
+    me = np.ascontiguousarray(me, dtype=np.int32)
+    return _load().oracle_validate(d, nq, me.shape[1] if me.ndim == 2 else 0, _ptr(me))
+
+
+def assemble(q, me, op: str, w=None, lam: float = 1.0, mu: float = 0.5, nq: int | None = None):
+    """Full CSR: returns (row_ptr, col_idx, val, absval) with absval the
+    per-entry sum of |contribution| (used for the floored tolerance)."""
+    d, q, me = _mesh_arrays(q, me)
+    nq = q.shape[1] if nq is None else nq
+    nme = me.shape[1]
+    m = d if op == "ELAS" else 1
+    cap = max(1, nme * ((d + 1) * m) ** 2)
+    rp = np.zeros(m * nq + 1, np.int64)
+    ci = np.zeros(cap, np.int64)
+    v = np.zeros(cap, np.float64)
+    av = np.zeros(cap, np.float64)
+    nnz = C.c_int64(0)
+    wv = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
+    st = _load().oracle_assemble(d, nq, nme, _ptr(q), _ptr(me), OP[op], _ptr(wv), lam, mu, cap,
+                                 C.byref(nnz), _ptr(rp), _ptr(ci), _ptr(v), _ptr(av))
+    if st:
+        raise OracleError(st, "assemble")
+    n = nnz.value
+    return rp, ci[:n].copy(), v[:n].copy(), av[:n].copy()
+
+
+def assemble_rows(q, me, op: str, rows, w=None, lam: float = 1.0, mu: float = 0.5):
+    """CSR restricted to the global rows listed in ``rows`` (in that order)."""
+    d, q, me = _mesh_arrays(q, me)
+    nq = q.shape[1]
+    nme = me.shape[1]
+    m = d if op == "ELAS" else 1
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    cap = max(1, len(rows) * 64 * m * m * 4)
+    while True:
+        rp = np.zeros(len(rows) + 1, np.int64)
+        ci = np.zeros(cap, np.int64)
+        v = np.zeros(cap, np.float64)
+        av = np.zeros(cap, np.float64)
+        nnz = C.c_int64(0)
+        wv = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
+        st = _load().oracle_assemble_rows(d, nq, nme, _ptr(q), _ptr(me), OP[op], _ptr(wv), lam,
+                                          mu, len(rows), _ptr(rows), cap, C.byref(nnz), _ptr(rp),
+                                          _ptr(ci), _ptr(v), _ptr(av))
+        if st == 4:
+            cap *= 4
+            continue
+        if st:
+            raise OracleError(st, "assemble_rows")
+        n = nnz.value
+        return rp, ci[:n].copy(), v[:n].copy(), av[:n].copy()
+
+
+def grad(q, me, w, a, b, want_w: bool = True, want_q: bool = True):
+    """J = a^T (S + M_w) b with dJ/dw (nq,) and dJ/dq (d, nq)."""
+    d, q, me = _mesh_arrays(q, me)
+    nq = q.shape[1]
+    w = np.ascontiguousarray(w, np.float64)
+    a = np.ascontiguousarray(a, np.float64)
+    b = np.ascontiguousarray(b, np.float64)
+    J = C.c_double(0.0)
+    gw = np.zeros(nq) if want_w else None
+    gq = np.zeros((d, nq)) if want_q else None
+    st = _load().oracle_grad(d, nq, me.shape[1], _ptr(q), _ptr(me), _ptr(w), _ptr(a), _ptr(b),
+                             C.byref(J), _ptr(gw), _ptr(gq))
+    if st:
+        raise OracleError(st, "grad")
+    return J.value, gw, gq
+
+
+def element_matrix(P, op: str, wloc=None, lam: float = 1.0, mu: float = 0.5):
+    """Local matrix of one simplex with vertex coordinates P ((d+1) x d)."""
+    P = np.ascontiguousarray(P, np.float64)
+    d = P.shape[1]
+    m = d if op == "ELAS" else 1
+    n = (d + 1) * m
+    E = np.zeros((n, n))
+    wl = None if wloc is None else np.ascontiguousarray(wloc, np.float64)
+    st = _load().oracle_element_matrix(d, OP[op], _ptr(P), _ptr(wl), lam, mu, _ptr(E))
+    if st:
+        raise OracleError(st, "element_matrix")
+    return E
