@@ -1,0 +1,212 @@
+/*
+ * femasm.h - C ABI of the MI355X (gfx950) P1 finite-element assembly library.
+ *
+ * What it computes (Cuvelier, Japhet, Scarella, "An efficient way to
+ * assemble finite element matrices in vector languages"):
+ *
+ *   A = sum over elements K of  P_K^T E(K) P_K            (Section 3)
+ *
+ * for a conforming mesh of d-simplices (d = 2 triangles, d = 3 tetrahedra)
+ * with P1 Lagrange elements.  E(K) is one of
+ *   FEM_OP_MASS    integral of lambda_a lambda_b            (magic formula, Section 2)
+ *   FEM_OP_MASS_W  integral of w_h lambda_a lambda_b, w_h the P1 interpolant of
+ *                  the nodal weight w (closed form of Section 4.1)
+ *   FEM_OP_STIFF   |K| <grad lambda_b, grad lambda_a>      (Section 4.2)
+ *   FEM_OP_ELAS    isotropic linear elasticity with constant Lame parameters
+ *                  lambda, mu (lemma of Section 5.1, Appendix B), vector dofs
+ *                  in the alternate numbering r = d*i + l (Section 5)
+ * and the duplicate (I, J) contributions are summed into CSR (the `sparse`
+ * primitive of Section 3), deterministically: every entry is the sum of its
+ * element contributions in ascending element number, starting from 0.0, so
+ * values are bitwise reproducible from run to run and A is exactly
+ * symmetric.  The pattern is structural (explicit zeros are kept).
+ *
+ * Conventions for every entry point:
+ *  - All array arguments are DEVICE pointers unless marked "host".
+ *  - Indices are 0-based.  Mesh arrays are row-major structure-of-arrays:
+ *      q  [d][nq]     double   q[v*nq + j] = coordinate v of vertex j
+ *      me [d+1][nme]  int32    me[a*nme + k] = local vertex a of element k
+ *      w  [nq]        double   nodal weight (FEM_OP_MASS_W only)
+ *  - CSR uses int32 row_ptr / col_idx (columns ascending, unique per row)
+ *    and double values.  Scalar operators have nq rows; FEM_OP_ELAS has d*nq
+ *    rows, row (i, l) = d*i + l, and its pattern is the scalar pattern with
+ *    every entry expanded to a d x d block.
+ *  - `stream` is a hipStream_t (0 = the null stream).  Numeric, pattern and
+ *    backward calls only enqueue work on it and never synchronise; buffers
+ *    they read must stay valid and unmodified until that work completes.
+ *  - Errors are returned as fem_status; nothing is thrown across the ABI and
+ *    out-parameters are written only on FEM_OK.  The caller owns every
+ *    buffer it passes; the library owns plans and batches.
+ */
+#ifndef FEMASM_H
+#define FEMASM_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum fem_status {
+    FEM_OK = 0,
+    FEM_ERR_ARG = 1,         /* bad argument: null pointer, d not 2 or 3, bad op, negative size */
+    FEM_ERR_INDEX = 2,       /* me holds an index outside [0, nq) or an element repeats a vertex */
+    FEM_ERR_DEGENERATE = 3,  /* an element has det B_k == 0 (reported after the fact, see below) */
+    FEM_ERR_OVERFLOW = 4,    /* a size exceeds the int32 CSR range or a row exceeds 255 entries */
+    FEM_ERR_NOMEM = 5,       /* device or host allocation failed */
+    FEM_ERR_DEVICE = 6       /* a HIP runtime call failed */
+} fem_status;
+
+typedef enum fem_op {
+    FEM_OP_MASS = 0,
+    FEM_OP_MASS_W = 1,
+    FEM_OP_STIFF = 2,
+    FEM_OP_ELAS = 3
+} fem_op;
+
+typedef struct fem_plan_s *fem_plan;
+typedef struct fem_batch_s *fem_batch;
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char *fem_status_str(fem_status s);
+
+/*
+ * Symbolic phase (Section 3: the (I, J) half of the triplets and the
+ * `sparse` pattern).  Validates me, builds the CSR pattern of the scalar
+ * operator (row i holds every vertex that shares an element with i, i
+ * included), the element-to-CSR slot addressing used by the numeric phase,
+ * and a locality-ordered copy of the connectivity.  The plan depends only on
+ * me: one plan serves every q, w, lambda, mu and operator.
+ *   d      2 or 3
+ *   nq     number of vertices (>= 0); vertices no element uses get empty rows
+ *   nme    number of elements (>= 0)
+ *   me     device, (d+1)*nme int32, layout above (may be NULL when nme == 0)
+ *   stream work is ordered on it; the call is synchronous (it returns once
+ *          the plan is complete)
+ *   out    receives the plan (host pointer to a handle)
+ * Errors: FEM_ERR_ARG, FEM_ERR_INDEX (index out of range, repeated vertex),
+ * FEM_ERR_OVERFLOW (nnz >= 2^31, a row with more than 255 entries, or
+ * (d+1)*nme >= 2^31), FEM_ERR_NOMEM, FEM_ERR_DEVICE.
+ */
+fem_status fem_assemble_symbolic(int32_t d, int64_t nq, int64_t nme, const int32_t *me,
+                                 hipStream_t stream, fem_plan *out);
+
+/* Matrix sizes of operator `op` for this plan: nrows (nq, or d*nq for
+ * FEM_OP_ELAS) and nnz (scalar nnz, or d*d times it).  Host out-pointers. */
+fem_status fem_plan_query(fem_plan plan, int32_t op, int64_t *nrows, int64_t *nnz);
+
+/* Plan facts: d, nq, nme and the longest scalar row.  Host out-pointers,
+ * any may be NULL. */
+fem_status fem_plan_info(fem_plan plan, int32_t *d, int64_t *nq, int64_t *nme,
+                         int32_t *max_row);
+
+/* Writes the CSR pattern of operator `op` into caller buffers:
+ * row_ptr[nrows+1], col_idx[nnz] (device).  Enqueued on `stream`. */
+fem_status fem_plan_pattern(fem_plan plan, int32_t op, int32_t *row_ptr, int32_t *col_idx,
+                            hipStream_t stream);
+
+/* Triplet-to-slot map of the scalar operator, in the column-wise local order
+ * of the OptV1 / OptV2 listings of Sections 3-4: for element k and local
+ * entry (row vertex a, column vertex b),
+ *   slot[k*(d+1)^2 + b*(d+1) + a] = CSR position of (me[a,k], me[b,k]).
+ * slot is a device buffer of (d+1)^2 * nme int32.  Enqueued on `stream`. */
+fem_status fem_plan_slot_map(fem_plan plan, int32_t *slot, hipStream_t stream);
+
+/*
+ * Numeric phase: CSR values of operator `op` (Sections 4.1, 4.2, 5.1).
+ *   q       device, d*nq doubles (layout above)
+ *   w       device, nq doubles; read only for FEM_OP_MASS_W (else may be NULL)
+ *   lambda, mu  Lame parameters; read only for FEM_OP_ELAS (need lambda+mu > 0
+ *           for a positive semi-definite result; not checked)
+ *   values  device, nnz doubles (fem_plan_query), fully overwritten
+ * Asynchronous: one kernel on `stream`, no host synchronisation, no
+ * allocation.  An element with det B_k == 0 contributes nothing and sets the
+ * plan's device status word; fem_plan_sync_status reports it.
+ * Errors (immediate): FEM_ERR_ARG, FEM_ERR_OVERFLOW (vector nnz >= 2^31),
+ * FEM_ERR_DEVICE (launch failure).
+ */
+fem_status fem_assemble_numeric(fem_plan plan, int32_t op, const double *q, const double *w,
+                                double lambda, double mu, double *values, hipStream_t stream);
+
+/*
+ * Adjoint of J(q, w) = a^T (S(q) + M_w(q)) b: the sum over elements of
+ * a_K^T (E_stiff(K) + E_mass_w(K)) b_K, differentiated through the element
+ * Jacobians (the gradient systems of Appendix C.1 give
+ * d g_a = -sum_c g_c (g_a . d q_c) and d|K| = |K| sum_c g_c . d q_c).
+ *   op_mask  bit (1 << FEM_OP_STIFF) and/or bit (1 << FEM_OP_MASS_W): which
+ *            terms J contains
+ *   q, w, a, b  device; w is read when MASS_W is in the mask; a, b have nq doubles
+ *   dJdw     device nq doubles or NULL
+ *   dJdq     device d*nq doubles (laid out like q) or NULL
+ * Each output entry is the sum of its element contributions in ascending
+ * element number (bitwise reproducible).  Asynchronous, no allocation.
+ */
+fem_status fem_assemble_backward(fem_plan plan, uint32_t op_mask, const double *q,
+                                 const double *w, const double *a, const double *b,
+                                 double *dJdw, double *dJdq, hipStream_t stream);
+
+/* J = a^T A b for CSR values of operator `op` produced with this plan:
+ * out (device, 1 double).  Row partial sums are combined in row order, so
+ * the result is bitwise reproducible.  Asynchronous. */
+fem_status fem_csr_bilinear(fem_plan plan, int32_t op, const double *values, const double *a,
+                            const double *b, double *out, hipStream_t stream);
+
+/* Synchronises `stream`, then reads and clears the plan's device status
+ * word: FEM_ERR_DEGENERATE if any numeric or backward call since the last
+ * read met an element with det B_k == 0, else FEM_OK. */
+fem_status fem_plan_sync_status(fem_plan plan, hipStream_t stream);
+
+/* Frees the plan (NULL is ignored).  Work using it must have completed. */
+void fem_plan_destroy(fem_plan plan);
+
+/*
+ * Batched assembly of many independent meshes in one persistent launch.
+ *   nmesh          number of meshes (>= 1)
+ *   d, nq, nme     host arrays [nmesh]
+ *   me             host array [nmesh] of device pointers (layout above)
+ * Builds one plan per mesh plus a device work list of (mesh, row tile)
+ * items, largest first.  Synchronous.
+ */
+fem_status fem_batch_create(int32_t nmesh, const int32_t *d, const int64_t *nq,
+                            const int64_t *nme, const int32_t *const *me, hipStream_t stream,
+                            fem_batch *out);
+
+/* Host arrays [nmesh+1] of offsets into the concatenated inputs/outputs of
+ * operator `op`: q_off (doubles of q, mesh b holds d_b*nq_b), w_off (doubles
+ * of w), row_off (CSR rows) and nnz_off (values).  Any may be NULL. */
+fem_status fem_batch_offsets(fem_batch batch, int32_t op, int64_t *q_off, int64_t *w_off,
+                             int64_t *row_off, int64_t *nnz_off);
+
+/* Plan of mesh `index` (borrowed; owned by the batch). */
+fem_status fem_batch_plan(fem_batch batch, int32_t index, fem_plan *plan);
+
+/* Tunables of the persistent kernel: threads per workgroup (64, 128 or 256)
+ * and workgroups per compute unit (1..8).  They change scheduling only, not
+ * the values (each CSR row is still summed by one thread in ascending
+ * element order).  Synchronous (rebuilds the work list). */
+fem_status fem_batch_set_params(fem_batch batch, int32_t block_threads, int32_t wg_per_cu);
+
+/*
+ * CSR values of operator `op` for every mesh of the batch, in one kernel
+ * launch.  q_cat, w_cat are the per-mesh arrays concatenated at q_off /
+ * w_off; values_cat receives mesh b's values at nnz_off[b].  No host
+ * synchronisation, no allocation, fixed kernel arguments: safe to capture
+ * in a hipGraph and replay.
+ */
+fem_status fem_batch_numeric(fem_batch batch, int32_t op, const double *q_cat,
+                             const double *w_cat, double lambda, double mu,
+                             double *values_cat, hipStream_t stream);
+
+/* Synchronises `stream`, then reads and clears the batch's device status
+ * word: FEM_ERR_DEGENERATE if a batched numeric call since the last read met
+ * an element with det B_k == 0, else FEM_OK. */
+fem_status fem_batch_sync_status(fem_batch batch, hipStream_t stream);
+
+/* Frees the batch and its plans (NULL is ignored). */
+void fem_batch_destroy(fem_batch batch);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FEMASM_H */

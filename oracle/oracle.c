@@ -30,6 +30,14 @@
  * Structural zeros are kept: the pattern is every (I, J) pair that appears
  * in a triplet, whatever its value.
  *
+ * Alongside each entry the oracle returns its magnitude scale: the sum over
+ * the contributing elements of the size of the terms each contribution is
+ * made of, |K| max_c |g_c|^2 for stiffness, (|lambda| + 2|mu|) times that for
+ * elasticity, |K| sum_g |w_g| x magic factor for the masses.  Any correct
+ * way of computing the gradients and summing rounds relative to this scale,
+ * also where a contribution or an entry cancels to (near) zero, so the
+ * tolerance of the parity tests is floored by it.
+ *
  * Vector case (elasticity, m = d): alternate numbering of Section 5, global
  * dof r = m*i + l for vertex i and component l (0-based), local index
  * a*m + l for local vertex a.
@@ -239,27 +247,36 @@ static void mat_QS(int d, int n, int l, double Q[MAXD][MAXD], double S[MAXD][MAX
 /* Full local matrix E (nloc x nloc, nloc = (d+1)*m), row index a*m+l (test
  * function psi_{l,a}), column index b*m+n (trial function psi_{n,b}). */
 static int element_matrix(int d, int op, const double P[MAXNL][MAXD], const double *wloc,
-                          double lam, double mu, double E[MAXLOC][MAXLOC]) {
+                          double lam, double mu, double E[MAXLOC][MAXLOC],
+                          double Eabs[MAXLOC][MAXLOC]) {
     double vol, G[MAXD][MAXNL];
     if (!element_geometry(d, P, &vol, G)) return 0;
     const int nl = d + 1;
+    double g2max = 0.0;  /* largest squared gradient norm on the element */
+    for (int a = 0; a < nl; ++a) {
+        double g2 = 0.0;
+        for (int i = 0; i < d; ++i) g2 += G[i][a] * G[i][a];
+        if (g2 > g2max) g2max = g2;
+    }
     if (op == OR_MASS || op == OR_MASS_W) {
         for (int a = 0; a < nl; ++a)
             for (int b = 0; b < nl; ++b) {
-                double s = 0.0;
+                double s = 0.0, sa = 0.0;
                 if (op == OR_MASS) {
                     int ex[MAXNL] = {0, 0, 0, 0};
                     ex[a] += 1; ex[b] += 1;
-                    s = magic_factor(d, ex);
+                    s = sa = magic_factor(d, ex);
                 } else {
                     /* w_h = sum_g w_g lambda_g (P1 interpolant, Section 4.1) */
                     for (int g = 0; g < nl; ++g) {
                         int ex[MAXNL] = {0, 0, 0, 0};
                         ex[a] += 1; ex[b] += 1; ex[g] += 1;
                         s += wloc[g] * magic_factor(d, ex);
+                        sa += fabs(wloc[g]) * magic_factor(d, ex);
                     }
                 }
                 E[a][b] = vol * s;
+                Eabs[a][b] = vol * sa;
             }
         return 1;
     }
@@ -269,6 +286,7 @@ static int element_matrix(int d, int op, const double P[MAXNL][MAXD], const doub
                 double s = 0.0;
                 for (int i = 0; i < d; ++i) s += G[i][b] * G[i][a];
                 E[a][b] = vol * s;
+                Eabs[a][b] = vol * g2max;
             }
         return 1;
     }
@@ -288,6 +306,7 @@ static int element_matrix(int d, int op, const double P[MAXNL][MAXD], const doub
                             xs += G[i][b] * S[i][j] * G[j][a];
                         }
                     E[a * m + l][b * m + n] = vol * (lam * xq + mu * xs);
+                    Eabs[a * m + l][b * m + n] = vol * (fabs(lam) + 2.0 * fabs(mu)) * g2max;
                 }
         }
     return 1;
@@ -313,7 +332,7 @@ int oracle_validate(int d, int64_t nq, int64_t nme, const int32_t *me) {
 
 typedef struct {
     int64_t row, col, seq;
-    double val;
+    double val, aval;
 } triplet_t;
 
 static int cmp_triplet(const void *pa, const void *pb) {
@@ -364,7 +383,7 @@ static int assemble_core(int d, int64_t nq, int64_t nme, const double *q, const 
     int64_t t = 0;
     for (int64_t k = 0; k < nme; ++k) {
         int32_t vid[MAXNL];
-        double P[MAXNL][MAXD], wloc[MAXNL] = {0, 0, 0, 0}, E[MAXLOC][MAXLOC];
+        double P[MAXNL][MAXD], wloc[MAXNL] = {0, 0, 0, 0}, E[MAXLOC][MAXLOC], Ea[MAXLOC][MAXLOC];
         int need = 0;
         for (int a = 0; a < nl && !need; ++a)
             for (int l = 0; l < m; ++l) {
@@ -375,7 +394,7 @@ static int assemble_core(int d, int64_t nq, int64_t nme, const double *q, const 
         gather_element(d, nq, nme, q, me, k, P, vid);
         if (op == OR_MASS_W)
             for (int a = 0; a < nl; ++a) wloc[a] = w[vid[a]];
-        if (!element_matrix(d, op, P, wloc, lam, mu, E)) {
+        if (!element_matrix(d, op, P, wloc, lam, mu, E, Ea)) {
             free(T);
             return OR_ERR_DEGENERATE;
         }
@@ -389,6 +408,7 @@ static int assemble_core(int d, int64_t nq, int64_t nme, const double *q, const 
                         T[t].col = (int64_t)m * vid[b] + n;
                         T[t].seq = t;
                         T[t].val = E[a * m + l][b * m + n];
+                        T[t].aval = Ea[a * m + l][b * m + n];
                         ++t;
                     }
     }
@@ -412,7 +432,7 @@ static int assemble_core(int d, int64_t nq, int64_t nme, const double *q, const 
             row_ptr[T[i].row + 1] += 1;
         }
         val[s] += T[i].val;
-        if (absval) absval[s] += fabs(T[i].val);
+        if (absval) absval[s] += T[i].aval;
     }
     for (int64_t r = 0; r < nout; ++r) row_ptr[r + 1] += row_ptr[r];
     *nnz_out = nnz;
@@ -492,16 +512,20 @@ static int element_J_cplx(int d, double complex P[MAXNL][MAXD], const double *wl
 }
 
 /* J = a^T (S + M_w) b and its gradients.  dJdw has nq entries, dJdq has
- * d*nq entries laid out like q (dJdq[v*nq + j]).  Either may be NULL. */
+ * d*nq entries laid out like q (dJdq[v*nq + j]).  Either may be NULL.  The
+ * *_abs arrays (optional) receive the sum of |element contribution| per
+ * entry, the scale that floors the parity tolerance. */
 int oracle_grad(int d, int64_t nq, int64_t nme, const double *q, const int32_t *me,
                 const double *w, const double *a, const double *b, double *J_out,
-                double *dJdw, double *dJdq) {
+                double *dJdw, double *dJdq, double *dJdw_abs, double *dJdq_abs) {
     int st = oracle_validate(d, nq, nme, me);
     if (st != OR_OK) return st;
     if (!q || !w || !a || !b) return OR_ERR_ARG;
     const double hstep = 1e-30;
     if (dJdw) memset(dJdw, 0, sizeof(double) * (size_t)nq);
     if (dJdq) memset(dJdq, 0, sizeof(double) * (size_t)(d * nq));
+    if (dJdw_abs) memset(dJdw_abs, 0, sizeof(double) * (size_t)nq);
+    if (dJdq_abs) memset(dJdq_abs, 0, sizeof(double) * (size_t)(d * nq));
     double Jsum = 0.0;
     for (int64_t k = 0; k < nme; ++k) {
         int32_t vid[MAXNL];
@@ -522,6 +546,7 @@ int oracle_grad(int d, int64_t nq, int64_t nme, const double *q, const int32_t *
                     double complex Jp;
                     if (!element_J_cplx(d, Pp, wl, al, bl, &Jp)) return OR_ERR_DEGENERATE;
                     dJdq[(int64_t)i * nq + vid[g]] += cimag(Jp) / hstep;
+                    if (dJdq_abs) dJdq_abs[(int64_t)i * nq + vid[g]] += fabs(cimag(Jp) / hstep);
                 }
         }
         if (dJdw) {
@@ -536,6 +561,7 @@ int oracle_grad(int d, int64_t nq, int64_t nme, const double *q, const int32_t *
                         s += al[aa] * bl[bb] * magic_factor(d, ex);
                     }
                 dJdw[vid[g]] += vol * s;
+                if (dJdw_abs) dJdw_abs[vid[g]] += fabs(vol * s);
             }
         }
     }
@@ -548,10 +574,10 @@ int oracle_grad(int d, int64_t nq, int64_t nme, const double *q, const int32_t *
 int oracle_element_matrix(int d, int op, const double *P, const double *wloc, double lam,
                           double mu, double *E_out) {
     if (d < 2 || d > 3 || op < OR_MASS || op > OR_ELAS) return OR_ERR_ARG;
-    double Pl[MAXNL][MAXD], E[MAXLOC][MAXLOC];
+    double Pl[MAXNL][MAXD], E[MAXLOC][MAXLOC], Ea[MAXLOC][MAXLOC];
     for (int a = 0; a <= d; ++a)
         for (int i = 0; i < d; ++i) Pl[a][i] = P[a * d + i];
-    if (!element_matrix(d, op, Pl, wloc, lam, mu, E)) return OR_ERR_DEGENERATE;
+    if (!element_matrix(d, op, Pl, wloc, lam, mu, E, Ea)) return OR_ERR_DEGENERATE;
     const int m = (op == OR_ELAS) ? d : 1, nloc = (d + 1) * m;
     for (int i = 0; i < nloc; ++i)
         for (int j = 0; j < nloc; ++j) E_out[i * nloc + j] = E[i][j];

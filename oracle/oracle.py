@@ -58,7 +58,7 @@ def _load():
                                         C.c_double, i64, P, P, P, P, P]
         lib.oracle_assemble_rows.argtypes = [C.c_int, i64, i64, P, P, C.c_int, P, C.c_double,
                                              C.c_double, i64, P, i64, P, P, P, P, P]
-        lib.oracle_grad.argtypes = [C.c_int, i64, i64, P, P, P, P, P, P, P, P]
+        lib.oracle_grad.argtypes = [C.c_int, i64, i64, P, P, P, P, P, P, P, P, P, P]
         lib.oracle_element_matrix.argtypes = [C.c_int, C.c_int, P, P, C.c_double, C.c_double, P]
         for f in (lib.oracle_validate, lib.oracle_assemble, lib.oracle_assemble_rows,
                   lib.oracle_grad, lib.oracle_element_matrix):
@@ -132,8 +132,9 @@ def assemble_rows(q, me, op: str, rows, w=None, lam: float = 1.0, mu: float = 0.
         return rp, ci[:n].copy(), v[:n].copy(), av[:n].copy()
 
 
-def grad(q, me, w, a, b, want_w: bool = True, want_q: bool = True):
-    """J = a^T (S + M_w) b with dJ/dw (nq,) and dJ/dq (d, nq)."""
+def grad(q, me, w, a, b, want_w: bool = True, want_q: bool = True, with_abs: bool = False):
+    """J = a^T (S + M_w) b with dJ/dw (nq,) and dJ/dq (d, nq); with_abs also
+    returns the per-entry sums of |element contribution|."""
     d, q, me = _mesh_arrays(q, me)
     nq = q.shape[1]
     w = np.ascontiguousarray(w, np.float64)
@@ -142,10 +143,14 @@ def grad(q, me, w, a, b, want_w: bool = True, want_q: bool = True):
     J = C.c_double(0.0)
     gw = np.zeros(nq) if want_w else None
     gq = np.zeros((d, nq)) if want_q else None
+    aw = np.zeros(nq) if (want_w and with_abs) else None
+    aq = np.zeros((d, nq)) if (want_q and with_abs) else None
     st = _load().oracle_grad(d, nq, me.shape[1], _ptr(q), _ptr(me), _ptr(w), _ptr(a), _ptr(b),
-                             C.byref(J), _ptr(gw), _ptr(gq))
+                             C.byref(J), _ptr(gw), _ptr(gq), _ptr(aw), _ptr(aq))
     if st:
         raise OracleError(st, "grad")
+    if with_abs:
+        return J.value, gw, gq, aw, aq
     return J.value, gw, gq
 
 

@@ -1,0 +1,347 @@
+"""Python binding of libfemasm.so (argument marshalling only).
+
+The functions named ``fem_*`` mirror the C ABI in include/femasm.h one to
+one and take raw device pointers (ints) and a stream handle.  The small
+classes below (:class:`Plan`, :class:`Batch`) only allocate torch tensors for
+outputs and pass their pointers through; every step of the assembly runs in
+the HIP library.  There is no CPU fallback: if the shared library is missing
+or no GPU is visible, loading raises :class:`FemasmUnavailable`.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfemasm.so")
+
+FEM_OP = {"MASS": 0, "MASS_W": 1, "STIFF": 2, "ELAS": 3}
+FEM_STATUS = {0: "FEM_OK", 1: "FEM_ERR_ARG", 2: "FEM_ERR_INDEX", 3: "FEM_ERR_DEGENERATE",
+              4: "FEM_ERR_OVERFLOW", 5: "FEM_ERR_NOMEM", 6: "FEM_ERR_DEVICE"}
+
+
+class FemasmUnavailable(RuntimeError):
+    pass
+
+
+class FemError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        self.name = FEM_STATUS.get(code, f"status {code}")
+        super().__init__(f"{where}: {self.name}")
+
+
+_lib = None
+P = C.c_void_p
+I32 = C.c_int32
+I64 = C.c_int64
+U32 = C.c_uint32
+D = C.c_double
+
+_SIGS = {
+    "fem_status_str": ([C.c_int], C.c_char_p),
+    "fem_assemble_symbolic": ([I32, I64, I64, P, P, C.POINTER(P)], C.c_int),
+    "fem_plan_query": ([P, I32, C.POINTER(I64), C.POINTER(I64)], C.c_int),
+    "fem_plan_info": ([P, C.POINTER(I32), C.POINTER(I64), C.POINTER(I64), C.POINTER(I32)], C.c_int),
+    "fem_plan_pattern": ([P, I32, P, P, P], C.c_int),
+    "fem_plan_slot_map": ([P, P, P], C.c_int),
+    "fem_assemble_numeric": ([P, I32, P, P, D, D, P, P], C.c_int),
+    "fem_assemble_backward": ([P, U32, P, P, P, P, P, P, P], C.c_int),
+    "fem_csr_bilinear": ([P, I32, P, P, P, P, P], C.c_int),
+    "fem_plan_sync_status": ([P, P], C.c_int),
+    "fem_plan_destroy": ([P], None),
+    "fem_batch_create": ([I32, P, P, P, P, P, C.POINTER(P)], C.c_int),
+    "fem_batch_offsets": ([P, I32, P, P, P, P], C.c_int),
+    "fem_batch_plan": ([P, I32, C.POINTER(P)], C.c_int),
+    "fem_batch_set_params": ([P, I32, I32], C.c_int),
+    "fem_batch_numeric": ([P, I32, P, P, D, D, P, P], C.c_int),
+    "fem_batch_sync_status": ([P, P], C.c_int),
+    "fem_batch_destroy": ([P], None),
+}
+
+EXPORTED = tuple(_SIGS)
+
+
+def load_library(require_gpu: bool = True):
+    """Load libfemasm.so (raises FemasmUnavailable if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise FemasmUnavailable(f"{LIB_PATH} is not built; run python -m paper_1401_3301_amd.build")
+    if require_gpu and not torch.cuda.is_available():
+        raise FemasmUnavailable("no GPU visible: the HIP library has no CPU path")
+    lib = C.CDLL(LIB_PATH)
+    for name, (args, res) in _SIGS.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(st: int, where: str):
+    if st != 0:
+        raise FemError(st, where)
+
+
+def _stream(stream=None) -> int:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+# ---------------------------------------------------------------- raw ABI
+def fem_status_str(code: int) -> str:
+    return load_library().fem_status_str(code).decode()
+
+
+def fem_assemble_symbolic(d: int, nq: int, nme: int, me_ptr: int, stream=None) -> int:
+    out = P()
+    _check(load_library().fem_assemble_symbolic(d, nq, nme, me_ptr, _stream(stream), C.byref(out)),
+           "fem_assemble_symbolic")
+    return out.value
+
+
+def fem_plan_query(plan: int, op: int):
+    nr, nz = I64(), I64()
+    _check(load_library().fem_plan_query(plan, op, C.byref(nr), C.byref(nz)), "fem_plan_query")
+    return nr.value, nz.value
+
+
+def fem_plan_info(plan: int):
+    d, nq, nme, mr = I32(), I64(), I64(), I32()
+    _check(load_library().fem_plan_info(plan, C.byref(d), C.byref(nq), C.byref(nme), C.byref(mr)),
+           "fem_plan_info")
+    return d.value, nq.value, nme.value, mr.value
+
+
+def fem_plan_pattern(plan: int, op: int, row_ptr: int, col_idx: int, stream=None):
+    _check(load_library().fem_plan_pattern(plan, op, row_ptr, col_idx, _stream(stream)),
+           "fem_plan_pattern")
+
+
+def fem_plan_slot_map(plan: int, slot: int, stream=None):
+    _check(load_library().fem_plan_slot_map(plan, slot, _stream(stream)), "fem_plan_slot_map")
+
+
+def fem_assemble_numeric(plan: int, op: int, q: int, w: int | None, lam: float, mu: float,
+                         values: int, stream=None):
+    _check(load_library().fem_assemble_numeric(plan, op, q, w, lam, mu, values, _stream(stream)),
+           "fem_assemble_numeric")
+
+
+def fem_assemble_backward(plan: int, op_mask: int, q: int, w: int | None, a: int, b: int,
+                          dJdw: int | None, dJdq: int | None, stream=None):
+    _check(load_library().fem_assemble_backward(plan, op_mask, q, w, a, b, dJdw, dJdq,
+                                                _stream(stream)), "fem_assemble_backward")
+
+
+def fem_csr_bilinear(plan: int, op: int, values: int, a: int, b: int, out: int, stream=None):
+    _check(load_library().fem_csr_bilinear(plan, op, values, a, b, out, _stream(stream)),
+           "fem_csr_bilinear")
+
+
+def fem_plan_sync_status(plan: int, stream=None) -> int:
+    return load_library().fem_plan_sync_status(plan, _stream(stream))
+
+
+def fem_plan_destroy(plan: int):
+    if plan:
+        load_library().fem_plan_destroy(plan)
+
+
+def fem_batch_create(d, nq, nme, me_ptrs, stream=None) -> int:
+    n = len(d)
+    arr_d = (I32 * n)(*d)
+    arr_nq = (I64 * n)(*nq)
+    arr_nme = (I64 * n)(*nme)
+    arr_me = (P * n)(*me_ptrs)
+    out = P()
+    _check(load_library().fem_batch_create(n, arr_d, arr_nq, arr_nme, arr_me, _stream(stream),
+                                           C.byref(out)), "fem_batch_create")
+    return out.value
+
+
+def fem_batch_offsets(batch: int, op: int, nmesh: int):
+    arrs = [(I64 * (nmesh + 1))() for _ in range(4)]
+    _check(load_library().fem_batch_offsets(batch, op, *arrs), "fem_batch_offsets")
+    return [list(a) for a in arrs]
+
+
+def fem_batch_plan(batch: int, index: int) -> int:
+    out = P()
+    _check(load_library().fem_batch_plan(batch, index, C.byref(out)), "fem_batch_plan")
+    return out.value
+
+
+def fem_batch_set_params(batch: int, block_threads: int, wg_per_cu: int):
+    _check(load_library().fem_batch_set_params(batch, block_threads, wg_per_cu),
+           "fem_batch_set_params")
+
+
+def fem_batch_numeric(batch: int, op: int, q_cat: int, w_cat: int | None, lam: float, mu: float,
+                      values_cat: int, stream=None):
+    _check(load_library().fem_batch_numeric(batch, op, q_cat, w_cat, lam, mu, values_cat,
+                                            _stream(stream)), "fem_batch_numeric")
+
+
+def fem_batch_sync_status(batch: int, stream=None) -> int:
+    return load_library().fem_batch_sync_status(batch, _stream(stream))
+
+
+def fem_batch_destroy(batch: int):
+    if batch:
+        load_library().fem_batch_destroy(batch)
+
+
+# ------------------------------------------------------------ torch helpers
+def _op(op) -> int:
+    return FEM_OP[op] if isinstance(op, str) else int(op)
+
+
+def _dev_f64(x, device):
+    if x is None:
+        return None
+    t = torch.as_tensor(x, dtype=torch.float64, device=device)
+    return t.contiguous()
+
+
+class Plan:
+    """A symbolic plan for one mesh (connectivity ``me`` of shape (d+1, nme))."""
+
+    def __init__(self, me: torch.Tensor, nq: int, stream=None):
+        load_library()
+        if me.dtype != torch.int32 or not me.is_cuda or me.dim() != 2:
+            raise ValueError("me must be a CUDA int32 tensor of shape (d+1, nme)")
+        self.me = me.contiguous()
+        self.d = self.me.shape[0] - 1
+        self.nq = int(nq)
+        self.nme = int(self.me.shape[1])
+        self.device = self.me.device
+        self.handle = fem_assemble_symbolic(self.d, self.nq, self.nme,
+                                            self.me.data_ptr() if self.nme else 0, stream)
+        self.max_row = fem_plan_info(self.handle)[3]
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            fem_plan_destroy(h)
+            self.handle = None
+
+    def query(self, op):
+        return fem_plan_query(self.handle, _op(op))
+
+    def pattern(self, op="STIFF", stream=None):
+        nrows, nnz = self.query(op)
+        rp = torch.empty(nrows + 1, dtype=torch.int32, device=self.device)
+        ci = torch.empty(max(nnz, 1), dtype=torch.int32, device=self.device)
+        fem_plan_pattern(self.handle, _op(op), rp.data_ptr(), ci.data_ptr(), stream)
+        return rp, ci[:nnz]
+
+    def slot_map(self, stream=None):
+        n = (self.d + 1) ** 2 * self.nme
+        s = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+        fem_plan_slot_map(self.handle, s.data_ptr(), stream)
+        return s[:n]
+
+    def numeric(self, op, q, w=None, lam=1.0, mu=0.5, out=None, stream=None):
+        nrows, nnz = self.query(op)
+        q = _dev_f64(q, self.device)
+        w = _dev_f64(w, self.device)
+        if out is None:
+            out = torch.empty(max(nnz, 1), dtype=torch.float64, device=self.device)
+        fem_assemble_numeric(self.handle, _op(op), q.data_ptr(), _ptr(w), float(lam), float(mu),
+                             out.data_ptr(), stream)
+        return out[:nnz]
+
+    def backward(self, q, w, a, b, op_mask=("STIFF", "MASS_W"), want_w=True, want_q=True,
+                 stream=None):
+        mask = 0
+        for o in op_mask:
+            mask |= 1 << _op(o)
+        q, w, a, b = (_dev_f64(x, self.device) for x in (q, w, a, b))
+        gw = torch.empty(self.nq, dtype=torch.float64, device=self.device) if want_w else None
+        gq = torch.empty(self.d, self.nq, dtype=torch.float64, device=self.device) if want_q else None
+        fem_assemble_backward(self.handle, mask, q.data_ptr(), _ptr(w), a.data_ptr(), b.data_ptr(),
+                              _ptr(gw), _ptr(gq), stream)
+        return gw, gq
+
+    def bilinear(self, op, values, a, b, stream=None):
+        out = torch.empty(1, dtype=torch.float64, device=self.device)
+        a = _dev_f64(a, self.device)
+        b = _dev_f64(b, self.device)
+        fem_csr_bilinear(self.handle, _op(op), values.data_ptr(), a.data_ptr(), b.data_ptr(),
+                         out.data_ptr(), stream)
+        return out
+
+    def sync_status(self, stream=None):
+        st = fem_plan_sync_status(self.handle, stream)
+        _check(st, "fem_plan_sync_status")
+
+
+@dataclass
+class BatchOffsets:
+    q: list
+    w: list
+    rows: list
+    nnz: list
+
+
+class Batch:
+    """Many meshes assembled by one persistent launch."""
+
+    def __init__(self, mes, nqs, stream=None):
+        load_library()
+        self.mes = [m.contiguous() for m in mes]
+        self.d = [int(m.shape[0]) - 1 for m in self.mes]
+        self.nq = [int(n) for n in nqs]
+        self.nme = [int(m.shape[1]) for m in self.mes]
+        self.device = self.mes[0].device
+        self.handle = fem_batch_create(self.d, self.nq, self.nme,
+                                       [m.data_ptr() for m in self.mes], stream)
+        self.params = (256, 2)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            fem_batch_destroy(h)
+            self.handle = None
+
+    def __len__(self):
+        return len(self.mes)
+
+    def offsets(self, op) -> BatchOffsets:
+        q, w, r, z = fem_batch_offsets(self.handle, _op(op), len(self.mes))
+        return BatchOffsets(q, w, r, z)
+
+    def plan_handle(self, index: int) -> int:
+        return fem_batch_plan(self.handle, index)
+
+    def set_params(self, block_threads: int, wg_per_cu: int):
+        fem_batch_set_params(self.handle, block_threads, wg_per_cu)
+        self.params = (block_threads, wg_per_cu)
+
+    def numeric(self, op, q_cat, w_cat=None, lam=1.0, mu=0.5, out=None, stream=None):
+        nnz = self.offsets(op).nnz[-1]
+        if out is None:
+            out = torch.empty(max(nnz, 1), dtype=torch.float64, device=self.device)
+        fem_batch_numeric(self.handle, _op(op), q_cat.data_ptr(), _ptr(w_cat), float(lam),
+                          float(mu), out.data_ptr(), stream)
+        return out[:nnz]
+
+    def sync_status(self, stream=None):
+        _check(fem_batch_sync_status(self.handle, stream), "fem_batch_sync_status")
