@@ -1,0 +1,215 @@
+// Host construction of the vertex-block layout used by the block kernels.
+//
+// Vertices (CSR rows) are grouped into compact blocks by breadth-first
+// growth over the mesh graph, seeded at the lowest unassigned vertex.  For
+// each block the plan stores
+//   - its rows (ascending vertex id) and its touched vertices: the rows first,
+//     then every other vertex of an element around a row (ascending id);
+//     "local vertex" = position in that list (16 bits);
+//   - its elements: every element with a vertex among the rows, in ascending
+//     caller element number, as d+1 local vertex ids (four 16-bit slots);
+//   - per row, its incidences in ascending element position, as 32-bit
+//     records: element position (bits 0-9), the row's local vertex index a
+//     within that element (bits 10-11) and, for each local vertex b of the
+//     element, the position of that vertex in the row's CSR columns (5 bits
+//     each from bit 12).  Records are interleaved across the rows of the
+//     block (record t of row r at t*nrows + r) and padded with ~0u.
+// Blocks grow until they hold R rows or the next vertex would bring the
+// element count above kMaxBlockElems.  A mesh with a row longer than 32
+// entries, or a vertex whose own star exceeds the element cap, does not fit
+// these formats (ok == false).
+#pragma once
+
+#include <algorithm>
+#include <cstdint>
+#include <thread>
+#include <vector>
+
+namespace femasm {
+
+struct BlockHost {
+    int nb = 0;
+    std::vector<int32_t> rows, row_ptr;
+    std::vector<int32_t> nodes, node_ptr;
+    std::vector<uint16_t> elem;   // 4 per block element
+    std::vector<int32_t> elem_ptr;
+    std::vector<uint32_t> rec;
+    std::vector<int64_t> rec_ptr;
+    std::vector<int32_t> maxdeg;
+    int max_rows = 0, max_nodes = 0, max_elems = 0;
+    int64_t max_nacc = 0;
+    int64_t total_elems = 0;
+    bool ok = false;
+};
+
+constexpr uint32_t kRecPad = 0xffffffffu;
+constexpr int kMaxBlockElems = 1023;
+constexpr int kMaxRowLen = 32;
+
+inline BlockHost build_block_host(int d, int64_t nq, int64_t nme, const int32_t *me,
+                                  const int32_t *rp, const int32_t *ci, const int64_t *ip,
+                                  const int32_t *inc_k, int R, int nthreads) {
+    BlockHost H;
+    const int NL = d + 1;
+    for (int64_t i = 0; i < nq; ++i)
+        if (rp[i + 1] - rp[i] > kMaxRowLen) return H;
+
+    // ---- breadth-first blocks over used vertices, capped in rows and elements
+    std::vector<int32_t> blk_of(nq, -1);
+    std::vector<int32_t> queue;
+    std::vector<int32_t> estamp(nme, -1);   // block that last counted the element
+    queue.reserve(R);
+    H.row_ptr.push_back(0);
+    auto new_elems = [&](int32_t v, int b) {
+        int n = 0;
+        for (int64_t t = ip[v]; t < ip[v + 1]; ++t) n += estamp[inc_k[t]] != b;
+        return n;
+    };
+    auto take = [&](int32_t v, int b) {
+        blk_of[v] = b;
+        for (int64_t t = ip[v]; t < ip[v + 1]; ++t) estamp[inc_k[t]] = b;
+    };
+    for (int64_t seed = 0; seed < nq; ++seed) {
+        if (blk_of[seed] != -1 || rp[seed + 1] == rp[seed]) continue;
+        const int b = H.nb;
+        if (ip[seed + 1] - ip[seed] > kMaxBlockElems) return H;
+        queue.clear();
+        queue.push_back(int32_t(seed));
+        int nel = new_elems(int32_t(seed), b);
+        take(int32_t(seed), b);
+        size_t head = 0;
+        bool full = false;
+        while (head < queue.size() && int(queue.size()) < R && !full) {
+            const int32_t v = queue[head++];
+            for (int32_t s = rp[v]; s < rp[v + 1] && int(queue.size()) < R; ++s) {
+                const int32_t j = ci[s];
+                if (blk_of[j] != -1 || rp[j + 1] == rp[j]) continue;
+                const int add = new_elems(j, b);
+                if (nel + add > kMaxBlockElems) {
+                    full = true;
+                    break;
+                }
+                nel += add;
+                take(j, b);
+                queue.push_back(j);
+            }
+        }
+        std::sort(queue.begin(), queue.end());
+        H.rows.insert(H.rows.end(), queue.begin(), queue.end());
+        H.row_ptr.push_back(int32_t(H.rows.size()));
+        H.nb += 1;
+    }
+    const int nb = H.nb;
+
+    // ---- per-block lists, built in parallel into per-block vectors
+    struct Blk {
+        std::vector<int32_t> nodes;
+        std::vector<uint16_t> elem;
+        std::vector<uint32_t> rec;
+        int32_t maxdeg = 0;
+        int64_t nacc = 0;
+        bool ok = true;
+    };
+    std::vector<Blk> blks(nb);
+    auto work = [&](int b0, int b1) {
+        std::vector<int32_t> loc(nq, -1);
+        std::vector<int32_t> elems, halo;
+        for (int b = b0; b < b1; ++b) {
+            Blk &B = blks[b];
+            const int32_t *rw = H.rows.data() + H.row_ptr[b];
+            const int nr = H.row_ptr[b + 1] - H.row_ptr[b];
+            elems.clear();
+            for (int r = 0; r < nr; ++r)
+                for (int64_t t = ip[rw[r]]; t < ip[rw[r] + 1]; ++t) elems.push_back(inc_k[t]);
+            std::sort(elems.begin(), elems.end());
+            elems.erase(std::unique(elems.begin(), elems.end()), elems.end());
+            if (int(elems.size()) > kMaxBlockElems) {
+                B.ok = false;
+                continue;
+            }
+            for (int r = 0; r < nr; ++r) loc[rw[r]] = r;
+            halo.clear();
+            for (int32_t k : elems)
+                for (int a = 0; a < NL; ++a) {
+                    const int32_t v = me[int64_t(a) * nme + k];
+                    if (loc[v] == -1) {
+                        loc[v] = -2;
+                        halo.push_back(v);
+                    }
+                }
+            std::sort(halo.begin(), halo.end());
+            B.nodes.assign(rw, rw + nr);
+            for (size_t h = 0; h < halo.size(); ++h) {
+                loc[halo[h]] = int32_t(nr + h);
+                B.nodes.push_back(halo[h]);
+            }
+            if (B.nodes.size() > 65535) {
+                B.ok = false;
+            } else {
+                B.elem.resize(elems.size() * 4, 0);
+                for (size_t e = 0; e < elems.size(); ++e)
+                    for (int a = 0; a < NL; ++a)
+                        B.elem[e * 4 + a] = uint16_t(loc[me[int64_t(a) * nme + elems[e]]]);
+                int maxdeg = 0;
+                for (int r = 0; r < nr; ++r)
+                    maxdeg = std::max<int>(maxdeg, int(ip[rw[r] + 1] - ip[rw[r]]));
+                B.maxdeg = maxdeg;
+                B.rec.assign(size_t(maxdeg) * nr, kRecPad);
+                for (int r = 0; r < nr; ++r) {
+                    const int32_t row = rw[r];
+                    const int32_t *c0 = ci + rp[row], *c1 = ci + rp[row + 1];
+                    B.nacc += c1 - c0;
+                    int t = 0;
+                    for (int64_t s = ip[row]; s < ip[row + 1]; ++s, ++t) {
+                        const int32_t k = inc_k[s];
+                        const uint32_t epos =
+                            uint32_t(std::lower_bound(elems.begin(), elems.end(), k) - elems.begin());
+                        uint32_t recv = epos;
+                        for (int a = 0; a < NL; ++a) {
+                            const int32_t v = me[int64_t(a) * nme + k];
+                            const uint32_t pos = uint32_t(std::lower_bound(c0, c1, v) - c0);
+                            recv |= pos << (12 + 5 * a);
+                            if (v == row) recv |= uint32_t(a) << 10;
+                        }
+                        B.rec[size_t(t) * nr + r] = recv;
+                    }
+                }
+            }
+            for (int32_t v : B.nodes) loc[v] = -1;
+        }
+    };
+    {
+        const int nt = std::max(1, std::min(nthreads, nb / 64 + 1));
+        std::vector<std::thread> th;
+        const int chunk = (nb + nt - 1) / nt;
+        for (int t = 0; t < nt; ++t) {
+            const int b0 = t * chunk, b1 = std::min(nb, b0 + chunk);
+            if (b0 >= b1) break;
+            th.emplace_back(work, b0, b1);
+        }
+        for (auto &x : th) x.join();
+    }
+    H.node_ptr.push_back(0);
+    H.elem_ptr.push_back(0);
+    H.rec_ptr.push_back(0);
+    for (int b = 0; b < nb; ++b) {
+        const Blk &B = blks[b];
+        if (!B.ok) return BlockHost();
+        H.nodes.insert(H.nodes.end(), B.nodes.begin(), B.nodes.end());
+        H.elem.insert(H.elem.end(), B.elem.begin(), B.elem.end());
+        H.rec.insert(H.rec.end(), B.rec.begin(), B.rec.end());
+        H.node_ptr.push_back(int32_t(H.nodes.size()));
+        H.elem_ptr.push_back(int32_t(H.elem.size() / 4));
+        H.rec_ptr.push_back(int64_t(H.rec.size()));
+        H.maxdeg.push_back(B.maxdeg);
+        H.max_rows = std::max(H.max_rows, H.row_ptr[b + 1] - H.row_ptr[b]);
+        H.max_nodes = std::max(H.max_nodes, int(B.nodes.size()));
+        H.max_elems = std::max(H.max_elems, int(B.elem.size() / 4));
+        H.max_nacc = std::max(H.max_nacc, B.nacc);
+    }
+    H.total_elems = H.elem_ptr.back();
+    H.ok = true;
+    return H;
+}
+
+}  // namespace femasm

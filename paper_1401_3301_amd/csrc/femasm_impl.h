@@ -22,6 +22,27 @@ struct RowLaunch {
     int64_t tiles = 0;
 };
 
+// Vertex-block layout of the block kernels (see blocks_host.h).
+struct BlockPlan {
+    bool ok = false;
+    int nb = 0;
+    int max_rows = 0, max_nodes = 0, max_elems = 0;
+    int64_t max_nacc = 0;
+    int64_t max_rec = 0;          // largest record array of a block
+    int wg = 128;                 // threads per workgroup of the block kernel
+    int32_t *rows = nullptr;      // [rows] owned rows, grouped by block
+    int32_t *row_ptr = nullptr;   // [nb+1]
+    int32_t *acc_off = nullptr;   // [rows] local accumulator offset of each owned row
+    int32_t *nacc = nullptr;      // [nb] accumulator length of each block
+    int32_t *nodes = nullptr;     // touched vertices, grouped by block
+    int32_t *node_ptr = nullptr;  // [nb+1]
+    uint16_t *elem = nullptr;     // 4 local vertex ids per block element
+    int32_t *elem_ptr = nullptr;  // [nb+1]
+    uint32_t *rec = nullptr;      // interleaved incidence records
+    int64_t *rec_ptr = nullptr;   // [nb+1]
+    int32_t *maxdeg = nullptr;    // [nb]
+};
+
 struct fem_plan_data {
     int d = 0;
     int64_t nq = 0, nme = 0, nnz = 0;
@@ -39,6 +60,7 @@ struct fem_plan_data {
     double *part = nullptr;       // [d*nq/256 + 1] row-block partial sums of fem_csr_bilinear
     std::vector<int32_t> h_rp;    // host copy of rp (launch geometry)
     RowLaunch launch[4];          // indexed by M
+    BlockPlan blk;                // block-kernel layout (scalar operators)
 };
 
 }  // namespace femasm
@@ -48,6 +70,14 @@ struct fem_plan_s : femasm::fem_plan_data {};
 namespace femasm {
 
 fem_status hip_status(hipError_t e);
+fem_status upload_blocks(fem_plan_data *p, int d, int64_t nq, int64_t nme, const int32_t *me,
+                         const int32_t *rp, const int32_t *ci, const int64_t *ip,
+                         const int32_t *inc_k);
+void free_blocks(BlockPlan *b);
+// Launches the block kernel for a scalar operator; returns false (nothing
+// launched) when the plan has no block layout.
+bool launch_block(const fem_plan_data *p, int op, const double *q, const double *w,
+                  double *values, hipStream_t s, hipError_t *err);
 RowLaunch row_launch_for(const std::vector<int32_t> &h_rp, int64_t nq, int M, size_t lds_cap);
 
 // Device-side view of one mesh for the shared tile routine.

@@ -118,7 +118,7 @@ __device__ __forceinline__ void assemble_row_tile(const MeshView &mv, int64_t r0
                     for (int b = 0; b < NL; ++b) {
                         const int pos = (off >> (8 * b)) & 255u;
                         const double f = (b == al) ? 2.0 * k : k;
-                        my[pos] = fma(f, ws + (wa + wl[b]), my[pos]);
+                        my[pos] += f * (ws + (wa + wl[b]));
                     }
                 }
             } else {
@@ -138,7 +138,7 @@ __device__ __forceinline__ void assemble_row_tile(const MeshView &mv, int64_t r0
 #pragma unroll
                     for (int b = 0; b < NL; ++b) {
                         const int pos = (off >> (8 * b)) & 255u;
-                        my[pos] = fma(cdot<D>(ca, E.c[b]), inv, my[pos]);
+                        my[pos] += cdot<D>(ca, E.c[b]) * inv;
                     }
                 } else {
                     // elasticity: row (al, l), columns (b, n)

@@ -75,6 +75,7 @@ void free_plan_arrays(fem_plan_data *p) {
     p->inc_elem = p->inc_off = nullptr;
     p->status = nullptr;
     p->part = nullptr;
+    free_blocks(&p->blk);
 }
 
 }  // namespace
@@ -275,6 +276,13 @@ extern "C" fem_status fem_assemble_symbolic(int32_t d, int64_t nq, int64_t nme, 
     if (st == FEM_OK) st = upload(&p->inc_off, ioff);
     if (st == FEM_OK) st = upload(&p->status, std::vector<int32_t>(1, 0));
     if (st == FEM_OK) st = upload(&p->part, std::vector<double>(size_t((int64_t(d) * nq + 255) / 256 + 1), 0.0));
+    if (st != FEM_OK) {
+        free_plan_arrays(p.get());
+        return st;
+    }
+    if (st == FEM_OK && nme > 0)
+        st = upload_blocks(p.get(), d, nq, nme, hme.data(), rp.data(), ci.data(), ip.data(),
+                           inc_k.data());
     if (st != FEM_OK) {
         free_plan_arrays(p.get());
         return st;
