@@ -27,8 +27,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-KERNEL_SOURCES = ["paper_1401_3301_amd/csrc/rowgather.h", "paper_1401_3301_amd/csrc/element.h",
-                  "paper_1401_3301_amd/csrc/numeric.hip"]
+KERNEL_SOURCES = ["paper_1401_3301_amd/csrc/block.hip", "paper_1401_3301_amd/csrc/blocks_host.h",
+                  "paper_1401_3301_amd/csrc/element.h", "paper_1401_3301_amd/csrc/rowgather.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_cube128_stiff.json")
 
 
@@ -109,6 +109,8 @@ def extras(torch, femasm, mg, plan, q, stream, steps):
         femasm.fem_batch_numeric(batch.handle, 2, q_cat.data_ptr(), None, 1.0, 0.5,
                                  v_cat.data_ptr(), stream.cuda_stream)
 
+    from paper_1401_3301_amd import autotune
+    tuned, tune_times = autotune.tune(batch, "STIFF", q_cat, w_cat, reps=3)
     handles = [batch.plan_handle(i) for i in range(len(meshes))]
 
     def per_mesh():
@@ -125,7 +127,7 @@ def extras(torch, femasm, mg, plan, q, stream, steps):
     out["batched"] = {"meshes": len(meshes), "elements": nel, "ops": "MASS_W+STIFF",
                       "batched_ms": tb * 1e3, "per_mesh_ms": tp * 1e3, "speedup": tp / tb,
                       "batched_elements_per_s": 2 * nel / tb, "create_s": t_create,
-                      "params": list(batch.params)}
+                      "params": list(batch.params), "tuning_ms": tune_times}
     # adjoint on the 55^3 cube
     ca = mg.config_adjoint()
     m5 = ca["mesh"]
@@ -151,6 +153,8 @@ def main():
     ap.add_argument("--n", type=int, default=128, help="cubes per side")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of known size (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the assembly is measured on one MI355X; "
@@ -159,6 +163,17 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        # a plain copy of 2^29 bytes, read once and written once, three times
+        n = (1 << 29) // 8
+        src = torch.arange(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": n * 8, "copies": 3}))
+        return
 
     from paper_1401_3301_amd import femasm
     from paper_1401_3301_amd import meshgen as mg
@@ -206,7 +221,7 @@ def main():
         "achieved_GBps": achieved,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
-                     "kernel": "k_numeric<3,STIFF>", "kernel_ms": kern_ms,
+                     "kernel": "k_block<3,STIFF>", "kernel_ms": kern_ms,
                      "algorithmic_bytes": ab},
         "symbolic_s": t_sym,
     }

@@ -1,0 +1,87 @@
+"""Autotuner for the persistent batched kernel.
+
+Times ``fem_batch_numeric`` for each candidate (threads per workgroup,
+workgroups per compute unit) with HIP events on the current stream and keeps
+the fastest.  The parameters change only how rows are scheduled, never the
+values (every CSR row is summed by one thread in ascending element number),
+so any choice gives bitwise-identical output.  Results are cached in a JSON
+file keyed by GPU architecture, operator and a size signature of the batch.
+"""
+from __future__ import annotations
+
+import json
+import os
+import statistics
+
+import torch
+
+from . import femasm
+
+CANDIDATES = [(bt, w) for bt in (64, 128, 256) for w in (1, 2, 4, 8)]
+
+
+def default_cache_path() -> str:
+    return os.environ.get("FEMASM_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "femasm_autotune.json"))
+
+
+def batch_key(batch: femasm.Batch, op: str) -> str:
+    arch = torch.cuda.get_device_properties(batch.device).gcnArchName.split(":")[0]
+    nel = sum(batch.nme)
+    bucket = 1 << max(0, int(nel).bit_length() - 1)
+    d2 = sum(1 for d in batch.d if d == 2)
+    return f"{arch}|{op}|n{len(batch)}|d2:{d2}|el~{bucket}"
+
+
+def _time(batch, op, q_cat, w_cat, out, reps):
+    stream = torch.cuda.current_stream()
+    for _ in range(2):
+        batch.numeric(op, q_cat, w_cat, out=out)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        batch.numeric(op, q_cat, w_cat, out=out)
+        b.record(stream)
+        torch.cuda.synchronize()
+        times.append(a.elapsed_time(b))
+    return statistics.median(times)
+
+
+def tune(batch: femasm.Batch, op: str, q_cat, w_cat=None, reps: int = 5,
+         cache_path: str | None = None, force: bool = False):
+    """Pick and apply the fastest (block_threads, wg_per_cu) for this batch
+    and operator.  Returns (params, {params: ms})."""
+    cache_path = cache_path or default_cache_path()
+    key = batch_key(batch, op)
+    cache = {}
+    if os.path.exists(cache_path):
+        try:
+            cache = json.load(open(cache_path))
+        except (OSError, ValueError):
+            cache = {}
+    if not force and key in cache:
+        params = tuple(cache[key]["params"])
+        batch.set_params(*params)
+        return params, cache[key].get("times", {})
+    nnz = batch.offsets(op).nnz[-1]
+    out = torch.empty(max(nnz, 1), dtype=torch.float64, device=batch.device)
+    times = {}
+    for bt, w in CANDIDATES:
+        try:
+            batch.set_params(bt, w)
+        except femasm.FemError:
+            continue
+        times[f"{bt}x{w}"] = _time(batch, op, q_cat, w_cat, out, reps)
+    best = min(times, key=times.get)
+    params = tuple(int(x) for x in best.split("x"))
+    batch.set_params(*params)
+    cache[key] = {"params": list(params), "times": times}
+    os.makedirs(os.path.dirname(cache_path) or ".", exist_ok=True)
+    tmp = cache_path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1)
+    os.replace(tmp, cache_path)
+    return params, times

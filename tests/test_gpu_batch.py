@@ -109,3 +109,19 @@ def test_graph_capture_replay(batch):
         torch.cuda.synchronize()
         assert torch.equal(out_s, ref_s), f"replay {rep} STIFF"
         assert torch.equal(out_m, ref_m), f"replay {rep} MASS_W"
+
+
+def test_autotuner(batch, tmp_path):
+    from paper_1401_3301_amd import autotune
+    B, meshes, ws, q_cat, w_cat = batch
+    ref = _per_mesh(B, "STIFF", q_cat, w_cat)
+    cache = str(tmp_path / "tune.json")
+    params, times = autotune.tune(B, "STIFF", q_cat, w_cat, reps=2, cache_path=cache)
+    assert params in autotune.CANDIDATES and len(times) >= 6
+    assert B.params == params
+    out = B.numeric("STIFF", q_cat, w_cat)
+    assert torch.equal(out, ref)
+    B.set_params(64, 1)
+    again, _ = autotune.tune(B, "STIFF", q_cat, w_cat, cache_path=cache)   # from the cache
+    assert again == params and B.params == params
+    B.set_params(256, 2)
