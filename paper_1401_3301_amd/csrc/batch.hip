@@ -126,18 +126,23 @@ static fem_status build_items(fem_batch_s *B) {
                 if (l) s += l * M * int64_t(p->h_rp[i + 1] - p->h_rp[i]);
                 return s;
             };
+            // elasticity tiles hold whole vertices: R a multiple of M
             int R = B->block_threads;
             for (;; R /= 2) {
-                int64_t span_max = 0;
-                for (int64_t r0 = 0; r0 < nrows; r0 += R)
-                    span_max = std::max(span_max, vstart(std::min(nrows, r0 + R)) - vstart(r0));
-                if (size_t(span_max) * sizeof(double) <= kLdsCap) break;
+                const int Rm = R / M * M;
+                size_t need = 0;
+                for (int64_t r0 = 0; r0 < nrows; r0 += Rm) {
+                    const int64_t r1 = std::min(nrows, r0 + Rm);
+                    need = std::max(need, tile_lds_bytes(M, vstart(r1) - vstart(r0), r1 - r0));
+                }
+                if (need <= kLdsCap) break;
                 if (R <= 16) return FEM_ERR_OVERFLOW;
             }
+            R = R / M * M;
             for (int64_t r0 = 0; r0 < nrows; r0 += R) {
                 const int64_t r1 = std::min(nrows, r0 + R);
                 const int64_t span = vstart(r1) - vstart(r0);
-                worst = std::max(worst, size_t(span) * sizeof(double));
+                worst = std::max(worst, tile_lds_bytes(M, span, r1 - r0));
                 items.push_back(BatchItem{int32_t(m), int32_t(r1 - r0), r0});
                 work.push_back(span * (p->d + 1));
             }

@@ -15,7 +15,8 @@
 //     each from bit 12).  Records are interleaved across the rows of the
 //     block (record t of row r at t*nrows + r) and padded with ~0u.
 // Blocks grow until they hold R rows or the next vertex would bring the
-// element count above kMaxBlockElems.  A mesh with a row longer than 32
+// element count above kMaxBlockElems (or, when max_pairs > 0, the number of
+// CSR entries of the block's rows above max_pairs).  A mesh with a row longer than 32
 // entries, or a vertex whose own star exceeds the element cap, does not fit
 // these formats (ok == false).
 #pragma once
@@ -48,7 +49,8 @@ constexpr int kMaxRowLen = 32;
 
 inline BlockHost build_block_host(int d, int64_t nq, int64_t nme, const int32_t *me,
                                   const int32_t *rp, const int32_t *ci, const int64_t *ip,
-                                  const int32_t *inc_k, int R, int nthreads) {
+                                  const int32_t *inc_k, int R, int nthreads,
+                                  int64_t max_pairs = 0) {
     BlockHost H;
     const int NL = d + 1;
     for (int64_t i = 0; i < nq; ++i)
@@ -76,6 +78,7 @@ inline BlockHost build_block_host(int d, int64_t nq, int64_t nme, const int32_t 
         queue.clear();
         queue.push_back(int32_t(seed));
         int nel = new_elems(int32_t(seed), b);
+        int64_t npairs = rp[seed + 1] - rp[seed];
         take(int32_t(seed), b);
         size_t head = 0;
         bool full = false;
@@ -85,11 +88,13 @@ inline BlockHost build_block_host(int d, int64_t nq, int64_t nme, const int32_t 
                 const int32_t j = ci[s];
                 if (blk_of[j] != -1 || rp[j + 1] == rp[j]) continue;
                 const int add = new_elems(j, b);
-                if (nel + add > kMaxBlockElems) {
+                const int64_t addp = rp[j + 1] - rp[j];
+                if (nel + add > kMaxBlockElems || (max_pairs > 0 && npairs + addp > max_pairs)) {
                     full = true;
                     break;
                 }
                 nel += add;
+                npairs += addp;
                 take(j, b);
                 queue.push_back(j);
             }
@@ -210,6 +215,161 @@ inline BlockHost build_block_host(int d, int64_t nq, int64_t nme, const int32_t 
     H.total_elems = H.elem_ptr.back();
     H.ok = true;
     return H;
+}
+
+// Vertex-pair work lists of the elasticity block kernel, derived from the
+// incidence records of a BlockHost.  A "pair" is one CSR entry (row r of the
+// block, column position p): the d x d block of the vector operator that one
+// thread sums in registers.  For each pair the plan lists the block elements
+// that contain both vertices, in ascending element position, as 16-bit
+// entries: element position (bits 0-9), local index a of the row vertex
+// (bits 10-11) and b of the column vertex (bits 12-13); 0xffff pads.
+// Pairs are sorted by list length (longest first, stable) and cut into tasks
+// of 64 (one per wavefront lane); a task's entries are stored entry-major
+// (entry t of lane j at t*64 + j) up to the task's longest list.  Tasks are
+// dealt to kWaves wavefronts, at most kSlots each, longest-first onto the
+// least-loaded wavefront, and stored wavefront by wavefront.  hdr holds, per
+// task lane, r | p << 7 (0xffff for an empty lane).
+struct PairHost {
+    std::vector<int32_t> wt;        // [nb*(kWaves+1)] first task of each wavefront (global)
+    std::vector<int32_t> task_cnt;  // entries per lane of each task
+    std::vector<int64_t> task_ent;  // first entry of each task (global)
+    std::vector<uint16_t> hdr;      // [ntask*64]
+    std::vector<uint16_t> ent;
+    std::vector<int64_t> ent_ptr;   // [nb+1]
+    int64_t max_ent = 0;
+    bool ok = false;
+};
+
+constexpr uint16_t kPairPad = 0xffffu;
+
+inline PairHost build_pair_host(const BlockHost &H, int d, const int32_t *rp, int kWaves,
+                                int kSlots, int nthreads) {
+    PairHost P;
+    const int NL = d + 1;
+    const int nb = H.nb;
+    struct Blk {
+        std::vector<int32_t> cnt;        // per task
+        std::vector<int32_t> eoff;       // per task, local entry offset
+        std::vector<int32_t> wfirst;     // [kWaves+1], local task index
+        std::vector<uint16_t> hdr, ent;
+        bool ok = true;
+    };
+    std::vector<Blk> blks(nb);
+    auto work = [&](int b0, int b1) {
+        std::vector<int32_t> off, lst_ptr, fill, order;
+        std::vector<uint16_t> lst;
+        for (int b = b0; b < b1; ++b) {
+            Blk &B = blks[b];
+            const int32_t *rw = H.rows.data() + H.row_ptr[b];
+            const int nr = H.row_ptr[b + 1] - H.row_ptr[b];
+            if (nr > 128) {
+                B.ok = false;
+                continue;
+            }
+            off.assign(nr + 1, 0);
+            for (int r = 0; r < nr; ++r) off[r + 1] = off[r] + rp[rw[r] + 1] - rp[rw[r]];
+            const int np = off[nr];
+            const uint32_t *rec = H.rec.data() + H.rec_ptr[b];
+            const int maxdeg = H.maxdeg[b];
+            // list lengths, then lists (records of a row come in ascending element position)
+            lst_ptr.assign(np + 1, 0);
+            for (int r = 0; r < nr; ++r)
+                for (int t = 0; t < maxdeg; ++t) {
+                    const uint32_t x = rec[size_t(t) * nr + r];
+                    if (x == kRecPad) break;
+                    for (int a = 0; a < NL; ++a) lst_ptr[off[r] + ((x >> (12 + 5 * a)) & 31u) + 1]++;
+                }
+            for (int q = 0; q < np; ++q) lst_ptr[q + 1] += lst_ptr[q];
+            lst.assign(lst_ptr[np], 0);
+            fill.assign(lst_ptr.begin(), lst_ptr.end() - 1);
+            for (int r = 0; r < nr; ++r)
+                for (int t = 0; t < maxdeg; ++t) {
+                    const uint32_t x = rec[size_t(t) * nr + r];
+                    if (x == kRecPad) break;
+                    const uint32_t ep = x & 1023u, al = (x >> 10) & 3u;
+                    for (int a = 0; a < NL; ++a) {
+                        const int q = off[r] + int((x >> (12 + 5 * a)) & 31u);
+                        lst[fill[q]++] = uint16_t(ep | (al << 10) | (uint32_t(a) << 12));
+                    }
+                }
+            order.resize(np);
+            for (int q = 0; q < np; ++q) order[q] = q;
+            std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+                return lst_ptr[x + 1] - lst_ptr[x] > lst_ptr[y + 1] - lst_ptr[y];
+            });
+            const int ntask = (np + 63) / 64;
+            if (ntask > kWaves * kSlots) {
+                B.ok = false;
+                continue;
+            }
+            // longest-first onto the least-loaded wavefront with a free slot
+            std::vector<std::vector<int>> wl(kWaves);
+            std::vector<int64_t> load(kWaves, 0);
+            for (int t = 0; t < ntask; ++t) {
+                const int q0 = order[size_t(t) * 64];
+                const int c = lst_ptr[q0 + 1] - lst_ptr[q0];
+                int best = -1;
+                for (int w = 0; w < kWaves; ++w)
+                    if (int(wl[w].size()) < kSlots && (best < 0 || load[w] < load[best])) best = w;
+                wl[best].push_back(t);
+                load[best] += c;
+            }
+            B.wfirst.push_back(0);
+            for (int w = 0; w < kWaves; ++w) {
+                for (int t : wl[w]) {
+                    const int q0 = order[size_t(t) * 64];
+                    const int c = lst_ptr[q0 + 1] - lst_ptr[q0];
+                    B.cnt.push_back(c);
+                    B.eoff.push_back(int32_t(B.ent.size()));
+                    const size_t e0 = B.ent.size();
+                    B.ent.resize(e0 + size_t(c) * 64, kPairPad);
+                    for (int j = 0; j < 64; ++j) {
+                        const int k = t * 64 + j;
+                        if (k >= np) {
+                            B.hdr.push_back(kPairPad);
+                            continue;
+                        }
+                        const int q = order[k];
+                        const int r = int(std::upper_bound(off.begin(), off.end(), q) - off.begin()) - 1;
+                        B.hdr.push_back(uint16_t(r | ((q - off[r]) << 7)));
+                        for (int u = lst_ptr[q]; u < lst_ptr[q + 1]; ++u)
+                            B.ent[e0 + size_t(u - lst_ptr[q]) * 64 + j] = lst[u];
+                    }
+                }
+                B.wfirst.push_back(int32_t(B.cnt.size()));
+            }
+        }
+    };
+    {
+        const int nt = std::max(1, std::min(nthreads, nb / 64 + 1));
+        std::vector<std::thread> th;
+        const int chunk = (nb + nt - 1) / nt;
+        for (int t = 0; t < nt; ++t) {
+            const int b0 = t * chunk, b1 = std::min(nb, b0 + chunk);
+            if (b0 >= b1) break;
+            th.emplace_back(work, b0, b1);
+        }
+        for (auto &x : th) x.join();
+    }
+    P.ent_ptr.push_back(0);
+    for (int b = 0; b < nb; ++b) {
+        const Blk &B = blks[b];
+        if (!B.ok) return PairHost();
+        const int32_t t0 = int32_t(P.task_cnt.size());
+        const int64_t e0 = int64_t(P.ent.size());
+        for (int w = 0; w <= kWaves; ++w) P.wt.push_back(t0 + B.wfirst[w]);
+        for (size_t t = 0; t < B.cnt.size(); ++t) {
+            P.task_cnt.push_back(B.cnt[t]);
+            P.task_ent.push_back(e0 + B.eoff[t]);
+        }
+        P.hdr.insert(P.hdr.end(), B.hdr.begin(), B.hdr.end());
+        P.ent.insert(P.ent.end(), B.ent.begin(), B.ent.end());
+        P.ent_ptr.push_back(int64_t(P.ent.size()));
+        P.max_ent = std::max<int64_t>(P.max_ent, int64_t(B.ent.size()));
+    }
+    P.ok = true;
+    return P;
 }
 
 }  // namespace femasm

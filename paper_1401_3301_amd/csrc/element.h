@@ -12,7 +12,8 @@
 //   weighted    |det| (1+delta) (w^s + (w_a + w_b)) / (d+3)!          (Section 4.1)
 //   elasticity  [lambda c_al c_bn + mu (delta_ln c_a.c_b + c_an c_bl)] / (d! |det|)
 // The elasticity form is the lemma of Section 5.1 with Q^{n,l}, S^{n,l}
-// multiplied out: Q^{n,l} picks g_al g_bn, S^{n,l} gives the strain product.
+// multiplied out: Q^{n,l} picks g_al g_bn, S^{n,l} gives the strain product;
+// it is evaluated as a combination of summed outer products (below).
 // Every expression is written so that swapping (a,l) with (b,n) yields the
 // same operations on swapped operands, which makes each element matrix, and
 // therefore the assembled matrix, exactly symmetric.  Contraction of a*b+c
@@ -90,6 +91,30 @@ __device__ __forceinline__ double cdot(const double (&a)[D], const double (&b)[D
 #pragma unroll
     for (int x = 1; x < D; ++x) s = fma(a[x], b[x], s);
     return s;
+}
+
+// Scaled cofactors for elasticity: ch_a = c_a / sqrt(d! |det|), so that
+// ch_al * ch_bn = |K| g_al g_bn.  The lemma of Section 5.1 then reads
+//   E[(a,l),(b,n)] = lambda X_ln + mu (delta_ln tr X + X_nl),  X = ch_a ch_b^T,
+// and summing X over the elements of a vertex pair before combining needs one
+// fused multiply-add per entry and element.  X_ji is exactly X_ij^T (the
+// products commute), so the assembled matrix stays exactly symmetric.
+template <int D>
+__device__ __forceinline__ double elas_scale(double det);
+template <>
+__device__ __forceinline__ double elas_scale<2>(double det) {
+    return 1.0 / sqrt(2.0 * fabs(det));
+}
+template <>
+__device__ __forceinline__ double elas_scale<3>(double det) {
+    return 1.0 / sqrt(6.0 * fabs(det));
+}
+
+// Final elasticity value of entry (l, n) of a vertex-pair block from the
+// summed X (xln = X_ln, xnl = X_nl, tr = X_00 + X_11 [+ X_22] in that order).
+__device__ __forceinline__ double elas_combine(double xln, double xnl, double tr, bool diag,
+                                               double lam, double mu) {
+    return fma(lam, xln, mu * (diag ? tr + xnl : xnl));
 }
 
 template <int D>

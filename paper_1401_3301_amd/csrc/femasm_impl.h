@@ -16,6 +16,14 @@ constexpr size_t kLdsCap = 64 * 1024;
 // Launch geometry of the row-gather kernel for one dof multiplicity M
 // (1 for scalar operators, d for elasticity): rows per workgroup and the
 // LDS bytes the largest row tile needs.
+// LDS bytes of a row-gather tile of `rows` dof rows spanning `span` CSR values:
+// the accumulators, plus the elasticity epilogue tables (M > 1).
+inline size_t tile_lds_bytes(int M, int64_t span, int64_t rows) {
+    size_t b = size_t(span) * sizeof(double);
+    if (M > 1) b += 8 * size_t((rows + M - 1) / M) + size_t(span / (M * M)) + 16;
+    return b;
+}
+
 struct RowLaunch {
     int rows_per_wg = 0;
     size_t lds_bytes = 0;
@@ -43,6 +51,23 @@ struct BlockPlan {
     int32_t *maxdeg = nullptr;    // [nb]
 };
 
+// Vertex-pair layout of the elasticity block kernel (see blocks_host.h):
+// the block's rows, touched vertices and elements as in BlockPlan (rec,
+// acc_off, nacc and maxdeg unused), plus the per-wavefront pair tasks.
+struct PairPlan {
+    BlockPlan blk;
+    int32_t *wt = nullptr;        // [nb*(kPairWaves+1)] first task of each wavefront
+    int32_t *task_cnt = nullptr;  // entries per lane of each task
+    int64_t *task_ent = nullptr;  // first entry of each task
+    uint16_t *hdr = nullptr;      // [ntask*64] r | p << 7 per task lane
+    uint16_t *ent = nullptr;      // entry lists, entry-major within a task
+    int64_t *ent_ptr = nullptr;   // [nb+1]
+    int64_t max_ent = 0;
+    bool ok = false;
+};
+constexpr int kPairWaves = 4;     // wavefronts per workgroup of the pair kernel
+constexpr int kPairSlots = 4;     // tasks per wavefront at most
+
 struct fem_plan_data {
     int d = 0;
     int64_t nq = 0, nme = 0, nnz = 0;
@@ -61,6 +86,7 @@ struct fem_plan_data {
     std::vector<int32_t> h_rp;    // host copy of rp (launch geometry)
     RowLaunch launch[4];          // indexed by M
     BlockPlan blk;                // block-kernel layout (scalar operators)
+    PairPlan pvec;                // pair-kernel layout (elasticity)
 };
 
 }  // namespace femasm
@@ -74,10 +100,13 @@ fem_status upload_blocks(fem_plan_data *p, int d, int64_t nq, int64_t nme, const
                          const int32_t *rp, const int32_t *ci, const int64_t *ip,
                          const int32_t *inc_k);
 void free_blocks(BlockPlan *b);
+void free_pairs(PairPlan *p);
 // Launches the block kernel for a scalar operator; returns false (nothing
 // launched) when the plan has no block layout.
 bool launch_block(const fem_plan_data *p, int op, const double *q, const double *w,
                   double *values, hipStream_t s, hipError_t *err);
+bool launch_block(const fem_plan_data *p, int op, const double *q, const double *w,
+                  double *values, hipStream_t s, hipError_t *err, double lam, double mu);
 RowLaunch row_launch_for(const std::vector<int32_t> &h_rp, int64_t nq, int M, size_t lds_cap);
 
 // Device-side view of one mesh for the shared tile routine.

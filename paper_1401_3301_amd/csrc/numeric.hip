@@ -148,7 +148,8 @@ extern "C" fem_status fem_assemble_numeric(fem_plan plan, int32_t op, const doub
     if (op == FEM_OP_MASS_W && plan->nnz > 0 && !w) return FEM_ERR_ARG;
     if (plan->launch[M].rows_per_wg == 0) return FEM_ERR_OVERFLOW;
     hipError_t e = hipSuccess;
-    if (plan->nq > 0 && launch_block(plan, op, q, w, values, stream, &e)) return hip_status(e);
+    if (plan->nq > 0 && launch_block(plan, op, q, w, values, stream, &e, lambda, mu))
+        return hip_status(e);
     const MeshView mv = plan_view(plan, q, w, values);
     if (plan->d == 2) {
         switch (op) {

@@ -71,6 +71,25 @@ __device__ __forceinline__ void assemble_row_tile(const MeshView &mv, int64_t r0
     const int64_t top = vrow_start<M>(mv.rp, r1);
     const int nacc = int(top - base);
     for (int s = threadIdx.x; s < nacc; s += blockDim.x) acc[s] = 0.0;
+    // Elasticity tiles hold whole vertices (r0, r1 multiples of M).  After the
+    // accumulators: per vertex its segment start and row length, and for each
+    // group of M*M accumulators the vertex it belongs to (combining epilogue).
+    int32_t *vinfo = nullptr;
+    uint8_t *vof = nullptr;
+    int nv = 0;
+    if constexpr (OP == FEM_OP_ELAS) {
+        nv = int((r1 - r0) / M);
+        vinfo = reinterpret_cast<int32_t *>(acc + nacc);
+        vof = reinterpret_cast<uint8_t *>(vinfo + 2 * nv);
+        for (int v = threadIdx.x; v < nv; v += blockDim.x) {
+            const int64_t i = r0 / M + v;
+            const int b0 = int(vrow_start<M>(mv.rp, i * M) - base);
+            const int len = mv.rp[i + 1] - mv.rp[i];
+            vinfo[v] = b0;
+            vinfo[nv + v] = len;
+            for (int k = 0; k < len; ++k) vof[b0 / (M * M) + k] = uint8_t(v);
+        }
+    }
     __syncthreads();
 
     const int64_t r = r0 + threadIdx.x;
@@ -125,7 +144,6 @@ __device__ __forceinline__ void assemble_row_tile(const MeshView &mv, int64_t r0
                 Elem<D> E;
                 elem_geometry(P, E);
                 if (E.det == 0.0) { bad = 1; continue; }
-                const double inv = 1.0 / (Fact<D>::dfact * fabs(E.det));
                 double ca[D];
 #pragma unroll
                 for (int x = 0; x < D; ++x) {
@@ -135,41 +153,48 @@ __device__ __forceinline__ void assemble_row_tile(const MeshView &mv, int64_t r0
                     ca[x] = sel<D>(cx, al);
                 }
                 if constexpr (OP == FEM_OP_STIFF) {
+                    const double inv = 1.0 / (Fact<D>::dfact * fabs(E.det));
 #pragma unroll
                     for (int b = 0; b < NL; ++b) {
                         const int pos = (off >> (8 * b)) & 255u;
                         my[pos] += cdot<D>(ca, E.c[b]) * inv;
                     }
                 } else {
-                    // elasticity: row (al, l), columns (b, n)
+                    // elasticity: X_ln += ch_al ch_bn for the columns (b, n)
+                    const double sc = elas_scale<D>(E.det);
                     double cal;
                     if constexpr (D == 2)
                         cal = (l == 1) ? ca[1] : ca[0];
                     else
                         cal = pick(ca[0], ca[1], ca[2], l);
+                    const double chal = cal * sc;
 #pragma unroll
                     for (int b = 0; b < NL; ++b) {
                         const int pos = (off >> (8 * b)) & 255u;
-                        const double dab = cdot<D>(ca, E.c[b]);
-                        double cbl;
-                        if constexpr (D == 2)
-                            cbl = (l == 1) ? E.c[b][1] : E.c[b][0];
-                        else
-                            cbl = pick(E.c[b][0], E.c[b][1], E.c[b][2], l);
 #pragma unroll
-                        for (int n = 0; n < D; ++n) {
-                            const double sym = (l == n) ? dab : 0.0;
-                            const double val =
-                                fma(lam, cal * E.c[b][n], mu * fma(ca[n], cbl, sym));
-                            my[M * pos + n] = fma(val, inv, my[M * pos + n]);
-                        }
+                        for (int n = 0; n < D; ++n)
+                            my[M * pos + n] = fma(chal, E.c[b][n] * sc, my[M * pos + n]);
                     }
                 }
             }
         }
     }
     __syncthreads();
-    for (int s = threadIdx.x; s < nacc; s += blockDim.x) mv.values[base + s] = acc[s];
+    if constexpr (OP == FEM_OP_ELAS) {
+        for (int s = threadIdx.x; s < nacc; s += blockDim.x) {
+            const int v = vof[s / (M * M)];
+            const int b0 = vinfo[v], ml = M * vinfo[nv + v];
+            const int sl = s - b0;
+            const int l = sl / ml, rem = sl - l * ml, pos = rem / M, n = rem - pos * M;
+            const double *x = acc + b0 + M * pos;
+            double tr = x[0];
+#pragma unroll
+            for (int m = 1; m < M; ++m) tr += x[m * ml + m];
+            mv.values[base + s] = elas_combine(x[l * ml + n], x[n * ml + l], tr, l == n, lam, mu);
+        }
+    } else {
+        for (int s = threadIdx.x; s < nacc; s += blockDim.x) mv.values[base + s] = acc[s];
+    }
 }
 
 }  // namespace femasm

@@ -76,6 +76,7 @@ void free_plan_arrays(fem_plan_data *p) {
     p->status = nullptr;
     p->part = nullptr;
     free_blocks(&p->blk);
+    free_pairs(&p->pvec);
 }
 
 }  // namespace
@@ -89,14 +90,14 @@ RowLaunch row_launch_for(const std::vector<int32_t> &h_rp, int64_t nq, int M, si
         if (l) s += l * M * int64_t(h_rp[i + 1] - h_rp[i]);
         return s;
     };
-    for (int R : {256, 128, 64}) {
+    for (int R0 : {256, 128, 64}) {
+        const int R = R0 / M * M;   // elasticity tiles hold whole vertices
         int64_t tiles = (nrows + R - 1) / R;
-        int64_t worst = 0;
+        size_t bytes = sizeof(double);
         for (int64_t t = 0; t < tiles; ++t) {
             int64_t r0 = t * R, r1 = std::min(nrows, r0 + R);
-            worst = std::max(worst, vstart(r1) - vstart(r0));
+            bytes = std::max(bytes, tile_lds_bytes(M, vstart(r1) - vstart(r0), r1 - r0));
         }
-        size_t bytes = size_t(std::max<int64_t>(worst, 1)) * sizeof(double);
         best.rows_per_wg = R;
         best.lds_bytes = bytes;
         best.tiles = tiles;

@@ -93,6 +93,23 @@ def test_deterministic_and_symmetric(op):
     assert (A != A.T).nnz == 0, "not exactly symmetric"
 
 
+@pytest.mark.parametrize("op", OPS)
+@pytest.mark.parametrize("name", ["square64", "cube9_perm", "cube14"])
+def test_block_and_rowgather_kernels_agree(name, op, monkeypatch):
+    """The vertex-block kernels (scalar operators), the vertex-pair kernel
+    (elasticity) and the row-gather kernel sum every entry in the same order
+    with the same expressions: their values agree bit for bit."""
+    mesh = SMALL[name]()
+    w = mg.lognormal_field(mesh.nq, 3)
+    me, q, wt = _gpu(mesh, w)
+    plan = femasm.Plan(me, mesh.nq)
+    v_blk = plan.numeric(op, q, wt, 1.3, 0.7).clone()
+    monkeypatch.setenv("FEMASM_KERNEL", "rowgather")
+    v_row = plan.numeric(op, q, wt, 1.3, 0.7).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(v_blk, v_row)
+
+
 def test_slot_map_consistency():
     mesh = mg.kuhn_cube(6, 0.15, seed=8, perm_seed=80)
     me, q, _ = _gpu(mesh)
