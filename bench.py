@@ -151,6 +151,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=128, help="cubes per side")
+    ap.add_argument("--op", choices=["STIFF", "ELAS"], default="STIFF",
+                    help="operator of the timed step (the headline metric is STIFF)")
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -189,9 +191,10 @@ def main():
     plan = femasm.Plan(me, mesh.nq)
     torch.cuda.synchronize()
     t_sym = time.perf_counter() - t0
-    nrows, nnz = plan.query("STIFF")
+    op_code = femasm.FEM_OP[args.op]
+    nrows, nnz = plan.query(args.op)
     vals = torch.empty(nnz, dtype=torch.float64, device=dev)
-    fn = lambda: femasm.fem_assemble_numeric(plan.handle, 2, q.data_ptr(), None, 1.0, 0.5,
+    fn = lambda: femasm.fem_assemble_numeric(plan.handle, op_code, q.data_ptr(), None, 1.0, 0.5,
                                             vals.data_ptr(), stream.cuda_stream)
     wall, per = time_launches(fn, stream, args.steps, args.warmup)
     plan.sync_status()
@@ -200,35 +203,37 @@ def main():
     value = mesh.nme / (ms_per_step / 1e3)
     ab = algorithmic_bytes(3, mesh.nq, mesh.nme, nnz)
     achieved = ab / (kern_ms / 1e3) / 1e9
-    print(f"[bench] stiffness: {ms_per_step:.3f} ms/step, kernel {kern_ms:.3f} ms, "
+    print(f"[bench] {args.op}: {ms_per_step:.3f} ms/step, kernel {kern_ms:.3f} ms, "
           f"{achieved:.0f} GB/s algorithmic", file=sys.stderr, flush=True)
 
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         tr = json.load(open(TRAFFIC_FILE))
-        if tr.get("kernel_sha") == kernel_sha() and tr.get("n") == args.n:
+        if tr.get("kernel_sha") == kernel_sha() and tr.get("n") == args.n and args.op == "STIFF":
             traffic = tr.get("traffic_bytes")
 
+    opname = {"STIFF": "stiffness", "ELAS": "elasticity"}[args.op]
+    kernel = {"STIFF": "k_block<3,STIFF>", "ELAS": "k_pair_elas<3>"}[args.op]
     line = {
-        "metric": "P1 elements assembled/s into CSR (3D stiffness, FP64) + achieved HBM GB/s",
+        "metric": f"P1 elements assembled/s into CSR (3D {opname}, FP64) + achieved HBM GB/s",
         "value": value, "unit": "elements/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"3D P1 stiffness, unit cube {args.n}^3 cubes x 6 Kuhn tets, "
+        "config": {"workload": f"3D P1 {opname}, unit cube {args.n}^3 cubes x 6 Kuhn tets, "
                                f"jitter 0.15h, permuted elements (seed 33)",
                    "nq": mesh.nq, "nme": mesh.nme, "nnz": nnz, "plan_reused": True},
         "nnz_per_s": nnz / (ms_per_step / 1e3),
         "achieved_GBps": achieved,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
-                     "kernel": "k_block<3,STIFF>", "kernel_ms": kern_ms,
+                     "kernel": kernel, "kernel_ms": kern_ms,
                      "algorithmic_bytes": ab},
         "symbolic_s": t_sym,
     }
-    if not args.no_cpu:
+    if not args.no_cpu and args.op == "STIFF":
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(mesh)
-    if not args.no_extra:
+    if not args.no_extra and args.op == "STIFF":
         print("[bench] extras ...", file=sys.stderr, flush=True)
         line["extra"] = extras(torch, femasm, mg, plan, q, stream, args.steps)
     print(json.dumps(line), flush=True)

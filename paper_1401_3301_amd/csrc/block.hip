@@ -257,193 +257,6 @@ __global__ void __launch_bounds__(kWG) k_block(BlockView bv, int32_t *status) {
 }
 
 
-struct PairView {
-    const int32_t *rp;
-    const int32_t *rows;
-    const int32_t *row_ptr;
-    const int32_t *nodes;
-    const int32_t *node_ptr;
-    const uint2 *elem;
-    const int32_t *elem_ptr;
-    const int32_t *wt;
-    const int32_t *task_cnt;
-    const int64_t *task_ent;
-    const uint16_t *hdr;
-    const uint16_t *ent;
-    const int64_t *ent_ptr;
-    const double *q;
-    double *values;
-    int64_t nq;
-    int32_t max_nodes, max_rows;
-    uint32_t off_ev, off_row, off_ent;
-};
-
-// Elasticity on vertex blocks, one vertex pair (CSR entry of the scalar
-// pattern) per thread.  Per chunk of block elements, the element phase stores
-// the scaled cofactors ch_a (d+1 vectors) of each element in LDS; each thread
-// then walks the entries of its pairs that fall in the chunk and sums
-// X_ln += ch_al ch_bn in registers, in ascending element position, i.e. in
-// ascending caller element number.  At the end every pair writes its d x d
-// block lambda X + mu (tr X I + X^T) straight to the CSR values.  A
-// wavefront owns up to kPairSlots tasks of 64 pairs.
-template <int D, int kChunk>
-__global__ void __launch_bounds__(kPairWaves * 64) k_pair_elas(PairView pv, double lam, double mu,
-                                                              int32_t *status) {
-    constexpr int kWG = kPairWaves * 64;
-    constexpr int NL = D + 1;
-    constexpr int NVE = (NL * D) | 1;
-    constexpr int S = kPairSlots;
-    extern __shared__ __align__(16) unsigned char smem[];
-    double *crd = reinterpret_cast<double *>(smem);
-    double *ev = reinterpret_cast<double *>(smem + pv.off_ev);
-    int32_t *rowg = reinterpret_cast<int32_t *>(smem + pv.off_row);
-    int32_t *rowl = rowg + pv.max_rows;
-    uint16_t *ent = reinterpret_cast<uint16_t *>(smem + pv.off_ent);
-
-    const int b = int(xcd_tile(blockIdx.x, gridDim.x));
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int r0 = pv.row_ptr[b], nr = pv.row_ptr[b + 1] - r0;
-    const int n0 = pv.node_ptr[b], nn = pv.node_ptr[b + 1] - n0;
-    const int e0 = pv.elem_ptr[b], ne = pv.elem_ptr[b + 1] - e0;
-    const int64_t eb = pv.ent_ptr[b];
-    const int nent = int(pv.ent_ptr[b + 1] - eb);
-    const int64_t nq = pv.nq;
-    const int MN = pv.max_nodes;
-
-    // entry lists of the block (a multiple of 64 entries, 128-byte aligned)
-    {
-        const uint4 *src = reinterpret_cast<const uint4 *>(pv.ent + eb);
-        uint4 *dst = reinterpret_cast<uint4 *>(ent);
-        for (int i = tid; i < nent / 8; i += kWG) dst[i] = src[i];
-    }
-    uint2 vnext = tid < ne && tid < kChunk ? pv.elem[e0 + tid] : make_uint2(0u, 0u);
-    for (int base = 0; base < nn; base += 2 * kWG) {
-        int64_t gi[2];
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int n = base + u * kWG + tid;
-            gi[u] = n < nn ? pv.nodes[n0 + n] : 0;
-        }
-        double c[2][D];
-#pragma unroll
-        for (int u = 0; u < 2; ++u)
-            if (base + u * kWG + tid < nn)
-#pragma unroll
-                for (int x = 0; x < D; ++x) c[u][x] = pv.q[x * nq + gi[u]];
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int n = base + u * kWG + tid;
-            if (n < nn)
-#pragma unroll
-                for (int x = 0; x < D; ++x) crd[x * MN + n] = c[u][x];
-        }
-    }
-    if (tid < nr) {
-        const int row = pv.rows[r0 + tid];
-        const int g = pv.rp[row];
-        rowg[tid] = g;
-        rowl[tid] = pv.rp[row + 1] - g;
-    }
-    // this wavefront's tasks (wavefront-uniform) and this lane's pairs
-    const int t0 = __builtin_amdgcn_readfirstlane(pv.wt[b * (kPairWaves + 1) + wave]);
-    const int ns = __builtin_amdgcn_readfirstlane(pv.wt[b * (kPairWaves + 1) + wave + 1]) - t0;
-    int cnt[S], ebase[S], cur[S];
-    uint32_t hd[S];
-    double X[S][D * D];
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-        cnt[s] = 0;
-        ebase[s] = 0;
-        cur[s] = 0;
-        hd[s] = kPairPad;
-        if (s < ns) {
-            cnt[s] = __builtin_amdgcn_readfirstlane(pv.task_cnt[t0 + s]);
-            ebase[s] = __builtin_amdgcn_readfirstlane(int(pv.task_ent[t0 + s] - eb)) + lane;
-            hd[s] = pv.hdr[int64_t(t0 + s) * 64 + lane];
-        }
-#pragma unroll
-        for (int k = 0; k < D * D; ++k) X[s][k] = 0.0;
-    }
-    int bad = 0;
-
-    for (int c0 = 0; c0 < ne; c0 += kChunk) {
-        __syncthreads();
-        if (tid < kChunk) {
-            const uint2 vv = vnext;
-            const int en = c0 + kChunk + tid;
-            if (en < ne) vnext = pv.elem[e0 + en];
-            if (c0 + tid < ne) {
-                const int v[4] = {int(vv.x & 0xffffu), int(vv.x >> 16), int(vv.y & 0xffffu),
-                                  int(vv.y >> 16)};
-                double P[NL][D];
-#pragma unroll
-                for (int a = 0; a < NL; ++a)
-#pragma unroll
-                    for (int x = 0; x < D; ++x) P[a][x] = crd[x * MN + v[a]];
-                Elem<D> E;
-                elem_geometry(P, E);
-                const bool deg = E.det == 0.0;
-                if (deg) bad = 1;
-                const double sc = deg ? 0.0 : elas_scale<D>(E.det);
-                double *out = ev + tid * NVE;
-#pragma unroll
-                for (int a = 0; a < NL; ++a)
-#pragma unroll
-                    for (int x = 0; x < D; ++x) out[a * D + x] = E.c[a][x] * sc;
-            }
-        }
-        __syncthreads();
-        const uint32_t cend = uint32_t(c0 + kChunk);
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            if (s < ns) {
-                while (cur[s] < cnt[s]) {
-                    const uint32_t x = ent[ebase[s] + cur[s] * 64];
-                    if (x == kPairPad) {
-                        cur[s] = cnt[s];
-                        break;
-                    }
-                    const uint32_t e = x & 1023u;
-                    if (e >= cend) break;
-                    ++cur[s];
-                    const double *Ee = ev + int(e - uint32_t(c0)) * NVE;
-                    const double *ha = Ee + int((x >> 10) & 3u) * D;
-                    const double *hb = Ee + int((x >> 12) & 3u) * D;
-                    double A[D], B[D];
-#pragma unroll
-                    for (int k = 0; k < D; ++k) {
-                        A[k] = ha[k];
-                        B[k] = hb[k];
-                    }
-#pragma unroll
-                    for (int l = 0; l < D; ++l)
-#pragma unroll
-                        for (int n = 0; n < D; ++n) X[s][l * D + n] = fma(A[l], B[n], X[s][l * D + n]);
-                }
-            }
-        }
-    }
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-        if (s < ns && hd[s] != kPairPad) {
-            const int r = int(hd[s] & 127u), p = int(hd[s] >> 7);
-            const int len = rowl[r];
-            double *out = pv.values + int64_t(D) * D * rowg[r] + D * p;
-            double tr = X[s][0];
-#pragma unroll
-            for (int m = 1; m < D; ++m) tr += X[s][m * D + m];
-#pragma unroll
-            for (int l = 0; l < D; ++l)
-#pragma unroll
-                for (int n = 0; n < D; ++n)
-                    out[l * D * len + n] =
-                        elas_combine(X[s][l * D + n], X[s][n * D + l], tr, l == n, lam, mu);
-        }
-    }
-    const unsigned long long any = __ballot(bad != 0);
-    if (any != 0ull && (threadIdx.x & 63) == __ffsll((long long)any) - 1) atomicOr(status, bad);
-}
-
 template <class T>
 static fem_status up(T **dst, const std::vector<T> &src) {
     *dst = nullptr;
@@ -479,9 +292,9 @@ static fem_status upload_layout(BlockPlan &B, const BlockHost &H, const int32_t 
     if (st == FEM_OK) st = up(&B.node_ptr, H.node_ptr);
     if (st == FEM_OK) st = up(&B.elem, H.elem);
     if (st == FEM_OK) st = up(&B.elem_ptr, H.elem_ptr);
+    if (st == FEM_OK) st = up(&B.acc_off, acc_off);
+    if (st == FEM_OK) st = up(&B.nacc, nacc);
     if (with_records) {
-        if (st == FEM_OK) st = up(&B.acc_off, acc_off);
-        if (st == FEM_OK) st = up(&B.nacc, nacc);
         if (st == FEM_OK) st = up(&B.rec, H.rec);
         if (st == FEM_OK) st = up(&B.rec_ptr, H.rec_ptr);
         if (st == FEM_OK) st = up(&B.maxdeg, H.maxdeg);
@@ -507,44 +320,11 @@ static fem_status upload_layout(BlockPlan &B, const BlockHost &H, const int32_t 
     return FEM_OK;
 }
 
-void free_pairs(PairPlan *p) {
-    free_blocks(&p->blk);
-    void *ptrs[] = {p->wt, p->task_cnt, p->task_ent, p->hdr, p->ent, p->ent_ptr};
-    for (void *x : ptrs)
-        if (x) (void)hipFree(x);
-    *p = PairPlan();
-}
-
-static fem_status upload_pairs(PairPlan &P, int R, int d, int64_t nq, int64_t nme,
-                               const int32_t *me, const int32_t *rp, const int32_t *ci,
-                               const int64_t *ip, const int32_t *inc_k) {
-    const int64_t max_pairs = int64_t(64) * kPairWaves * kPairSlots;
-    BlockHost H = build_block_host(d, nq, nme, me, rp, ci, ip, inc_k, R, 16, max_pairs);
-    if (!H.ok || H.nb == 0) return FEM_OK;  // row-gather kernel only
-    PairHost PH = build_pair_host(H, d, rp, kPairWaves, kPairSlots, 16);
-    if (!PH.ok) return FEM_OK;
-    fem_status st = upload_layout(P.blk, H, rp, false);
-    if (st == FEM_OK) st = up(&P.wt, PH.wt);
-    if (st == FEM_OK) st = up(&P.task_cnt, PH.task_cnt);
-    if (st == FEM_OK) st = up(&P.task_ent, PH.task_ent);
-    if (st == FEM_OK) st = up(&P.hdr, PH.hdr);
-    if (st == FEM_OK) st = up(&P.ent, PH.ent);
-    if (st == FEM_OK) st = up(&P.ent_ptr, PH.ent_ptr);
-    if (st != FEM_OK) {
-        free_pairs(&P);
-        return st;
-    }
-    P.max_ent = PH.max_ent;
-    P.ok = true;
-    return FEM_OK;
-}
-
 fem_status upload_blocks(fem_plan_data *p, int d, int64_t nq, int64_t nme, const int32_t *me,
                          const int32_t *rp, const int32_t *ci, const int64_t *ip,
                          const int32_t *inc_k) {
-    // scalar operators: FEMASM_BLOCK_ROWS (16..128) rows per block when set,
-    // else 64; elasticity pairs: FEMASM_ELAS_BLOCK_ROWS (16..128) when set,
-    // else 64 in 3D and 128 in 2D (blocks also stop at 1024 CSR entries)
+    // record layout (scalar operators): FEMASM_BLOCK_ROWS (16..128) rows
+    // per block when set, else 64
     int R = 64;
     if (const char *env = getenv("FEMASM_BLOCK_ROWS")) R = std::max(16, std::min(kMaxWG, atoi(env)));
     {
@@ -554,11 +334,27 @@ fem_status upload_blocks(fem_plan_data *p, int d, int64_t nq, int64_t nme, const
             if (st != FEM_OK) return st;
         }
     }
-    int Re = d == 3 ? 64 : 128;
-    if (const char *env = getenv("FEMASM_ELAS_BLOCK_ROWS"))
-        Re = std::max(16, std::min(128, atoi(env)));
-    fem_status st = upload_pairs(p->pvec, Re, d, nq, nme, me, rp, ci, ip, inc_k);
-    if (st != FEM_OK) free_blocks(&p->blk);
+    // pair layouts: FEMASM_PAIR_ROWS / FEMASM_ELAS_ROWS rows per block when
+    // set (16..128), else 32 (scalar operators) and 24 in 3D / 64 in 2D
+    // (elasticity); FEMASM_PAIR_SLOTS / FEMASM_ELAS_SLOTS (1, 2 or 4) tasks
+    // of 64 pairs per wavefront, else 2.  A block also stops at
+    // 256 * slots CSR entries.
+    auto env_int = [](const char *name, int dflt, int lo, int hi) {
+        const char *e = getenv(name);
+        return e ? std::max(lo, std::min(hi, atoi(e))) : dflt;
+    };
+    auto slots_of = [](int v) { return v >= 4 ? 4 : (v <= 1 ? 1 : 2); };
+    const int Rs = env_int("FEMASM_PAIR_ROWS", 32, 16, 128);
+    const int Ss = slots_of(env_int("FEMASM_PAIR_SLOTS", 2, 1, 4));
+    const int Re = env_int("FEMASM_ELAS_ROWS", d == 3 ? 24 : 64, 16, 128);
+    const int Se = slots_of(env_int("FEMASM_ELAS_SLOTS", 2, 1, 4));
+    fem_status st = upload_pairs(p->pscal, Rs, Ss, true, d, nq, nme, me, rp, ci, ip, inc_k);
+    if (st == FEM_OK) st = upload_pairs(p->pvec, Re, Se, false, d, nq, nme, me, rp, ci, ip, inc_k);
+    if (st != FEM_OK) {
+        free_blocks(&p->blk);
+        free_pairs(&p->pscal);
+        free_pairs(&p->pvec);
+    }
     return st;
 }
 
@@ -623,9 +419,6 @@ static hipError_t launch_block_t(const fem_plan_data *p, const double *q, const 
 bool launch_block(const fem_plan_data *p, int op, const double *q, const double *w,
                   double *values, hipStream_t s, hipError_t *err) {
     if (!p->blk.ok || op == FEM_OP_ELAS) return false;
-    // FEMASM_KERNEL=rowgather selects the row-gather kernel (A/B comparisons)
-    const char *sel = getenv("FEMASM_KERNEL");
-    if (sel && std::string(sel) == "rowgather") return false;
     hipError_t e;
     if (p->d == 2) {
         switch (op) {
@@ -642,68 +435,6 @@ bool launch_block(const fem_plan_data *p, int op, const double *q, const double 
     }
     *err = e;
     return true;
-}
-
-
-template <int D, int kChunk>
-static hipError_t launch_pair_elas(const fem_plan_data *p, const double *q, double lam,
-                                   double mu, double *values, hipStream_t s) {
-    constexpr int NL = D + 1;
-    constexpr int NVE = (NL * D) | 1;
-    const PairPlan &P = p->pvec;
-    const BlockPlan &B = P.blk;
-    PairView pv;
-    pv.rp = p->rp;
-    pv.rows = B.rows;
-    pv.row_ptr = B.row_ptr;
-    pv.nodes = B.nodes;
-    pv.node_ptr = B.node_ptr;
-    pv.elem = reinterpret_cast<const uint2 *>(B.elem);
-    pv.elem_ptr = B.elem_ptr;
-    pv.wt = P.wt;
-    pv.task_cnt = P.task_cnt;
-    pv.task_ent = P.task_ent;
-    pv.hdr = P.hdr;
-    pv.ent = P.ent;
-    pv.ent_ptr = P.ent_ptr;
-    pv.q = q;
-    pv.values = values;
-    pv.nq = p->nq;
-    pv.max_nodes = B.max_nodes;
-    pv.max_rows = B.max_rows;
-    size_t o = size_t(D) * B.max_nodes * sizeof(double);
-    pv.off_ev = align16(o);
-    o = pv.off_ev + size_t(kChunk) * NVE * sizeof(double);
-    pv.off_row = align16(o);
-    o = pv.off_row + 2 * size_t(B.max_rows) * sizeof(int32_t);
-    pv.off_ent = align16(o);
-    o = pv.off_ent + size_t(P.max_ent) * sizeof(uint16_t);
-    const size_t lds = align16(o);
-    if (lds > 160 * 1024) return hipErrorNotSupported;   // caller falls back to row-gather
-    static thread_local bool attr_set = false;
-    if (!attr_set) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_pair_elas<D, kChunk>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        attr_set = true;
-    }
-    hipLaunchKernelGGL((k_pair_elas<D, kChunk>), dim3(unsigned(B.nb)), dim3(kPairWaves * 64), lds,
-                       s, pv, lam, mu, p->status);
-    return hipGetLastError();
-}
-
-bool launch_block(const fem_plan_data *p, int op, const double *q, const double *w,
-                  double *values, hipStream_t s, hipError_t *err, double lam, double mu) {
-    if (op == FEM_OP_ELAS) {
-        if (!p->pvec.ok) return false;
-        const char *sel = getenv("FEMASM_KERNEL");
-        if (sel && std::string(sel) == "rowgather") return false;
-        const hipError_t e = p->d == 2 ? launch_pair_elas<2, 256>(p, q, lam, mu, values, s)
-                                       : launch_pair_elas<3, 128>(p, q, lam, mu, values, s);
-        if (e == hipErrorNotSupported) return false;
-        *err = e;
-        return true;
-    }
-    return launch_block(p, op, q, w, values, s, err);
 }
 
 }  // namespace femasm

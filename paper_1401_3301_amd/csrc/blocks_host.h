@@ -223,7 +223,11 @@ inline BlockHost build_block_host(int d, int64_t nq, int64_t nme, const int32_t 
 // thread sums in registers.  For each pair the plan lists the block elements
 // that contain both vertices, in ascending element position, as 16-bit
 // entries: element position (bits 0-9), local index a of the row vertex
-// (bits 10-11) and b of the column vertex (bits 12-13); 0xffff pads.
+// (bits 10-11) and b of the column vertex (bits 12-13), or, with `tri`, the
+// index of (min(a,b), max(a,b)) in the packed upper triangle of the element
+// matrix (bits 10-13; symmetric operators).  Lists are padded
+// with entries naming position ne (the block's element count), a dummy
+// element whose scaled cofactors the kernel sets to zero.
 // Pairs are sorted by list length (longest first, stable) and cut into tasks
 // of 64 (one per wavefront lane); a task's entries are stored entry-major
 // (entry t of lane j at t*64 + j) up to the task's longest list.  Tasks are
@@ -244,7 +248,7 @@ struct PairHost {
 constexpr uint16_t kPairPad = 0xffffu;
 
 inline PairHost build_pair_host(const BlockHost &H, int d, const int32_t *rp, int kWaves,
-                                int kSlots, int nthreads) {
+                                int kSlots, int nthreads, bool tri = false) {
     PairHost P;
     const int NL = d + 1;
     const int nb = H.nb;
@@ -290,7 +294,12 @@ inline PairHost build_pair_host(const BlockHost &H, int d, const int32_t *rp, in
                     const uint32_t ep = x & 1023u, al = (x >> 10) & 3u;
                     for (int a = 0; a < NL; ++a) {
                         const int q = off[r] + int((x >> (12 + 5 * a)) & 31u);
-                        lst[fill[q]++] = uint16_t(ep | (al << 10) | (uint32_t(a) << 12));
+                        uint32_t code = (al << 10) | (uint32_t(a) << 12);
+                        if (tri) {
+                            const uint32_t lo = std::min<uint32_t>(al, a), hi = std::max<uint32_t>(al, a);
+                            code = (lo * NL - lo * (lo - 1) / 2 + (hi - lo)) << 10;
+                        }
+                        lst[fill[q]++] = uint16_t(ep | code);
                     }
                 }
             order.resize(np);
@@ -323,7 +332,7 @@ inline PairHost build_pair_host(const BlockHost &H, int d, const int32_t *rp, in
                     B.cnt.push_back(c);
                     B.eoff.push_back(int32_t(B.ent.size()));
                     const size_t e0 = B.ent.size();
-                    B.ent.resize(e0 + size_t(c) * 64, kPairPad);
+                    B.ent.resize(e0 + size_t(c) * 64, uint16_t(H.elem_ptr[b + 1] - H.elem_ptr[b]));
                     for (int j = 0; j < 64; ++j) {
                         const int k = t * 64 + j;
                         if (k >= np) {

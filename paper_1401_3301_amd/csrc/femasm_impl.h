@@ -13,9 +13,6 @@ namespace femasm {
 // Largest dynamic LDS block a numeric workgroup may request.
 constexpr size_t kLdsCap = 64 * 1024;
 
-// Launch geometry of the row-gather kernel for one dof multiplicity M
-// (1 for scalar operators, d for elasticity): rows per workgroup and the
-// LDS bytes the largest row tile needs.
 // LDS bytes of a row-gather tile of `rows` dof rows spanning `span` CSR values:
 // the accumulators, plus the elasticity epilogue tables (M > 1).
 inline size_t tile_lds_bytes(int M, int64_t span, int64_t rows) {
@@ -24,6 +21,9 @@ inline size_t tile_lds_bytes(int M, int64_t span, int64_t rows) {
     return b;
 }
 
+// Launch geometry of the row-gather kernel for one dof multiplicity M
+// (1 for scalar operators, d for elasticity): rows per workgroup and the
+// LDS bytes the largest row tile needs.
 struct RowLaunch {
     int rows_per_wg = 0;
     size_t lds_bytes = 0;
@@ -51,22 +51,23 @@ struct BlockPlan {
     int32_t *maxdeg = nullptr;    // [nb]
 };
 
-// Vertex-pair layout of the elasticity block kernel (see blocks_host.h):
-// the block's rows, touched vertices and elements as in BlockPlan (rec,
-// acc_off, nacc and maxdeg unused), plus the per-wavefront pair tasks.
+// Vertex-pair layout of the pair kernel (see blocks_host.h and pair.hip).
 struct PairPlan {
-    BlockPlan blk;
-    int32_t *wt = nullptr;        // [nb*(kPairWaves+1)] first task of each wavefront
-    int32_t *task_cnt = nullptr;  // entries per lane of each task
-    int64_t *task_ent = nullptr;  // first entry of each task
-    uint16_t *hdr = nullptr;      // [ntask*64] r | p << 7 per task lane
-    uint16_t *ent = nullptr;      // entry lists, entry-major within a task
-    int64_t *ent_ptr = nullptr;   // [nb+1]
-    int64_t max_ent = 0;
     bool ok = false;
+    int nb = 0;
+    int slots = 2;                // tasks of 64 pairs per wavefront at most
+    int max_rows = 0, max_nodes = 0, max_elems = 0;
+    int64_t max_nacc = 0, max_ent = 0;
+    int32_t *desc = nullptr;      // [nb*12] block descriptors (pair.hip)
+    int4 *rowinfo = nullptr;      // [rows] (rp[row], row length, local offset, 0)
+    int32_t *nodes = nullptr;     // touched vertices, grouped by block
+    uint16_t *elem = nullptr;     // 4 local vertex ids per block element
+    int32_t *task_cnt = nullptr;  // entries per lane of each task
+    int32_t *task_eoff = nullptr; // first entry of each task, relative to its block
+    uint16_t *hdr = nullptr;      // [ntask*64] r | p << 7 per task lane (0xffff: empty)
+    uint16_t *ent = nullptr;      // entry lists, entry-major within a task
 };
 constexpr int kPairWaves = 4;     // wavefronts per workgroup of the pair kernel
-constexpr int kPairSlots = 4;     // tasks per wavefront at most
 
 struct fem_plan_data {
     int d = 0;
@@ -86,7 +87,8 @@ struct fem_plan_data {
     std::vector<int32_t> h_rp;    // host copy of rp (launch geometry)
     RowLaunch launch[4];          // indexed by M
     BlockPlan blk;                // block-kernel layout (scalar operators)
-    PairPlan pvec;                // pair-kernel layout (elasticity)
+    PairPlan pscal;               // pair-kernel layout, scalar operators
+    PairPlan pvec;                // pair-kernel layout, elasticity
 };
 
 }  // namespace femasm
@@ -101,6 +103,13 @@ fem_status upload_blocks(fem_plan_data *p, int d, int64_t nq, int64_t nme, const
                          const int32_t *inc_k);
 void free_blocks(BlockPlan *b);
 void free_pairs(PairPlan *p);
+fem_status upload_pairs(PairPlan &P, int R, int slots, bool tri, int d, int64_t nq, int64_t nme,
+                        const int32_t *me, const int32_t *rp, const int32_t *ci, const int64_t *ip,
+                        const int32_t *inc_k);
+// Launches the pair kernel; returns false (nothing launched) when the plan
+// has no pair layout for this operator.
+bool launch_pair(const fem_plan_data *p, int op, const double *q, const double *w, double lam,
+                 double mu, double *values, hipStream_t s, hipError_t *err);
 // Launches the block kernel for a scalar operator; returns false (nothing
 // launched) when the plan has no block layout.
 bool launch_block(const fem_plan_data *p, int op, const double *q, const double *w,

@@ -1,4 +1,6 @@
 // Numeric phase and the small helper kernels of a plan.
+#include <cstring>
+
 #include "femasm_impl.h"
 #include "rowgather.h"
 
@@ -148,7 +150,16 @@ extern "C" fem_status fem_assemble_numeric(fem_plan plan, int32_t op, const doub
     if (op == FEM_OP_MASS_W && plan->nnz > 0 && !w) return FEM_ERR_ARG;
     if (plan->launch[M].rows_per_wg == 0) return FEM_ERR_OVERFLOW;
     hipError_t e = hipSuccess;
-    if (plan->nq > 0 && launch_block(plan, op, q, w, values, stream, &e, lambda, mu))
+    // FEMASM_KERNEL=pair|block|rowgather forces one kernel family (A/B
+    // comparisons); by default the pair kernel, else the record-block kernel
+    // (scalar operators), else the row-gather kernel.
+    const char *sel = getenv("FEMASM_KERNEL");
+    const bool any = !sel || !*sel;
+    if (plan->nq > 0 && (any || !strcmp(sel, "pair")) &&
+        launch_pair(plan, op, q, w, lambda, mu, values, stream, &e))
+        return hip_status(e);
+    if (plan->nq > 0 && (any || !strcmp(sel, "block")) &&
+        launch_block(plan, op, q, w, values, stream, &e))
         return hip_status(e);
     const MeshView mv = plan_view(plan, q, w, values);
     if (plan->d == 2) {

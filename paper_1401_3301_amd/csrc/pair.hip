@@ -1,0 +1,611 @@
+// Pair kernel: every entry of the scalar CSR pattern (a "vertex pair" (i, j))
+// is summed by one thread, in registers, over the elements that contain both
+// vertices (the duplicate sum of the `sparse` step, Section 3).
+//
+// Work is organised in vertex blocks (blocks_host.h): the block's rows, every
+// element around them, and per pair the list of those elements in ascending
+// caller element number.  For one block a workgroup
+//   1. computes each block element's values once (closed forms of Sections
+//      4.1, 4.2 and 5.1, element.h) into LDS, plus an all-zero dummy element
+//      that pads the pair lists;
+//   2. lets every lane walk its pairs' lists and accumulate; all lanes of a
+//      64-pair task run the same number of entries (no divergence);
+//   3. places the finished values into an LDS image of the block's CSR value
+//      range and writes it out with coalesced stores.
+// Each pair's sum is taken in ascending element number with the same
+// expressions as the row-gather kernel, so both give identical bits.
+//
+// The kernel is persistent: a fixed grid sized to the occupancy walks the
+// blocks (each XCD a contiguous range, for L2 locality).  While one block is
+// summed, the next block's lists and coordinates are already in flight into
+// registers, and the vertex ids of the block after it as well, so the HBM
+// latency of the dependent loads (block descriptor -> vertex ids ->
+// coordinates) is hidden behind the previous block's work.
+#include <algorithm>
+#include <cstring>
+#include <thread>
+#include <vector>
+
+#include "blocks_host.h"
+#include "element.h"
+#include "femasm_impl.h"
+
+#pragma clang fp contract(off)
+
+namespace femasm {
+
+namespace {
+
+constexpr int kPairWG = kPairWaves * 64;
+constexpr int kEntSlots = 4;    // uint4 entry slots per thread: <= 8192 entries per block
+constexpr int kNodeSlots = 2;   // touched vertices per thread: <= 512 per block
+constexpr int kElemSlots = 4;   // elements per thread: <= 1023 (+ dummy) per block
+
+struct PairView {
+    const int32_t *desc;
+    const int4 *rowinfo;
+    const int32_t *nodes;
+    const uint2 *elem;
+    const int32_t *task_cnt;
+    const int32_t *task_eoff;
+    const uint16_t *hdr;
+    const uint16_t *ent;
+    const double *q;
+    const double *w;
+    double *values;
+    int64_t nq;
+    int32_t nb, max_nodes;
+    uint32_t off_w, off_row, off_rowof, off_ev, off_ent;
+};
+
+// Per-element values kept in LDS (odd slot size: consecutive elements fall on
+// different banks).  ELAS: scaled cofactors ch_a; the scalar operators: the
+// packed upper triangle of the element matrix, entry (a, b), a <= b, at
+// a*(d+1) - a*(a-1)/2 + (b-a) (the pair entries carry that index).
+template <int D, int OP>
+struct PairOp {
+    static constexpr int NL = D + 1;
+    static constexpr int NV0 = OP == FEM_OP_ELAS ? NL * D : NL * (NL + 1) / 2;
+    static constexpr int NV = NV0 | 1;
+    static constexpr int M = OP == FEM_OP_ELAS ? D : 1;
+};
+
+template <int NL>
+__device__ __forceinline__ constexpr int tri_index(int a, int b) {
+    return a * NL - a * (a - 1) / 2 + (b - a);
+}
+
+// Block descriptor, kDescInts ints per block: first row, rows, first touched
+// vertex, touched vertices, first element, elements, CSR entries of the rows,
+// first task, entry count / 8, task starts of wavefronts 1..4 relative to the
+// first task (5 bits each), first entry (64 bits, low word first).
+constexpr int kDescInts = 12;
+struct Desc {
+    int r0, nr, n0, nn, e0, ne, nacc, t0, nent8;
+    uint32_t wp;
+    int64_t eb;
+};
+
+__device__ __forceinline__ Desc load_desc(const PairView &pv, int b) {
+    Desc d;
+    const int32_t *x = pv.desc + int64_t(b) * kDescInts;
+    d.r0 = x[0];
+    d.nr = x[1];
+    d.n0 = x[2];
+    d.nn = x[3];
+    d.e0 = x[4];
+    d.ne = x[5];
+    d.nacc = x[6];
+    d.t0 = x[7];
+    d.nent8 = x[8];
+    d.wp = uint32_t(x[9]);
+    d.eb = int64_t(uint32_t(x[10])) | (int64_t(x[11]) << 32);
+    return d;
+}
+
+// First task of wavefront w (0..kPairWaves) of a block, relative to its t0.
+__device__ __forceinline__ int wave_task(uint32_t wp, int w) {
+    return w == 0 ? 0 : int((wp >> (5 * (w - 1))) & 31u);
+}
+
+template <int D, int OP>
+__device__ __forceinline__ void element_values(const double (&P)[D + 1][D], const double *wl,
+                                               double *out, int &bad) {
+    constexpr int NL = D + 1;
+    if constexpr (OP == FEM_OP_MASS || OP == FEM_OP_MASS_W) {
+        // the same operations as the row-gather kernel: (1+delta) k, and
+        // f (w^s + (w_a + w_b)) with f = (1+delta) k
+        const double det = elem_det(P);
+        const bool deg = det == 0.0;
+        if (deg) bad = 1;
+        const double ad = fabs(det);
+        if constexpr (OP == FEM_OP_MASS) {
+            const double k = ad / Fact<D>::mass_den;
+#pragma unroll
+            for (int a = 0; a < NL; ++a)
+#pragma unroll
+                for (int b = a; b < NL; ++b)
+                    out[tri_index<NL>(a, b)] = deg ? 0.0 : (a == b ? 2.0 * k : k);
+        } else {
+            double ws = wl[0];
+#pragma unroll
+            for (int b = 1; b < NL; ++b) ws += wl[b];
+            const double k = ad / Fact<D>::massw_den;
+#pragma unroll
+            for (int a = 0; a < NL; ++a)
+#pragma unroll
+                for (int b = a; b < NL; ++b) {
+                    const double f = a == b ? 2.0 * k : k;
+                    out[tri_index<NL>(a, b)] = deg ? 0.0 : f * (ws + (wl[a] + wl[b]));
+                }
+        }
+    } else {
+        Elem<D> E;
+        elem_geometry(P, E);
+        const bool deg = E.det == 0.0;
+        if (deg) bad = 1;
+        if constexpr (OP == FEM_OP_STIFF) {
+            const double inv = deg ? 0.0 : 1.0 / (Fact<D>::dfact * fabs(E.det));
+#pragma unroll
+            for (int a = 0; a < NL; ++a)
+#pragma unroll
+                for (int b = a; b < NL; ++b)
+                    out[tri_index<NL>(a, b)] = deg ? 0.0 : cdot<D>(E.c[a], E.c[b]) * inv;
+        } else {
+            const double sc = deg ? 0.0 : elas_scale<D>(E.det);
+#pragma unroll
+            for (int a = 0; a < NL; ++a)
+#pragma unroll
+                for (int x = 0; x < D; ++x) out[a * D + x] = E.c[a][x] * sc;
+        }
+    }
+}
+
+template <int D, int OP, int S>
+__global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, double mu,
+                                                  int32_t *status) {
+    using O = PairOp<D, OP>;
+    constexpr int NL = D + 1;
+    constexpr int NV = O::NV;
+    constexpr int M = O::M;
+    constexpr int M2 = M * M;
+    constexpr bool kW = OP == FEM_OP_MASS_W;
+    extern __shared__ __align__(16) unsigned char smem[];
+    double *crd = reinterpret_cast<double *>(smem);
+    double *wv = reinterpret_cast<double *>(smem + pv.off_w);
+    int4 *rinf = reinterpret_cast<int4 *>(smem + pv.off_row);
+    uint8_t *rowof = smem + pv.off_rowof;
+    double *ev = reinterpret_cast<double *>(smem + pv.off_ev);
+    uint16_t *ent = reinterpret_cast<uint16_t *>(smem + pv.off_ent);
+    double *outb = ev;   // the output image reuses the element and entry buffers
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int MN = pv.max_nodes;
+    const int64_t nq = pv.nq;
+    // blocks of this workgroup: XCD x (workgroups x, x+8, ...) owns a
+    // contiguous range of blocks, walked with stride J
+    const int xcd = blockIdx.x & 7, jj = blockIdx.x >> 3, J = gridDim.x >> 3;
+    const int per = pv.nb >> 3, rem = pv.nb & 7;
+    const int xs = xcd * per + (xcd < rem ? xcd : rem);
+    const int xn = per + (xcd < rem ? 1 : 0);
+    auto block_at = [&](int k) { return jj + k * J < xn ? xs + jj + k * J : -1; };
+
+    // ---- prefetch registers
+    // entry slots as named registers (an indexed array ends up in scratch)
+    uint4 rent0 = make_uint4(0, 0, 0, 0), rent1 = rent0, rent2 = rent0, rent3 = rent0;
+    static_assert(kEntSlots == 4, "four named entry slots");
+    uint2 rel[kElemSlots];
+    int4 rrow = make_int4(0, 0, 0, 0);
+    uint32_t rhd[S];
+    int rcnt[S], reoff[S], rns = 0;
+    double rq[kNodeSlots][D];
+    double rw[kNodeSlots];
+    int nid[kNodeSlots];
+
+    auto load_nodes = [&](const Desc &d) {
+#pragma unroll
+        for (int u = 0; u < kNodeSlots; ++u) {
+            const int n = u * kPairWG + tid;
+            nid[u] = n < d.nn ? pv.nodes[d.n0 + n] : 0;
+        }
+    };
+    auto issue_coords = [&](const Desc &d) {
+#pragma unroll
+        for (int u = 0; u < kNodeSlots; ++u) {
+            if (u * kPairWG + tid < d.nn) {
+#pragma unroll
+                for (int x = 0; x < D; ++x) rq[u][x] = pv.q[x * nq + nid[u]];
+                if constexpr (kW) rw[u] = pv.w[nid[u]];
+            }
+        }
+    };
+    auto issue_raw = [&](const Desc &d) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(pv.ent + d.eb);
+        const int tw0 = d.t0 + wave_task(d.wp, wave);
+        rns = d.t0 + wave_task(d.wp, wave + 1) - tw0;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            rcnt[s] = 0;
+            reoff[s] = 0;
+            rhd[s] = kPairPad;
+            if (s < rns) {
+                rcnt[s] = pv.task_cnt[tw0 + s];
+                reoff[s] = pv.task_eoff[tw0 + s];
+                rhd[s] = pv.hdr[int64_t(tw0 + s) * 64 + lane];
+            }
+        }
+        if (tid < d.nent8) rent0 = src[tid];
+        if (kPairWG + tid < d.nent8) rent1 = src[kPairWG + tid];
+        if (2 * kPairWG + tid < d.nent8) rent2 = src[2 * kPairWG + tid];
+        if (3 * kPairWG + tid < d.nent8) rent3 = src[3 * kPairWG + tid];
+#pragma unroll
+        for (int u = 0; u < kElemSlots; ++u) {
+            const int e = u * kPairWG + tid;
+            rel[u] = e < d.ne ? pv.elem[d.e0 + e] : make_uint2(0u, 0u);
+        }
+        if (tid < d.nr) rrow = pv.rowinfo[d.r0 + tid];
+    };
+
+    int bc = block_at(0);
+    if (bc < 0) return;
+    Desc dc = load_desc(pv, bc);
+    load_nodes(dc);
+    issue_coords(dc);
+    issue_raw(dc);
+    int bn = block_at(1);
+    Desc dn = dc;
+    if (bn >= 0) {
+        dn = load_desc(pv, bn);
+        load_nodes(dn);
+    }
+
+    Desc dp = dc;
+    bool have_prev = false;
+    int bad = 0;
+    for (int k = 0;; ++k) {
+        // L1: coordinates of the current block into LDS
+#pragma unroll
+        for (int u = 0; u < kNodeSlots; ++u) {
+            const int n = u * kPairWG + tid;
+            if (n < dc.nn) {
+#pragma unroll
+                for (int x = 0; x < D; ++x) crd[x * MN + n] = rq[u][x];
+                if constexpr (kW) wv[n] = rw[u];
+            }
+        }
+        // L2: coordinates of the next block in flight
+        if (bn >= 0) issue_coords(dn);
+        // L3: output image of the previous block to HBM
+        if (have_prev) {
+            for (int kk = tid; kk < M2 * dp.nacc; kk += kPairWG) {
+                const int4 ri = rinf[rowof[kk / M2]];
+                pv.values[int64_t(M2) * ri.x + (kk - M2 * ri.z)] = outb[kk];
+            }
+        }
+        __syncthreads();
+        // L5: entry lists and rows of the current block into LDS
+        {
+            uint4 *e4 = reinterpret_cast<uint4 *>(ent);
+            if (tid < dc.nent8) e4[tid] = rent0;
+            if (kPairWG + tid < dc.nent8) e4[kPairWG + tid] = rent1;
+            if (2 * kPairWG + tid < dc.nent8) e4[2 * kPairWG + tid] = rent2;
+            if (3 * kPairWG + tid < dc.nent8) e4[3 * kPairWG + tid] = rent3;
+        }
+        if (tid < dc.nr) {
+            rinf[tid] = rrow;
+            for (int kk = 0; kk < rrow.y; ++kk) rowof[rrow.z + kk] = uint8_t(tid);
+        }
+        uint32_t hd[S];
+        int cnt[S], eoff[S];
+        const int ns = rns;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            hd[s] = rhd[s];
+            cnt[s] = rcnt[s];
+            eoff[s] = reoff[s];
+        }
+        uint2 el[kElemSlots];
+#pragma unroll
+        for (int u = 0; u < kElemSlots; ++u) el[u] = rel[u];
+        __syncthreads();
+        // L7: element phase
+#pragma unroll
+        for (int u = 0; u < kElemSlots; ++u) {
+            const int e = u * kPairWG + tid;
+            if (e < dc.ne) {
+                const uint2 vv = el[u];
+                const int v[4] = {int(vv.x & 0xffffu), int(vv.x >> 16), int(vv.y & 0xffffu),
+                                  int(vv.y >> 16)};
+                double P[NL][D];
+                double wl[NL];
+#pragma unroll
+                for (int a = 0; a < NL; ++a) {
+#pragma unroll
+                    for (int x = 0; x < D; ++x) P[a][x] = crd[x * MN + v[a]];
+                    if constexpr (kW) wl[a] = wv[v[a]];
+                }
+                element_values<D, OP>(P, wl, ev + e * NV, bad);
+            } else if (e == dc.ne) {
+#pragma unroll
+                for (int t = 0; t < NV; ++t) ev[e * NV + t] = 0.0;
+            }
+        }
+        // L8: lists of the next block, vertex ids of the one after it
+        const int bnn = block_at(k + 2);
+        Desc dnn = dn;
+        if (bn >= 0) issue_raw(dn);
+        if (bnn >= 0) {
+            dnn = load_desc(pv, bnn);
+            load_nodes(dnn);
+        }
+        __syncthreads();
+        // L10: pair sums
+        double X[S][M2];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+#pragma unroll
+            for (int t = 0; t < M2; ++t) X[s][t] = 0.0;
+            if (s < ns) {
+                const uint16_t *lst = ent + eoff[s] + lane;
+                const int C = cnt[s];
+                uint32_t x = lst[0];
+                uint32_t xn = C > 1 ? lst[64] : x;
+                for (int t = 0; t < C; ++t) {
+                    const uint32_t xnn = t + 2 < C ? lst[(t + 2) * 64] : xn;
+                    const double *Ee = ev + int(x & 1023u) * NV;
+                    if constexpr (OP == FEM_OP_ELAS) {
+                        const int a = int((x >> 10) & 3u), b = int((x >> 12) & 3u);
+                        double A[D], B[D];
+#pragma unroll
+                        for (int c = 0; c < D; ++c) {
+                            A[c] = Ee[a * D + c];
+                            B[c] = Ee[b * D + c];
+                        }
+#pragma unroll
+                        for (int l = 0; l < D; ++l)
+#pragma unroll
+                            for (int n = 0; n < D; ++n)
+                                X[s][l * D + n] = fma(A[l], B[n], X[s][l * D + n]);
+                    } else {
+                        X[s][0] += Ee[(x >> 10) & 15u];
+                    }
+                    x = xn;
+                    xn = xnn;
+                }
+            }
+        }
+        __syncthreads();
+        // L12: output image of the current block
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            if (s < ns && hd[s] != kPairPad) {
+                const int r = int(hd[s] & 127u), p = int(hd[s] >> 7);
+                const int4 ri = rinf[r];
+                double *o = outb + M2 * ri.z + M * p;
+                if constexpr (OP == FEM_OP_ELAS) {
+                    double tr = X[s][0];
+#pragma unroll
+                    for (int m = 1; m < D; ++m) tr += X[s][m * D + m];
+#pragma unroll
+                    for (int l = 0; l < D; ++l)
+#pragma unroll
+                        for (int n = 0; n < D; ++n)
+                            o[l * D * ri.y + n] = elas_combine(X[s][l * D + n], X[s][n * D + l],
+                                                               tr, l == n, lam, mu);
+                } else {
+                    o[0] = X[s][0];
+                }
+            }
+        }
+        __syncthreads();
+        dp = dc;
+        have_prev = true;
+        if (bn < 0) break;
+        bc = bn;
+        dc = dn;
+        bn = bnn;
+        dn = dnn;
+    }
+    for (int kk = tid; kk < M2 * dp.nacc; kk += kPairWG) {
+        const int4 ri = rinf[rowof[kk / M2]];
+        pv.values[int64_t(M2) * ri.x + (kk - M2 * ri.z)] = outb[kk];
+    }
+    const unsigned long long any = __ballot(bad != 0);
+    if (any != 0ull && (threadIdx.x & 63) == __ffsll((long long)any) - 1) atomicOr(status, bad);
+}
+
+template <class T>
+fem_status up(T **dst, const std::vector<T> &src) {
+    *dst = nullptr;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(dst), sizeof(T) * std::max<size_t>(1, src.size()));
+    if (e == hipSuccess && !src.empty())
+        e = hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
+    return hip_status(e);
+}
+
+uint32_t align16(size_t x) { return uint32_t((x + 15) & ~size_t(15)); }
+
+struct PairLds {
+    PairView pv;
+    size_t bytes;
+};
+
+template <int D, int OP>
+PairLds pair_lds(const PairPlan &P) {
+    using O = PairOp<D, OP>;
+    PairView pv{};
+    size_t o = size_t(D) * P.max_nodes * sizeof(double);
+    pv.off_w = align16(o);
+    if (OP == FEM_OP_MASS_W) o = pv.off_w + size_t(P.max_nodes) * sizeof(double);
+    pv.off_row = align16(o);
+    o = pv.off_row + size_t(P.max_rows) * sizeof(int4);
+    pv.off_rowof = align16(o);
+    o = pv.off_rowof + size_t(P.max_nacc);
+    pv.off_ev = align16(o);
+    o = pv.off_ev + size_t(P.max_elems + 1) * O::NV * sizeof(double);
+    pv.off_ent = align16(o);
+    o = pv.off_ent + size_t(P.max_ent) * sizeof(uint16_t);
+    o = std::max(o, pv.off_ev + size_t(O::M) * O::M * P.max_nacc * sizeof(double));
+    return PairLds{pv, align16(o)};
+}
+
+template <int D, int OP, int S>
+hipError_t launch_pair_t(const fem_plan_data *p, const PairPlan &P, const double *q,
+                         const double *w, double lam, double mu, double *values, hipStream_t s) {
+    PairLds L = pair_lds<D, OP>(P);
+    if (L.bytes > 160 * 1024) return hipErrorNotSupported;   // caller falls back
+    PairView pv = L.pv;
+    pv.desc = P.desc;
+    pv.rowinfo = P.rowinfo;
+    pv.nodes = P.nodes;
+    pv.elem = reinterpret_cast<const uint2 *>(P.elem);
+    pv.task_cnt = P.task_cnt;
+    pv.task_eoff = P.task_eoff;
+    pv.hdr = P.hdr;
+    pv.ent = P.ent;
+    pv.q = q;
+    pv.w = w;
+    pv.values = values;
+    pv.nq = p->nq;
+    pv.nb = P.nb;
+    pv.max_nodes = P.max_nodes;
+    const void *fn = reinterpret_cast<const void *>(&k_pair<D, OP, S>);
+    // persistent grid: resident workgroups per CU x CUs, a multiple of the 8 XCDs
+    static thread_local int cached[2][4][3] = {};
+    static thread_local size_t cached_lds[2][4][3] = {};
+    const int si = S == 1 ? 0 : (S == 2 ? 1 : 2);
+    int &occ = cached[D - 2][OP][si];
+    if (occ == 0 || cached_lds[D - 2][OP][si] != L.bytes) {
+        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, kPairWG, L.bytes) != hipSuccess ||
+            n < 1)
+            n = 1;
+        occ = n;
+        cached_lds[D - 2][OP][si] = L.bytes;
+    }
+    int dev = 0, cus = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (cus < 8) cus = 8;
+    int64_t grid = int64_t(occ) * cus / 8 * 8;
+    const int64_t need = (int64_t(P.nb) + 7) / 8 * 8;
+    grid = std::max<int64_t>(8, std::min(grid, need));
+    hipLaunchKernelGGL((k_pair<D, OP, S>), dim3(unsigned(grid)), dim3(kPairWG), L.bytes, s, pv,
+                       lam, mu, p->status);
+    return hipGetLastError();
+}
+
+template <int D, int OP>
+hipError_t launch_pair_s(const fem_plan_data *p, const PairPlan &P, const double *q,
+                         const double *w, double lam, double mu, double *values, hipStream_t s) {
+    if (P.slots == 4) return launch_pair_t<D, OP, 4>(p, P, q, w, lam, mu, values, s);
+    if (P.slots == 1) return launch_pair_t<D, OP, 1>(p, P, q, w, lam, mu, values, s);
+    return launch_pair_t<D, OP, 2>(p, P, q, w, lam, mu, values, s);
+}
+
+template <int D>
+hipError_t launch_pair_d(const fem_plan_data *p, int op, const double *q, const double *w,
+                         double lam, double mu, double *values, hipStream_t s) {
+    switch (op) {
+        case FEM_OP_MASS: return launch_pair_s<D, FEM_OP_MASS>(p, p->pscal, q, w, lam, mu, values, s);
+        case FEM_OP_MASS_W:
+            return launch_pair_s<D, FEM_OP_MASS_W>(p, p->pscal, q, w, lam, mu, values, s);
+        case FEM_OP_STIFF:
+            return launch_pair_s<D, FEM_OP_STIFF>(p, p->pscal, q, w, lam, mu, values, s);
+        default: return launch_pair_s<D, FEM_OP_ELAS>(p, p->pvec, q, w, lam, mu, values, s);
+    }
+}
+
+}  // namespace
+
+void free_pairs(PairPlan *p) {
+    void *ptrs[] = {p->desc, p->rowinfo, p->nodes, p->elem, p->task_cnt, p->task_eoff, p->hdr,
+                    p->ent};
+    for (void *x : ptrs)
+        if (x) (void)hipFree(x);
+    *p = PairPlan();
+}
+
+fem_status upload_pairs(PairPlan &P, int R, int slots, bool tri, int d, int64_t nq, int64_t nme,
+                        const int32_t *me, const int32_t *rp, const int32_t *ci, const int64_t *ip,
+                        const int32_t *inc_k) {
+    P = PairPlan();
+    const int64_t max_pairs = int64_t(64) * kPairWaves * slots;
+    BlockHost H = build_block_host(d, nq, nme, me, rp, ci, ip, inc_k, std::min(R, 128), 16,
+                                   max_pairs);
+    if (!H.ok || H.nb == 0) return FEM_OK;   // row-gather kernel only
+    PairHost PH = build_pair_host(H, d, rp, kPairWaves, slots, 16, tri);
+    if (!PH.ok || PH.max_ent > int64_t(kEntSlots) * kPairWG * 8 ||
+        H.max_nodes > kNodeSlots * kPairWG || H.max_elems + 1 > kElemSlots * kPairWG)
+        return FEM_OK;
+    const int nb = H.nb;
+    std::vector<int32_t> desc(size_t(nb) * kDescInts), task_eoff(PH.task_ent.size());
+    std::vector<int4> rowinfo(H.rows.size());
+    int64_t max_nacc = 0;
+    for (int b = 0; b < nb; ++b) {
+        int32_t o = 0;
+        for (int r = H.row_ptr[b]; r < H.row_ptr[b + 1]; ++r) {
+            const int32_t row = H.rows[r];
+            const int32_t len = rp[row + 1] - rp[row];
+            rowinfo[r] = make_int4(rp[row], len, o, 0);
+            o += len;
+        }
+        max_nacc = std::max<int64_t>(max_nacc, o);
+        const int32_t t0 = PH.wt[size_t(b) * (kPairWaves + 1)];
+        int32_t *x = desc.data() + size_t(b) * kDescInts;
+        x[0] = H.row_ptr[b];
+        x[1] = H.row_ptr[b + 1] - H.row_ptr[b];
+        x[2] = H.node_ptr[b];
+        x[3] = H.node_ptr[b + 1] - H.node_ptr[b];
+        x[4] = H.elem_ptr[b];
+        x[5] = H.elem_ptr[b + 1] - H.elem_ptr[b];
+        x[6] = o;
+        x[7] = t0;
+        uint32_t wp = 0;
+        for (int w = 1; w <= kPairWaves; ++w)
+            wp |= uint32_t(PH.wt[size_t(b) * (kPairWaves + 1) + w] - t0) << (5 * (w - 1));
+        x[8] = int32_t((PH.ent_ptr[b + 1] - PH.ent_ptr[b]) / 8);
+        x[9] = int32_t(wp);
+        x[10] = int32_t(uint32_t(uint64_t(PH.ent_ptr[b]) & 0xffffffffu));
+        x[11] = int32_t(uint64_t(PH.ent_ptr[b]) >> 32);
+        for (int t = t0; t < PH.wt[size_t(b) * (kPairWaves + 1) + kPairWaves]; ++t)
+            task_eoff[t] = int32_t(PH.task_ent[t] - PH.ent_ptr[b]);
+    }
+    fem_status st = FEM_OK;
+    if (st == FEM_OK) st = up(&P.desc, desc);
+    if (st == FEM_OK) st = up(&P.rowinfo, rowinfo);
+    if (st == FEM_OK) st = up(&P.nodes, H.nodes);
+    if (st == FEM_OK) st = up(&P.elem, H.elem);
+    if (st == FEM_OK) st = up(&P.task_cnt, PH.task_cnt);
+    if (st == FEM_OK) st = up(&P.task_eoff, task_eoff);
+    if (st == FEM_OK) st = up(&P.hdr, PH.hdr);
+    if (st == FEM_OK) st = up(&P.ent, PH.ent);
+    if (st != FEM_OK) {
+        free_pairs(&P);
+        return st;
+    }
+    P.nb = nb;
+    P.slots = slots;
+    P.max_rows = H.max_rows;
+    P.max_nodes = H.max_nodes;
+    P.max_elems = H.max_elems;
+    P.max_nacc = max_nacc;
+    P.max_ent = PH.max_ent;
+    P.ok = true;
+    return FEM_OK;
+}
+
+bool launch_pair(const fem_plan_data *p, int op, const double *q, const double *w, double lam,
+                 double mu, double *values, hipStream_t s, hipError_t *err) {
+    const PairPlan &P = op == FEM_OP_ELAS ? p->pvec : p->pscal;
+    if (!P.ok) return false;
+    const hipError_t e = p->d == 2 ? launch_pair_d<2>(p, op, q, w, lam, mu, values, s)
+                                   : launch_pair_d<3>(p, op, q, w, lam, mu, values, s);
+    if (e == hipErrorNotSupported) return false;
+    *err = e;
+    return true;
+}
+
+}  // namespace femasm
