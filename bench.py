@@ -27,9 +27,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-KERNEL_SOURCES = ["paper_1401_3301_amd/csrc/block.hip", "paper_1401_3301_amd/csrc/blocks_host.h",
-                  "paper_1401_3301_amd/csrc/element.h", "paper_1401_3301_amd/csrc/rowgather.h"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_cube128_stiff.json")
+KERNEL_SOURCES = ["paper_1401_3301_amd/csrc/pair.hip", "paper_1401_3301_amd/csrc/blocks_host.h",
+                  "paper_1401_3301_amd/csrc/element.h", "paper_1401_3301_amd/csrc/block.hip"]
+KERNEL_NAME = {"STIFF": "k_pair<3,STIFF>", "ELAS": "k_pair<3,ELAS>"}
+
+
+def traffic_file(op: str) -> str:
+    return os.path.join(ROOT, "profiles", f"traffic_cube128_{op.lower()}.json")
 
 
 def kernel_sha() -> str:
@@ -207,13 +211,13 @@ def main():
           f"{achieved:.0f} GB/s algorithmic", file=sys.stderr, flush=True)
 
     traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        tr = json.load(open(TRAFFIC_FILE))
-        if tr.get("kernel_sha") == kernel_sha() and tr.get("n") == args.n and args.op == "STIFF":
+    if os.path.exists(traffic_file(args.op)):
+        tr = json.load(open(traffic_file(args.op)))
+        if tr.get("kernel_sha") == kernel_sha() and tr.get("n") == args.n and tr.get("op") == args.op:
             traffic = tr.get("traffic_bytes")
 
     opname = {"STIFF": "stiffness", "ELAS": "elasticity"}[args.op]
-    kernel = {"STIFF": "k_block<3,STIFF>", "ELAS": "k_pair_elas<3>"}[args.op]
+    kernel = KERNEL_NAME[args.op]
     line = {
         "metric": f"P1 elements assembled/s into CSR (3D {opname}, FP64) + achieved HBM GB/s",
         "value": value, "unit": "elements/s", "n_gpus": 1, "steps": args.steps,

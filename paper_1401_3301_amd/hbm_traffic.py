@@ -1,7 +1,7 @@
 """Turn rocprofv3 FETCH_SIZE / WRITE_SIZE counter files into HBM bytes.
 
     python -m paper_1401_3301_amd.hbm_traffic <fetch_dir> <write_dir> \\
-        <copy_fetch_dir> <copy_write_dir> <kernel_substring> <out.json>
+        <copy_fetch_dir> <copy_write_dir> <kernel_substring> <op> <out.json>
 
 Each directory is a rocprofv3 ``--pmc ... --output-format csv`` output.
 FETCH_SIZE and WRITE_SIZE are read in KiB per dispatch, averaged over the
@@ -34,7 +34,7 @@ def counter_mean(d: str, counter: str, kernel_sub: str) -> float:
 
 
 def main(argv):
-    fd, wd, cfd, cwd, ksub, out = argv[1:7]
+    fd, wd, cfd, cwd, ksub, op, out = argv[1:8]
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     from bench import kernel_sha
 
@@ -46,7 +46,7 @@ def main(argv):
     f_scale = copy_bytes / (cf_kib * 1024.0)
     w_scale = copy_bytes / (cw_kib * 1024.0)
     res = {
-        "kernel": ksub, "kernel_sha": kernel_sha(), "n": 128,
+        "kernel": ksub, "op": op, "kernel_sha": kernel_sha(), "n": 128,
         "fetch_kib": f_kib, "write_kib": w_kib,
         "copy_fetch_kib": cf_kib, "copy_write_kib": cw_kib,
         "fetch_scale": f_scale, "write_scale": w_scale,

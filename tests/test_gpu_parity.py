@@ -95,19 +95,21 @@ def test_deterministic_and_symmetric(op):
 
 @pytest.mark.parametrize("op", OPS)
 @pytest.mark.parametrize("name", ["square64", "cube9_perm", "cube14"])
-def test_block_and_rowgather_kernels_agree(name, op, monkeypatch):
-    """The vertex-block kernels (scalar operators), the vertex-pair kernel
-    (elasticity) and the row-gather kernel sum every entry in the same order
-    with the same expressions: their values agree bit for bit."""
+def test_kernel_families_agree_bitwise(name, op, monkeypatch):
+    """The vertex-pair kernel, the record-block kernel (scalar operators) and
+    the row-gather kernel sum every entry in the same order with the same
+    expressions: their values agree bit for bit (and with the default)."""
     mesh = SMALL[name]()
     w = mg.lognormal_field(mesh.nq, 3)
     me, q, wt = _gpu(mesh, w)
     plan = femasm.Plan(me, mesh.nq)
-    v_blk = plan.numeric(op, q, wt, 1.3, 0.7).clone()
-    monkeypatch.setenv("FEMASM_KERNEL", "rowgather")
-    v_row = plan.numeric(op, q, wt, 1.3, 0.7).clone()
-    torch.cuda.synchronize()
-    assert torch.equal(v_blk, v_row)
+    v_def = plan.numeric(op, q, wt, 1.3, 0.7).clone()
+    kernels = ["pair", "rowgather"] + ([] if op == "ELAS" else ["block"])
+    for kern in kernels:
+        monkeypatch.setenv("FEMASM_KERNEL", kern)
+        v = plan.numeric(op, q, wt, 1.3, 0.7).clone()
+        torch.cuda.synchronize()
+        assert torch.equal(v, v_def), f"{kern} differs from the default kernel"
 
 
 def test_slot_map_consistency():
