@@ -234,11 +234,16 @@ inline BlockHost build_block_host(int d, int64_t nq, int64_t nme, const int32_t 
 // dealt to kWaves wavefronts, at most kSlots each, longest-first onto the
 // least-loaded wavefront, and stored wavefront by wavefront.  hdr holds, per
 // task lane, r | p << 7 (0xffff for an empty lane).
+// With `dedup`, a pair (r, p) whose column vertex is row r2 > r of the same
+// block also stands for its mirror (r2, p2) (same elements, transposed
+// block, equal for symmetric operators); the mirror is not listed and hdr2
+// holds r2 | p2 << 7 for its writer (0xffff otherwise).
 struct PairHost {
     std::vector<int32_t> wt;        // [nb*(kWaves+1)] first task of each wavefront (global)
     std::vector<int32_t> task_cnt;  // entries per lane of each task
     std::vector<int64_t> task_ent;  // first entry of each task (global)
     std::vector<uint16_t> hdr;      // [ntask*64]
+    std::vector<uint16_t> hdr2;     // [ntask*64] mirror target (dedup)
     std::vector<uint16_t> ent;
     std::vector<int64_t> ent_ptr;   // [nb+1]
     int64_t max_ent = 0;
@@ -247,8 +252,9 @@ struct PairHost {
 
 constexpr uint16_t kPairPad = 0xffffu;
 
-inline PairHost build_pair_host(const BlockHost &H, int d, const int32_t *rp, int kWaves,
-                                int kSlots, int nthreads, bool tri = false) {
+inline PairHost build_pair_host(const BlockHost &H, int d, const int32_t *rp, const int32_t *ci,
+                                int kWaves, int kSlots, int nthreads, bool tri = false,
+                                bool dedup = false) {
     PairHost P;
     const int NL = d + 1;
     const int nb = H.nb;
@@ -256,12 +262,12 @@ inline PairHost build_pair_host(const BlockHost &H, int d, const int32_t *rp, in
         std::vector<int32_t> cnt;        // per task
         std::vector<int32_t> eoff;       // per task, local entry offset
         std::vector<int32_t> wfirst;     // [kWaves+1], local task index
-        std::vector<uint16_t> hdr, ent;
+        std::vector<uint16_t> hdr, hdr2, ent;
         bool ok = true;
     };
     std::vector<Blk> blks(nb);
     auto work = [&](int b0, int b1) {
-        std::vector<int32_t> off, lst_ptr, fill, order;
+        std::vector<int32_t> off, lst_ptr, fill, order, mir;
         std::vector<uint16_t> lst;
         for (int b = b0; b < b1; ++b) {
             Blk &B = blks[b];
@@ -302,12 +308,29 @@ inline PairHost build_pair_host(const BlockHost &H, int d, const int32_t *rp, in
                         lst[fill[q]++] = uint16_t(ep | code);
                     }
                 }
-            order.resize(np);
-            for (int q = 0; q < np; ++q) order[q] = q;
+            // mirrors: column vertex = row r2 of this block; r2 > r writes both
+            mir.assign(np, -1);
+            order.clear();
+            for (int r = 0; r < nr; ++r) {
+                const int32_t row = rw[r];
+                for (int p = 0; p < off[r + 1] - off[r]; ++p) {
+                    const int q = off[r] + p;
+                    const int32_t c = ci[rp[row] + p];
+                    const int32_t *it = std::lower_bound(rw, rw + nr, c);
+                    const int r2 = (it != rw + nr && *it == c) ? int(it - rw) : -1;
+                    if (dedup && r2 >= 0 && r2 < r) continue;   // written by its mirror
+                    if (dedup && r2 > r) {
+                        const int p2 = int(std::lower_bound(ci + rp[c], ci + rp[c + 1], row) - (ci + rp[c]));
+                        mir[q] = r2 | (p2 << 7);
+                    }
+                    order.push_back(q);
+                }
+            }
+            const int nlisted = int(order.size());
             std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
                 return lst_ptr[x + 1] - lst_ptr[x] > lst_ptr[y + 1] - lst_ptr[y];
             });
-            const int ntask = (np + 63) / 64;
+            const int ntask = (nlisted + 63) / 64;
             if (ntask > kWaves * kSlots) {
                 B.ok = false;
                 continue;
@@ -335,13 +358,15 @@ inline PairHost build_pair_host(const BlockHost &H, int d, const int32_t *rp, in
                     B.ent.resize(e0 + size_t(c) * 64, uint16_t(H.elem_ptr[b + 1] - H.elem_ptr[b]));
                     for (int j = 0; j < 64; ++j) {
                         const int k = t * 64 + j;
-                        if (k >= np) {
+                        if (k >= nlisted) {
                             B.hdr.push_back(kPairPad);
+                            B.hdr2.push_back(kPairPad);
                             continue;
                         }
                         const int q = order[k];
                         const int r = int(std::upper_bound(off.begin(), off.end(), q) - off.begin()) - 1;
                         B.hdr.push_back(uint16_t(r | ((q - off[r]) << 7)));
+                        B.hdr2.push_back(mir[q] >= 0 ? uint16_t(mir[q]) : kPairPad);
                         for (int u = lst_ptr[q]; u < lst_ptr[q + 1]; ++u)
                             B.ent[e0 + size_t(u - lst_ptr[q]) * 64 + j] = lst[u];
                     }
@@ -373,6 +398,7 @@ inline PairHost build_pair_host(const BlockHost &H, int d, const int32_t *rp, in
             P.task_ent.push_back(e0 + B.eoff[t]);
         }
         P.hdr.insert(P.hdr.end(), B.hdr.begin(), B.hdr.end());
+        P.hdr2.insert(P.hdr2.end(), B.hdr2.begin(), B.hdr2.end());
         P.ent.insert(P.ent.end(), B.ent.begin(), B.ent.end());
         P.ent_ptr.push_back(int64_t(P.ent.size()));
         P.max_ent = std::max<int64_t>(P.max_ent, int64_t(B.ent.size()));

@@ -65,6 +65,7 @@ struct PairPlan {
     int32_t *task_cnt = nullptr;  // entries per lane of each task
     int32_t *task_eoff = nullptr; // first entry of each task, relative to its block
     uint16_t *hdr = nullptr;      // [ntask*64] r | p << 7 per task lane (0xffff: empty)
+    uint16_t *hdr2 = nullptr;     // [ntask*64] mirror pair written by the same lane (0xffff: none)
     uint16_t *ent = nullptr;      // entry lists, entry-major within a task
 };
 constexpr int kPairWaves = 4;     // wavefronts per workgroup of the pair kernel

@@ -49,6 +49,7 @@ struct PairView {
     const int32_t *task_cnt;
     const int32_t *task_eoff;
     const uint16_t *hdr;
+    const uint16_t *hdr2;
     const uint16_t *ent;
     const double *q;
     const double *w;
@@ -197,7 +198,7 @@ __global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, doubl
     static_assert(kEntSlots == 4, "four named entry slots");
     uint2 rel[kElemSlots];
     int4 rrow = make_int4(0, 0, 0, 0);
-    uint32_t rhd[S];
+    uint32_t rhd[S], rhd2[S];
     int rcnt[S], reoff[S], rns = 0;
     double rq[kNodeSlots][D];
     double rw[kNodeSlots];
@@ -229,10 +230,12 @@ __global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, doubl
             rcnt[s] = 0;
             reoff[s] = 0;
             rhd[s] = kPairPad;
+            rhd2[s] = kPairPad;
             if (s < rns) {
                 rcnt[s] = pv.task_cnt[tw0 + s];
                 reoff[s] = pv.task_eoff[tw0 + s];
                 rhd[s] = pv.hdr[int64_t(tw0 + s) * 64 + lane];
+                rhd2[s] = pv.hdr2[int64_t(tw0 + s) * 64 + lane];
             }
         }
         if (tid < d.nent8) rent0 = src[tid];
@@ -296,12 +299,13 @@ __global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, doubl
             rinf[tid] = rrow;
             for (int kk = 0; kk < rrow.y; ++kk) rowof[rrow.z + kk] = uint8_t(tid);
         }
-        uint32_t hd[S];
+        uint32_t hd[S], hd2[S];
         int cnt[S], eoff[S];
         const int ns = rns;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             hd[s] = rhd[s];
+            hd2[s] = rhd2[s];
             cnt[s] = rcnt[s];
             eoff[s] = reoff[s];
         }
@@ -383,6 +387,14 @@ __global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, doubl
                 const int r = int(hd[s] & 127u), p = int(hd[s] >> 7);
                 const int4 ri = rinf[r];
                 double *o = outb + M2 * ri.z + M * p;
+                // the mirror pair (if any): the transposed block, or the same value
+                double *o2 = nullptr;
+                int len2 = 0;
+                if (hd2[s] != kPairPad) {
+                    const int4 r2 = rinf[hd2[s] & 127u];
+                    o2 = outb + M2 * r2.z + M * int(hd2[s] >> 7);
+                    len2 = r2.y;
+                }
                 if constexpr (OP == FEM_OP_ELAS) {
                     double tr = X[s][0];
 #pragma unroll
@@ -390,11 +402,15 @@ __global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, doubl
 #pragma unroll
                     for (int l = 0; l < D; ++l)
 #pragma unroll
-                        for (int n = 0; n < D; ++n)
-                            o[l * D * ri.y + n] = elas_combine(X[s][l * D + n], X[s][n * D + l],
-                                                               tr, l == n, lam, mu);
+                        for (int n = 0; n < D; ++n) {
+                            const double v = elas_combine(X[s][l * D + n], X[s][n * D + l], tr,
+                                                          l == n, lam, mu);
+                            o[l * D * ri.y + n] = v;
+                            if (o2) o2[n * D * len2 + l] = v;
+                        }
                 } else {
                     o[0] = X[s][0];
+                    if (o2) o2[0] = X[s][0];
                 }
             }
         }
@@ -463,6 +479,7 @@ hipError_t launch_pair_t(const fem_plan_data *p, const PairPlan &P, const double
     pv.task_cnt = P.task_cnt;
     pv.task_eoff = P.task_eoff;
     pv.hdr = P.hdr;
+    pv.hdr2 = P.hdr2;
     pv.ent = P.ent;
     pv.q = q;
     pv.w = w;
@@ -522,7 +539,7 @@ hipError_t launch_pair_d(const fem_plan_data *p, int op, const double *q, const 
 
 void free_pairs(PairPlan *p) {
     void *ptrs[] = {p->desc, p->rowinfo, p->nodes, p->elem, p->task_cnt, p->task_eoff, p->hdr,
-                    p->ent};
+                    p->hdr2, p->ent};
     for (void *x : ptrs)
         if (x) (void)hipFree(x);
     *p = PairPlan();
@@ -531,12 +548,15 @@ void free_pairs(PairPlan *p) {
 fem_status upload_pairs(PairPlan &P, int R, int slots, bool tri, int d, int64_t nq, int64_t nme,
                         const int32_t *me, const int32_t *rp, const int32_t *ci, const int64_t *ip,
                         const int32_t *inc_k) {
+    // mirror pairs inside a block are summed once (FEMASM_PAIR_DEDUP=0: off)
+    bool dedup = true;
+    if (const char *e = getenv("FEMASM_PAIR_DEDUP")) dedup = atoi(e) != 0;
     P = PairPlan();
     const int64_t max_pairs = int64_t(64) * kPairWaves * slots;
     BlockHost H = build_block_host(d, nq, nme, me, rp, ci, ip, inc_k, std::min(R, 128), 16,
                                    max_pairs);
     if (!H.ok || H.nb == 0) return FEM_OK;   // row-gather kernel only
-    PairHost PH = build_pair_host(H, d, rp, kPairWaves, slots, 16, tri);
+    PairHost PH = build_pair_host(H, d, rp, ci, kPairWaves, slots, 16, tri, dedup);
     if (!PH.ok || PH.max_ent > int64_t(kEntSlots) * kPairWG * 8 ||
         H.max_nodes > kNodeSlots * kPairWG || H.max_elems + 1 > kElemSlots * kPairWG)
         return FEM_OK;
@@ -581,6 +601,7 @@ fem_status upload_pairs(PairPlan &P, int R, int slots, bool tri, int d, int64_t 
     if (st == FEM_OK) st = up(&P.task_cnt, PH.task_cnt);
     if (st == FEM_OK) st = up(&P.task_eoff, task_eoff);
     if (st == FEM_OK) st = up(&P.hdr, PH.hdr);
+    if (st == FEM_OK) st = up(&P.hdr2, PH.hdr2);
     if (st == FEM_OK) st = up(&P.ent, PH.ent);
     if (st != FEM_OK) {
         free_pairs(&P);
