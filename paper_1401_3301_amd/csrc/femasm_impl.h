@@ -55,7 +55,7 @@ struct BlockPlan {
 struct PairPlan {
     bool ok = false;
     int nb = 0;
-    int slots = 2;                // tasks of 64 pairs per wavefront at most
+    int slots = 2;                // tasks of 64 pairs per wavefront at most (1, 2 or 4)
     int max_rows = 0, max_nodes = 0, max_elems = 0;
     int64_t max_nacc = 0, max_ent = 0;
     int32_t *desc = nullptr;      // [nb*12] block descriptors (pair.hip)
@@ -68,7 +68,7 @@ struct PairPlan {
     uint16_t *hdr2 = nullptr;     // [ntask*64] mirror pair written by the same lane (0xffff: none)
     uint16_t *ent = nullptr;      // entry lists, entry-major within a task
 };
-constexpr int kPairWaves = 4;     // wavefronts per workgroup of the pair kernel
+constexpr int kPairWaves = 8;     // wavefronts per workgroup of the pair kernel
 
 struct fem_plan_data {
     int d = 0;

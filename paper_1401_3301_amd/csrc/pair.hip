@@ -37,9 +37,10 @@ namespace femasm {
 namespace {
 
 constexpr int kPairWG = kPairWaves * 64;
-constexpr int kEntSlots = 4;    // uint4 entry slots per thread: <= 8192 entries per block
-constexpr int kNodeSlots = 2;   // touched vertices per thread: <= 512 per block
-constexpr int kElemSlots = 4;   // elements per thread: <= 1023 (+ dummy) per block
+constexpr int kEntSlots = 8192 / 8 / kPairWG;   // uint4 entry slots per thread: <= 8192 entries
+constexpr int kNodeSlots = 512 / kPairWG;       // touched vertices per thread: <= 512 per block
+constexpr int kElemSlots = 1024 / kPairWG;      // elements per thread: <= 1023 (+ dummy)
+static_assert(kEntSlots == 2 && kNodeSlots == 1 && kElemSlots == 2, "512-thread workgroups");
 
 struct PairView {
     const int32_t *desc;
@@ -78,12 +79,13 @@ __device__ __forceinline__ constexpr int tri_index(int a, int b) {
 
 // Block descriptor, kDescInts ints per block: first row, rows, first touched
 // vertex, touched vertices, first element, elements, CSR entries of the rows,
-// first task, entry count / 8, task starts of wavefronts 1..4 relative to the
-// first task (5 bits each), first entry (64 bits, low word first).
-constexpr int kDescInts = 12;
+// first task, entry count / 8, task starts of wavefronts 1..8 relative to the
+// first task (5 bits each, 64-bit field, low word first), first entry (64
+// bits, low word first), two unused.
+constexpr int kDescInts = 16;
 struct Desc {
     int r0, nr, n0, nn, e0, ne, nacc, t0, nent8;
-    uint32_t wp;
+    uint64_t wp;
     int64_t eb;
 };
 
@@ -99,13 +101,13 @@ __device__ __forceinline__ Desc load_desc(const PairView &pv, int b) {
     d.nacc = x[6];
     d.t0 = x[7];
     d.nent8 = x[8];
-    d.wp = uint32_t(x[9]);
+    d.wp = uint64_t(uint32_t(x[9])) | (uint64_t(uint32_t(x[12])) << 32);
     d.eb = int64_t(uint32_t(x[10])) | (int64_t(x[11]) << 32);
     return d;
 }
 
 // First task of wavefront w (0..kPairWaves) of a block, relative to its t0.
-__device__ __forceinline__ int wave_task(uint32_t wp, int w) {
+__device__ __forceinline__ int wave_task(uint64_t wp, int w) {
     return w == 0 ? 0 : int((wp >> (5 * (w - 1))) & 31u);
 }
 
@@ -120,24 +122,25 @@ __device__ __forceinline__ void element_values(const double (&P)[D + 1][D], cons
         const bool deg = det == 0.0;
         if (deg) bad = 1;
         const double ad = fabs(det);
+        // a degenerate element gets k = 0, so every value is a signed zero
+        // (adding it leaves a sum unchanged, as skipping the element does)
         if constexpr (OP == FEM_OP_MASS) {
-            const double k = ad / Fact<D>::mass_den;
+            const double k = deg ? 0.0 : ad / Fact<D>::mass_den;
 #pragma unroll
             for (int a = 0; a < NL; ++a)
 #pragma unroll
-                for (int b = a; b < NL; ++b)
-                    out[tri_index<NL>(a, b)] = deg ? 0.0 : (a == b ? 2.0 * k : k);
+                for (int b = a; b < NL; ++b) out[tri_index<NL>(a, b)] = a == b ? 2.0 * k : k;
         } else {
             double ws = wl[0];
 #pragma unroll
             for (int b = 1; b < NL; ++b) ws += wl[b];
-            const double k = ad / Fact<D>::massw_den;
+            const double k = deg ? 0.0 : ad / Fact<D>::massw_den;
 #pragma unroll
             for (int a = 0; a < NL; ++a)
 #pragma unroll
                 for (int b = a; b < NL; ++b) {
                     const double f = a == b ? 2.0 * k : k;
-                    out[tri_index<NL>(a, b)] = deg ? 0.0 : f * (ws + (wl[a] + wl[b]));
+                    out[tri_index<NL>(a, b)] = f * (ws + (wl[a] + wl[b]));
                 }
         }
     } else {
@@ -146,12 +149,12 @@ __device__ __forceinline__ void element_values(const double (&P)[D + 1][D], cons
         const bool deg = E.det == 0.0;
         if (deg) bad = 1;
         if constexpr (OP == FEM_OP_STIFF) {
+            // degenerate: inv = 0, so every value is a signed zero
             const double inv = deg ? 0.0 : 1.0 / (Fact<D>::dfact * fabs(E.det));
 #pragma unroll
             for (int a = 0; a < NL; ++a)
 #pragma unroll
-                for (int b = a; b < NL; ++b)
-                    out[tri_index<NL>(a, b)] = deg ? 0.0 : cdot<D>(E.c[a], E.c[b]) * inv;
+                for (int b = a; b < NL; ++b) out[tri_index<NL>(a, b)] = cdot<D>(E.c[a], E.c[b]) * inv;
         } else {
             const double sc = deg ? 0.0 : elas_scale<D>(E.det);
 #pragma unroll
@@ -194,8 +197,7 @@ __global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, doubl
 
     // ---- prefetch registers
     // entry slots as named registers (an indexed array ends up in scratch)
-    uint4 rent0 = make_uint4(0, 0, 0, 0), rent1 = rent0, rent2 = rent0, rent3 = rent0;
-    static_assert(kEntSlots == 4, "four named entry slots");
+    uint4 rent0 = make_uint4(0, 0, 0, 0), rent1 = rent0;
     uint2 rel[kElemSlots];
     int4 rrow = make_int4(0, 0, 0, 0);
     uint32_t rhd[S], rhd2[S];
@@ -240,8 +242,6 @@ __global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, doubl
         }
         if (tid < d.nent8) rent0 = src[tid];
         if (kPairWG + tid < d.nent8) rent1 = src[kPairWG + tid];
-        if (2 * kPairWG + tid < d.nent8) rent2 = src[2 * kPairWG + tid];
-        if (3 * kPairWG + tid < d.nent8) rent3 = src[3 * kPairWG + tid];
 #pragma unroll
         for (int u = 0; u < kElemSlots; ++u) {
             const int e = u * kPairWG + tid;
@@ -292,8 +292,6 @@ __global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, doubl
             uint4 *e4 = reinterpret_cast<uint4 *>(ent);
             if (tid < dc.nent8) e4[tid] = rent0;
             if (kPairWG + tid < dc.nent8) e4[kPairWG + tid] = rent1;
-            if (2 * kPairWG + tid < dc.nent8) e4[2 * kPairWG + tid] = rent2;
-            if (3 * kPairWG + tid < dc.nent8) e4[3 * kPairWG + tid] = rent3;
         }
         if (tid < dc.nr) {
             rinf[tid] = rrow;
@@ -583,11 +581,12 @@ fem_status upload_pairs(PairPlan &P, int R, int slots, bool tri, int d, int64_t 
         x[5] = H.elem_ptr[b + 1] - H.elem_ptr[b];
         x[6] = o;
         x[7] = t0;
-        uint32_t wp = 0;
+        uint64_t wp = 0;
         for (int w = 1; w <= kPairWaves; ++w)
-            wp |= uint32_t(PH.wt[size_t(b) * (kPairWaves + 1) + w] - t0) << (5 * (w - 1));
+            wp |= uint64_t(PH.wt[size_t(b) * (kPairWaves + 1) + w] - t0) << (5 * (w - 1));
         x[8] = int32_t((PH.ent_ptr[b + 1] - PH.ent_ptr[b]) / 8);
-        x[9] = int32_t(wp);
+        x[9] = int32_t(uint32_t(wp & 0xffffffffu));
+        x[12] = int32_t(uint32_t(wp >> 32));
         x[10] = int32_t(uint32_t(uint64_t(PH.ent_ptr[b]) & 0xffffffffu));
         x[11] = int32_t(uint64_t(PH.ent_ptr[b]) >> 32);
         for (int t = t0; t < PH.wt[size_t(b) * (kPairWaves + 1) + kPairWaves]; ++t)
