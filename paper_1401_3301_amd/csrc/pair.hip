@@ -89,20 +89,28 @@ struct Desc {
     int64_t eb;
 };
 
-__device__ __forceinline__ Desc load_desc(const PairView &pv, int b) {
+// Descriptors travel as vector loads, lane k holding int k, and are read out
+// with readlane an iteration later: a scalar load shares its wait counter
+// with LDS operations and would stall the next LDS access on HBM latency.
+__device__ __forceinline__ int load_desc_vec(const PairView &pv, int b, int lane) {
+    return b >= 0 && lane < kDescInts ? pv.desc[int64_t(b) * kDescInts + lane] : 0;
+}
+
+__device__ __forceinline__ Desc desc_from(int dv) {
     Desc d;
-    const int32_t *x = pv.desc + int64_t(b) * kDescInts;
-    d.r0 = x[0];
-    d.nr = x[1];
-    d.n0 = x[2];
-    d.nn = x[3];
-    d.e0 = x[4];
-    d.ne = x[5];
-    d.nacc = x[6];
-    d.t0 = x[7];
-    d.nent8 = x[8];
-    d.wp = uint64_t(uint32_t(x[9])) | (uint64_t(uint32_t(x[12])) << 32);
-    d.eb = int64_t(uint32_t(x[10])) | (int64_t(x[11]) << 32);
+    d.r0 = __builtin_amdgcn_readlane(dv, 0);
+    d.nr = __builtin_amdgcn_readlane(dv, 1);
+    d.n0 = __builtin_amdgcn_readlane(dv, 2);
+    d.nn = __builtin_amdgcn_readlane(dv, 3);
+    d.e0 = __builtin_amdgcn_readlane(dv, 4);
+    d.ne = __builtin_amdgcn_readlane(dv, 5);
+    d.nacc = __builtin_amdgcn_readlane(dv, 6);
+    d.t0 = __builtin_amdgcn_readlane(dv, 7);
+    d.nent8 = __builtin_amdgcn_readlane(dv, 8);
+    d.wp = uint64_t(uint32_t(__builtin_amdgcn_readlane(dv, 9))) |
+           (uint64_t(uint32_t(__builtin_amdgcn_readlane(dv, 12))) << 32);
+    d.eb = int64_t(uint32_t(__builtin_amdgcn_readlane(dv, 10))) |
+           (int64_t(__builtin_amdgcn_readlane(dv, 11)) << 32);
     return d;
 }
 
@@ -201,7 +209,7 @@ __global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, doubl
     uint2 rel[kElemSlots];
     int4 rrow = make_int4(0, 0, 0, 0);
     uint32_t rhd[S], rhd2[S];
-    int rcnt[S], reoff[S], rns = 0;
+    int rcntv = 0, reoffv = 0, rns = 0;   // task entry counts / offsets, lane s = slot s
     double rq[kNodeSlots][D];
     double rw[kNodeSlots];
     int nid[kNodeSlots];
@@ -227,18 +235,12 @@ __global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, doubl
         const uint4 *src = reinterpret_cast<const uint4 *>(pv.ent + d.eb);
         const int tw0 = d.t0 + wave_task(d.wp, wave);
         rns = d.t0 + wave_task(d.wp, wave + 1) - tw0;
+        rcntv = lane < rns ? pv.task_cnt[tw0 + lane] : 0;
+        reoffv = lane < rns ? pv.task_eoff[tw0 + lane] : 0;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            rcnt[s] = 0;
-            reoff[s] = 0;
-            rhd[s] = kPairPad;
-            rhd2[s] = kPairPad;
-            if (s < rns) {
-                rcnt[s] = pv.task_cnt[tw0 + s];
-                reoff[s] = pv.task_eoff[tw0 + s];
-                rhd[s] = pv.hdr[int64_t(tw0 + s) * 64 + lane];
-                rhd2[s] = pv.hdr2[int64_t(tw0 + s) * 64 + lane];
-            }
+            rhd[s] = s < rns ? pv.hdr[int64_t(tw0 + s) * 64 + lane] : kPairPad;
+            rhd2[s] = s < rns ? pv.hdr2[int64_t(tw0 + s) * 64 + lane] : kPairPad;
         }
         if (tid < d.nent8) rent0 = src[tid];
         if (kPairWG + tid < d.nent8) rent1 = src[kPairWG + tid];
@@ -250,18 +252,21 @@ __global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, doubl
         if (tid < d.nr) rrow = pv.rowinfo[d.r0 + tid];
     };
 
+    // blocks k, k+1, k+2 of this workgroup: current, next, after next; the
+    // descriptor registers run three blocks ahead
     int bc = block_at(0);
     if (bc < 0) return;
-    Desc dc = load_desc(pv, bc);
+    int bn = block_at(1), bnn = block_at(2);
+    Desc dc = desc_from(load_desc_vec(pv, bc, lane));
     load_nodes(dc);
     issue_coords(dc);
     issue_raw(dc);
-    int bn = block_at(1);
     Desc dn = dc;
     if (bn >= 0) {
-        dn = load_desc(pv, bn);
+        dn = desc_from(load_desc_vec(pv, bn, lane));
         load_nodes(dn);
     }
+    int dv_nn = load_desc_vec(pv, bnn, lane);
 
     Desc dp = dc;
     bool have_prev = false;
@@ -304,12 +309,23 @@ __global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, doubl
         for (int s = 0; s < S; ++s) {
             hd[s] = rhd[s];
             hd2[s] = rhd2[s];
-            cnt[s] = rcnt[s];
-            eoff[s] = reoff[s];
+            cnt[s] = __builtin_amdgcn_readlane(rcntv, s);
+            eoff[s] = __builtin_amdgcn_readlane(reoffv, s);
         }
         uint2 el[kElemSlots];
 #pragma unroll
         for (int u = 0; u < kElemSlots; ++u) el[u] = rel[u];
+        // lists of the next block, vertex ids of the one after it and the
+        // descriptor of the block after that: in flight during this block's
+        // element and pair phases
+        const int bnnn = block_at(k + 3);
+        Desc dnn = dn;
+        if (bn >= 0) issue_raw(dn);
+        if (bnn >= 0) {
+            dnn = desc_from(dv_nn);
+            load_nodes(dnn);
+        }
+        const int dv_nnn = load_desc_vec(pv, bnnn, lane);
         __syncthreads();
         // L7: element phase
 #pragma unroll
@@ -332,14 +348,6 @@ __global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, doubl
 #pragma unroll
                 for (int t = 0; t < NV; ++t) ev[e * NV + t] = 0.0;
             }
-        }
-        // L8: lists of the next block, vertex ids of the one after it
-        const int bnn = block_at(k + 2);
-        Desc dnn = dn;
-        if (bn >= 0) issue_raw(dn);
-        if (bnn >= 0) {
-            dnn = load_desc(pv, bnn);
-            load_nodes(dnn);
         }
         __syncthreads();
         // L10: pair sums
@@ -420,6 +428,8 @@ __global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, doubl
         dc = dn;
         bn = bnn;
         dn = dnn;
+        bnn = bnnn;
+        dv_nn = dv_nnn;
     }
     for (int kk = tid; kk < M2 * dp.nacc; kk += kPairWG) {
         const int4 ri = rinf[rowof[kk / M2]];
