@@ -165,8 +165,8 @@ void fem_plan_destroy(fem_plan plan);
  *   nmesh          number of meshes (>= 1)
  *   d, nq, nme     host arrays [nmesh]
  *   me             host array [nmesh] of device pointers (layout above)
- * Builds one plan per mesh plus a device work list of (mesh, row tile)
- * items, largest first.  Synchronous.
+ * Builds one plan per mesh, a device work list of (mesh, row tile) items
+ * (largest first) and the concatenated vertex-pair layouts.  Synchronous.
  */
 fem_status fem_batch_create(int32_t nmesh, const int32_t *d, const int64_t *nq,
                             const int64_t *nme, const int32_t *const *me, hipStream_t stream,
@@ -181,15 +181,28 @@ fem_status fem_batch_offsets(fem_batch batch, int32_t op, int64_t *q_off, int64_
 /* Plan of mesh `index` (borrowed; owned by the batch). */
 fem_status fem_batch_plan(fem_batch batch, int32_t index, fem_plan *plan);
 
-/* Tunables of the persistent kernel: threads per workgroup (64, 128 or 256)
- * and workgroups per compute unit (1..8).  They change scheduling only, not
- * the values (each CSR row is still summed by one thread in ascending
- * element order).  Synchronous (rebuilds the work list). */
+/* Tunables of the persistent row-gather kernel: threads per workgroup (64,
+ * 128 or 256) and workgroups per compute unit (1..8).  They change
+ * scheduling only, not the values (each CSR row is still summed by one
+ * thread in ascending element order).  Synchronous (rebuilds the work list). */
 fem_status fem_batch_set_params(fem_batch batch, int32_t block_threads, int32_t wg_per_cu);
 
+/* Kernel family of fem_batch_numeric:
+ *   FEM_BATCH_PAIR (default)  the vertex-pair kernel over the concatenated
+ *                             pair layouts of all meshes, one persistent
+ *                             launch per dimension present
+ *   FEM_BATCH_ROWGATHER       one persistent launch of the row-gather kernel
+ *                             over (mesh, row tile) items (fem_batch_set_params)
+ * Both give the same values bit for bit; FEM_BATCH_PAIR falls back to the
+ * row-gather launch when a mesh has no pair layout.  FEM_ERR_ARG for another
+ * value. */
+enum { FEM_BATCH_ROWGATHER = 0, FEM_BATCH_PAIR = 1 };
+fem_status fem_batch_set_kernel(fem_batch batch, int32_t kernel);
+
 /*
- * CSR values of operator `op` for every mesh of the batch, in one kernel
- * launch.  q_cat, w_cat are the per-mesh arrays concatenated at q_off /
+ * CSR values of operator `op` for every mesh of the batch: one persistent
+ * launch (row-gather) or one per dimension present (pair; see
+ * fem_batch_set_kernel).  q_cat, w_cat are the per-mesh arrays concatenated at q_off /
  * w_off; values_cat receives mesh b's values at nnz_off[b].  No host
  * synchronisation, no allocation, fixed kernel arguments: safe to capture
  * in a hipGraph and replay.

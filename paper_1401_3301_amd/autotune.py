@@ -1,11 +1,13 @@
-"""Autotuner for the persistent batched kernel.
+"""Autotuner for the batched assembly.
 
-Times ``fem_batch_numeric`` for each candidate (threads per workgroup,
-workgroups per compute unit) with HIP events on the current stream and keeps
-the fastest.  The parameters change only how rows are scheduled, never the
-values (every CSR row is summed by one thread in ascending element number),
-so any choice gives bitwise-identical output.  Results are cached in a JSON
-file keyed by GPU architecture, operator and a size signature of the batch.
+Times ``fem_batch_numeric`` for each candidate -- the vertex-pair kernel, or
+the persistent row-gather kernel with a given number of threads per
+workgroup and workgroups per compute unit -- with HIP events on the current
+stream and keeps the fastest.  The candidates differ only in how the work is
+scheduled, never in the values (every CSR entry is summed in ascending
+element number with the same expressions), so any choice gives
+bitwise-identical output.  Results are cached in a JSON file keyed by GPU
+architecture, operator and a size signature of the batch.
 """
 from __future__ import annotations
 
@@ -17,7 +19,8 @@ import torch
 
 from . import femasm
 
-CANDIDATES = [(bt, w) for bt in (64, 128, 256) for w in (1, 2, 4, 8)]
+CANDIDATES = [("pair", 256, 2)] + [("rowgather", bt, w) for bt in (64, 128, 256)
+                                   for w in (1, 2, 4, 8)]
 
 
 def default_cache_path() -> str:
@@ -52,8 +55,8 @@ def _time(batch, op, q_cat, w_cat, out, reps):
 
 def tune(batch: femasm.Batch, op: str, q_cat, w_cat=None, reps: int = 5,
          cache_path: str | None = None, force: bool = False):
-    """Pick and apply the fastest (block_threads, wg_per_cu) for this batch
-    and operator.  Returns (params, {params: ms})."""
+    """Pick and apply the fastest (kernel, block_threads, wg_per_cu) for this
+    batch and operator.  Returns (params, {params: ms})."""
     cache_path = cache_path or default_cache_path()
     key = batch_key(batch, op)
     cache = {}
@@ -62,22 +65,23 @@ def tune(batch: femasm.Batch, op: str, q_cat, w_cat=None, reps: int = 5,
             cache = json.load(open(cache_path))
         except (OSError, ValueError):
             cache = {}
-    if not force and key in cache:
+    if not force and key in cache and len(cache[key]["params"]) == 3:
         params = tuple(cache[key]["params"])
-        batch.set_params(*params)
+        batch.configure(params)
         return params, cache[key].get("times", {})
     nnz = batch.offsets(op).nnz[-1]
     out = torch.empty(max(nnz, 1), dtype=torch.float64, device=batch.device)
     times = {}
-    for bt, w in CANDIDATES:
+    for cand in CANDIDATES:
         try:
-            batch.set_params(bt, w)
+            batch.configure(cand)
         except femasm.FemError:
             continue
-        times[f"{bt}x{w}"] = _time(batch, op, q_cat, w_cat, out, reps)
+        times["%s:%dx%d" % cand] = _time(batch, op, q_cat, w_cat, out, reps)
     best = min(times, key=times.get)
-    params = tuple(int(x) for x in best.split("x"))
-    batch.set_params(*params)
+    kern, rest = best.split(":")
+    params = (kern,) + tuple(int(x) for x in rest.split("x"))
+    batch.configure(params)
     cache[key] = {"params": list(params), "times": times}
     os.makedirs(os.path.dirname(cache_path) or ".", exist_ok=True)
     tmp = cache_path + ".tmp"

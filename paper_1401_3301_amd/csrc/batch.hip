@@ -94,6 +94,9 @@ struct fem_batch_s {
     int cus = 256;
     int32_t *status = nullptr;
     bool has_d[4] = {false, false, false, false};
+    // batched pair layouts [scalar / elasticity][d] and the kernel in use
+    PairPlan pairs[2][4];
+    int kernel = FEM_BATCH_PAIR;
 };
 
 static void free_batch(fem_batch_s *b) {
@@ -106,6 +109,29 @@ static void free_batch(fem_batch_s *b) {
     b->d_meshes = nullptr;
     b->d_items[0] = b->d_items[1] = nullptr;
     b->status = nullptr;
+    for (auto &row : b->pairs)
+        for (PairPlan &P : row) free_pairs(&P);
+}
+
+// One pair layout per (scalar / elasticity, d) over all meshes of that d.
+static fem_status build_pair_layouts(fem_batch_s *B) {
+    for (int vec = 0; vec < 2; ++vec)
+        for (int d = 2; d <= 3; ++d) {
+            std::vector<const PairPlan *> parts;
+            std::vector<int64_t> qo, wo, vo, nq;
+            for (size_t m = 0; m < B->plans.size(); ++m) {
+                const fem_plan p = B->plans[m];
+                if (p->d != d || p->nq == 0) continue;
+                parts.push_back(vec ? &p->pvec : &p->pscal);
+                qo.push_back(B->q_off[m]);
+                wo.push_back(B->w_off[m]);
+                vo.push_back(B->nnz_off[vec][m]);
+                nq.push_back(p->nq);
+            }
+            fem_status st = concat_pairs(B->pairs[vec][d], parts, qo, wo, vo, nq);
+            if (st != FEM_OK) return st;
+        }
+    return FEM_OK;
 }
 
 // (Re)builds the two work lists for the current block size.  Each mesh is
@@ -221,11 +247,18 @@ extern "C" fem_status fem_batch_create(int32_t nmesh, const int32_t *d, const in
         return hip_status(e);
     }
     fem_status st = build_items(B.get());
+    if (st == FEM_OK) st = build_pair_layouts(B.get());
     if (st != FEM_OK) {
         free_batch(B.get());
         return st;
     }
     *out = B.release();
+    return FEM_OK;
+}
+
+extern "C" fem_status fem_batch_set_kernel(fem_batch batch, int32_t kernel) {
+    if (!batch || (kernel != FEM_BATCH_ROWGATHER && kernel != FEM_BATCH_PAIR)) return FEM_ERR_ARG;
+    batch->kernel = kernel;
     return FEM_OK;
 }
 
@@ -274,6 +307,21 @@ extern "C" fem_status fem_batch_numeric(fem_batch batch, int32_t op, const doubl
     for (fem_plan p : batch->plans) {
         const int64_t M = vec ? p->d : 1;
         if (M * M * p->nnz >= (int64_t(1) << 31)) return FEM_ERR_OVERFLOW;
+    }
+    if (batch->kernel == FEM_BATCH_PAIR) {
+        // one pair launch per dimension present; any layout missing or too
+        // large for LDS: the row-gather launch below covers every mesh
+        bool ok = true;
+        for (int d = 2; d <= 3; ++d)
+            if (batch->has_d[d] && !batch->pairs[vec][d].ok) ok = false;
+        for (int d = 2; d <= 3 && ok; ++d) {
+            if (!batch->has_d[d]) continue;
+            const hipError_t e = launch_pair_layout(batch->pairs[vec][d], d, op, q_cat, w_cat,
+                                                    lambda, mu, values_cat, batch->status, stream);
+            if (e == hipErrorNotSupported) ok = false;
+            else if (e != hipSuccess) return hip_status(e);
+        }
+        if (ok) return FEM_OK;
     }
     return launch_batch(op, batch->d_meshes, batch->d_items[vec], batch->nitems[vec],
                         batch->block_threads, batch->lds[vec], batch->cus * batch->wg_per_cu,

@@ -58,7 +58,7 @@ struct PairPlan {
     int slots = 2;                // tasks of 64 pairs per wavefront at most (1, 2 or 4)
     int max_rows = 0, max_nodes = 0, max_elems = 0;
     int64_t max_nacc = 0, max_ent = 0;
-    int32_t *desc = nullptr;      // [nb*12] block descriptors (pair.hip)
+    int32_t *desc = nullptr;      // [nb*24] block descriptors (pair.hip)
     int4 *rowinfo = nullptr;      // [rows] (rp[row], row length, local offset, 0)
     int32_t *nodes = nullptr;     // touched vertices, grouped by block
     uint16_t *elem = nullptr;     // 4 local vertex ids per block element
@@ -67,6 +67,8 @@ struct PairPlan {
     uint16_t *hdr = nullptr;      // [ntask*64] r | p << 7 per task lane (0xffff: empty)
     uint16_t *hdr2 = nullptr;     // [ntask*64] mirror pair written by the same lane (0xffff: none)
     uint16_t *ent = nullptr;      // entry lists, entry-major within a task
+    int64_t n_rows = 0, n_nodes = 0, n_elems = 0, n_tasks = 0, n_ent = 0;   // array lengths
+    std::vector<int32_t> h_desc;  // host copy of desc (batched layouts are built from it)
 };
 constexpr int kPairWaves = 8;     // wavefronts per workgroup of the pair kernel
 
@@ -111,6 +113,17 @@ fem_status upload_pairs(PairPlan &P, int R, int slots, bool tri, int d, int64_t 
 // has no pair layout for this operator.
 bool launch_pair(const fem_plan_data *p, int op, const double *q, const double *w, double lam,
                  double mu, double *values, hipStream_t s, hipError_t *err);
+// Launches the pair kernel over a layout of dimension d (hipErrorNotSupported:
+// its LDS need exceeds the workgroup limit, nothing launched).
+hipError_t launch_pair_layout(const PairPlan &P, int d, int op, const double *q, const double *w,
+                              double lam, double mu, double *values, int32_t *status,
+                              hipStream_t s);
+// Concatenates per-mesh pair layouts into one (block descriptors carry each
+// mesh's coordinate / weight / value offsets and vertex count).  out.ok is
+// false when some part has no layout or the slot counts differ.
+fem_status concat_pairs(PairPlan &out, const std::vector<const PairPlan *> &parts,
+                        const std::vector<int64_t> &qo, const std::vector<int64_t> &wo,
+                        const std::vector<int64_t> &vo, const std::vector<int64_t> &nq);
 // Launches the block kernel for a scalar operator; returns false (nothing
 // launched) when the plan has no block layout.
 bool launch_block(const fem_plan_data *p, int op, const double *q, const double *w,

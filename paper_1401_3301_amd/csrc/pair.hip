@@ -55,7 +55,6 @@ struct PairView {
     const double *q;
     const double *w;
     double *values;
-    int64_t nq;
     int32_t nb, max_nodes;
     uint32_t off_w, off_row, off_rowof, off_ev, off_ent;
 };
@@ -77,17 +76,26 @@ __device__ __forceinline__ constexpr int tri_index(int a, int b) {
     return a * NL - a * (a - 1) / 2 + (b - a);
 }
 
-// Block descriptor, kDescInts ints per block: first row, rows, first touched
-// vertex, touched vertices, first element, elements, CSR entries of the rows,
-// first task, entry count / 8, task starts of wavefronts 1..8 relative to the
-// first task (5 bits each, 64-bit field, low word first), first entry (64
-// bits, low word first), two unused.
-constexpr int kDescInts = 16;
+// Block descriptor, kDescInts ints per block: [0] first row, [1] rows,
+// [2] first touched vertex, [3] touched vertices, [4] first element,
+// [5] elements, [6] CSR entries of the rows, [7] first task, [8] entry
+// count / 8, [9],[12] task starts of wavefronts 1..8 relative to the first
+// task (5 bits each, low word first), [10..11] first entry, and the block's
+// mesh within the coordinate, weight and value arrays (several meshes share
+// one launch in the batched assembly): [14..15] coordinate offset, [16..17]
+// weight offset, [18..19] value offset, [20..21] its vertex count n_q; 64-bit
+// fields low word first.
+constexpr int kDescInts = 24;
 struct Desc {
     int r0, nr, n0, nn, e0, ne, nacc, t0, nent8;
     uint64_t wp;
-    int64_t eb;
+    int64_t eb, qo, wo, vo, nq;
 };
+
+__device__ __forceinline__ int64_t lane64(int dv, int lo) {
+    return int64_t(uint32_t(__builtin_amdgcn_readlane(dv, lo))) |
+           (int64_t(__builtin_amdgcn_readlane(dv, lo + 1)) << 32);
+}
 
 // Descriptors travel as vector loads, lane k holding int k, and are read out
 // with readlane an iteration later: a scalar load shares its wait counter
@@ -109,8 +117,11 @@ __device__ __forceinline__ Desc desc_from(int dv) {
     d.nent8 = __builtin_amdgcn_readlane(dv, 8);
     d.wp = uint64_t(uint32_t(__builtin_amdgcn_readlane(dv, 9))) |
            (uint64_t(uint32_t(__builtin_amdgcn_readlane(dv, 12))) << 32);
-    d.eb = int64_t(uint32_t(__builtin_amdgcn_readlane(dv, 10))) |
-           (int64_t(__builtin_amdgcn_readlane(dv, 11)) << 32);
+    d.eb = lane64(dv, 10);
+    d.qo = lane64(dv, 14);
+    d.wo = lane64(dv, 16);
+    d.vo = lane64(dv, 18);
+    d.nq = lane64(dv, 20);
     return d;
 }
 
@@ -194,7 +205,6 @@ __global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, doubl
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int MN = pv.max_nodes;
-    const int64_t nq = pv.nq;
     // blocks of this workgroup: XCD x (workgroups x, x+8, ...) owns a
     // contiguous range of blocks, walked with stride J
     const int xcd = blockIdx.x & 7, jj = blockIdx.x >> 3, J = gridDim.x >> 3;
@@ -226,8 +236,8 @@ __global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, doubl
         for (int u = 0; u < kNodeSlots; ++u) {
             if (u * kPairWG + tid < d.nn) {
 #pragma unroll
-                for (int x = 0; x < D; ++x) rq[u][x] = pv.q[x * nq + nid[u]];
-                if constexpr (kW) rw[u] = pv.w[nid[u]];
+                for (int x = 0; x < D; ++x) rq[u][x] = pv.q[d.qo + x * d.nq + nid[u]];
+                if constexpr (kW) rw[u] = pv.w[d.wo + nid[u]];
             }
         }
     };
@@ -288,7 +298,7 @@ __global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, doubl
         if (have_prev) {
             for (int kk = tid; kk < M2 * dp.nacc; kk += kPairWG) {
                 const int4 ri = rinf[rowof[kk / M2]];
-                pv.values[int64_t(M2) * ri.x + (kk - M2 * ri.z)] = outb[kk];
+                pv.values[dp.vo + int64_t(M2) * ri.x + (kk - M2 * ri.z)] = outb[kk];
             }
         }
         __syncthreads();
@@ -433,7 +443,7 @@ __global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, doubl
     }
     for (int kk = tid; kk < M2 * dp.nacc; kk += kPairWG) {
         const int4 ri = rinf[rowof[kk / M2]];
-        pv.values[int64_t(M2) * ri.x + (kk - M2 * ri.z)] = outb[kk];
+        pv.values[dp.vo + int64_t(M2) * ri.x + (kk - M2 * ri.z)] = outb[kk];
     }
     const unsigned long long any = __ballot(bad != 0);
     if (any != 0ull && (threadIdx.x & 63) == __ffsll((long long)any) - 1) atomicOr(status, bad);
@@ -475,8 +485,8 @@ PairLds pair_lds(const PairPlan &P) {
 }
 
 template <int D, int OP, int S>
-hipError_t launch_pair_t(const fem_plan_data *p, const PairPlan &P, const double *q,
-                         const double *w, double lam, double mu, double *values, hipStream_t s) {
+hipError_t launch_pair_t(const PairPlan &P, const double *q, const double *w, double lam,
+                         double mu, double *values, int32_t *status, hipStream_t s) {
     PairLds L = pair_lds<D, OP>(P);
     if (L.bytes > 160 * 1024) return hipErrorNotSupported;   // caller falls back
     PairView pv = L.pv;
@@ -492,7 +502,6 @@ hipError_t launch_pair_t(const fem_plan_data *p, const PairPlan &P, const double
     pv.q = q;
     pv.w = w;
     pv.values = values;
-    pv.nq = p->nq;
     pv.nb = P.nb;
     pv.max_nodes = P.max_nodes;
     const void *fn = reinterpret_cast<const void *>(&k_pair<D, OP, S>);
@@ -518,28 +527,28 @@ hipError_t launch_pair_t(const fem_plan_data *p, const PairPlan &P, const double
     const int64_t need = (int64_t(P.nb) + 7) / 8 * 8;
     grid = std::max<int64_t>(8, std::min(grid, need));
     hipLaunchKernelGGL((k_pair<D, OP, S>), dim3(unsigned(grid)), dim3(kPairWG), L.bytes, s, pv,
-                       lam, mu, p->status);
+                       lam, mu, status);
     return hipGetLastError();
 }
 
 template <int D, int OP>
-hipError_t launch_pair_s(const fem_plan_data *p, const PairPlan &P, const double *q,
-                         const double *w, double lam, double mu, double *values, hipStream_t s) {
-    if (P.slots == 4) return launch_pair_t<D, OP, 4>(p, P, q, w, lam, mu, values, s);
-    if (P.slots == 1) return launch_pair_t<D, OP, 1>(p, P, q, w, lam, mu, values, s);
-    return launch_pair_t<D, OP, 2>(p, P, q, w, lam, mu, values, s);
+hipError_t launch_pair_s(const PairPlan &P, const double *q, const double *w, double lam,
+                         double mu, double *values, int32_t *status, hipStream_t s) {
+    if (P.slots == 4) return launch_pair_t<D, OP, 4>(P, q, w, lam, mu, values, status, s);
+    if (P.slots == 1) return launch_pair_t<D, OP, 1>(P, q, w, lam, mu, values, status, s);
+    return launch_pair_t<D, OP, 2>(P, q, w, lam, mu, values, status, s);
 }
 
 template <int D>
-hipError_t launch_pair_d(const fem_plan_data *p, int op, const double *q, const double *w,
-                         double lam, double mu, double *values, hipStream_t s) {
+hipError_t launch_pair_d(const PairPlan &P, int op, const double *q, const double *w, double lam,
+                         double mu, double *values, int32_t *status, hipStream_t s) {
     switch (op) {
-        case FEM_OP_MASS: return launch_pair_s<D, FEM_OP_MASS>(p, p->pscal, q, w, lam, mu, values, s);
+        case FEM_OP_MASS: return launch_pair_s<D, FEM_OP_MASS>(P, q, w, lam, mu, values, status, s);
         case FEM_OP_MASS_W:
-            return launch_pair_s<D, FEM_OP_MASS_W>(p, p->pscal, q, w, lam, mu, values, s);
+            return launch_pair_s<D, FEM_OP_MASS_W>(P, q, w, lam, mu, values, status, s);
         case FEM_OP_STIFF:
-            return launch_pair_s<D, FEM_OP_STIFF>(p, p->pscal, q, w, lam, mu, values, s);
-        default: return launch_pair_s<D, FEM_OP_ELAS>(p, p->pvec, q, w, lam, mu, values, s);
+            return launch_pair_s<D, FEM_OP_STIFF>(P, q, w, lam, mu, values, status, s);
+        default: return launch_pair_s<D, FEM_OP_ELAS>(P, q, w, lam, mu, values, status, s);
     }
 }
 
@@ -597,6 +606,8 @@ fem_status upload_pairs(PairPlan &P, int R, int slots, bool tri, int d, int64_t 
         x[8] = int32_t((PH.ent_ptr[b + 1] - PH.ent_ptr[b]) / 8);
         x[9] = int32_t(uint32_t(wp & 0xffffffffu));
         x[12] = int32_t(uint32_t(wp >> 32));
+        x[20] = int32_t(uint32_t(uint64_t(nq) & 0xffffffffu));   // one mesh: offsets 0
+        x[21] = int32_t(uint64_t(nq) >> 32);
         x[10] = int32_t(uint32_t(uint64_t(PH.ent_ptr[b]) & 0xffffffffu));
         x[11] = int32_t(uint64_t(PH.ent_ptr[b]) >> 32);
         for (int t = t0; t < PH.wt[size_t(b) * (kPairWaves + 1) + kPairWaves]; ++t)
@@ -618,6 +629,12 @@ fem_status upload_pairs(PairPlan &P, int R, int slots, bool tri, int d, int64_t 
     }
     P.nb = nb;
     P.slots = slots;
+    P.n_rows = int64_t(H.rows.size());
+    P.n_nodes = int64_t(H.nodes.size());
+    P.n_elems = int64_t(H.elem.size() / 4);
+    P.n_tasks = int64_t(PH.task_cnt.size());
+    P.n_ent = int64_t(PH.ent.size());
+    P.h_desc = desc;
     P.max_rows = H.max_rows;
     P.max_nodes = H.max_nodes;
     P.max_elems = H.max_elems;
@@ -627,15 +644,115 @@ fem_status upload_pairs(PairPlan &P, int R, int slots, bool tri, int d, int64_t 
     return FEM_OK;
 }
 
+hipError_t launch_pair_layout(const PairPlan &P, int d, int op, const double *q, const double *w,
+                              double lam, double mu, double *values, int32_t *status,
+                              hipStream_t s) {
+    return d == 2 ? launch_pair_d<2>(P, op, q, w, lam, mu, values, status, s)
+                  : launch_pair_d<3>(P, op, q, w, lam, mu, values, status, s);
+}
+
 bool launch_pair(const fem_plan_data *p, int op, const double *q, const double *w, double lam,
                  double mu, double *values, hipStream_t s, hipError_t *err) {
     const PairPlan &P = op == FEM_OP_ELAS ? p->pvec : p->pscal;
     if (!P.ok) return false;
-    const hipError_t e = p->d == 2 ? launch_pair_d<2>(p, op, q, w, lam, mu, values, s)
-                                   : launch_pair_d<3>(p, op, q, w, lam, mu, values, s);
+    const hipError_t e = launch_pair_layout(P, p->d, op, q, w, lam, mu, values, p->status, s);
     if (e == hipErrorNotSupported) return false;
     *err = e;
     return true;
+}
+
+fem_status concat_pairs(PairPlan &out, const std::vector<const PairPlan *> &parts,
+                        const std::vector<int64_t> &qo, const std::vector<int64_t> &wo,
+                        const std::vector<int64_t> &vo, const std::vector<int64_t> &nq) {
+    out = PairPlan();
+    if (parts.empty()) return FEM_OK;
+    int64_t rows = 0, nodes = 0, elems = 0, tasks = 0, ents = 0, nb = 0;
+    for (const PairPlan *P : parts) {
+        if (!P->ok || P->slots != parts[0]->slots) return FEM_OK;   // no batched pair layout
+        rows += P->n_rows;
+        nodes += P->n_nodes;
+        elems += P->n_elems;
+        tasks += P->n_tasks;
+        ents += P->n_ent;
+        nb += P->nb;
+    }
+    std::vector<int32_t> desc(size_t(nb) * kDescInts);
+    auto put64 = [](int32_t *x, int64_t v) {
+        x[0] = int32_t(uint32_t(uint64_t(v) & 0xffffffffu));
+        x[1] = int32_t(uint64_t(v) >> 32);
+    };
+    fem_status st = FEM_OK;
+    hipError_t e = hipSuccess;
+    auto alloc = [&](auto **ptr, int64_t n) {
+        if (e == hipSuccess)
+            e = hipMalloc(reinterpret_cast<void **>(ptr), sizeof(**ptr) * size_t(std::max<int64_t>(1, n)));
+    };
+    alloc(&out.rowinfo, rows);
+    alloc(&out.nodes, nodes);
+    alloc(&out.elem, 4 * elems);
+    alloc(&out.task_cnt, tasks);
+    alloc(&out.task_eoff, tasks);
+    alloc(&out.hdr, 64 * tasks);
+    alloc(&out.hdr2, 64 * tasks);
+    alloc(&out.ent, ents);
+    int64_t r0 = 0, n0 = 0, e0 = 0, t0 = 0, eb = 0, b0 = 0;
+    for (size_t m = 0; m < parts.size() && e == hipSuccess; ++m) {
+        const PairPlan &P = *parts[m];
+        auto cp = [&](auto *dst, const auto *src, int64_t n) {
+            if (e == hipSuccess && n > 0)
+                e = hipMemcpy(dst, src, sizeof(*src) * size_t(n), hipMemcpyDeviceToDevice);
+        };
+        cp(out.rowinfo + r0, P.rowinfo, P.n_rows);
+        cp(out.nodes + n0, P.nodes, P.n_nodes);
+        cp(out.elem + 4 * e0, P.elem, 4 * P.n_elems);
+        cp(out.task_cnt + t0, P.task_cnt, P.n_tasks);
+        cp(out.task_eoff + t0, P.task_eoff, P.n_tasks);
+        cp(out.hdr + 64 * t0, P.hdr, 64 * P.n_tasks);
+        cp(out.hdr2 + 64 * t0, P.hdr2, 64 * P.n_tasks);
+        cp(out.ent + eb, P.ent, P.n_ent);
+        for (int b = 0; b < P.nb; ++b) {
+            int32_t *x = desc.data() + size_t(b0 + b) * kDescInts;
+            const int32_t *y = P.h_desc.data() + size_t(b) * kDescInts;
+            std::copy(y, y + kDescInts, x);
+            x[0] += int32_t(r0);
+            x[2] += int32_t(n0);
+            x[4] += int32_t(e0);
+            x[7] += int32_t(t0);
+            put64(x + 10, (int64_t(uint32_t(y[10])) | (int64_t(y[11]) << 32)) + eb);
+            put64(x + 14, qo[m]);
+            put64(x + 16, wo[m]);
+            put64(x + 18, vo[m]);
+            put64(x + 20, nq[m]);
+        }
+        r0 += P.n_rows;
+        n0 += P.n_nodes;
+        e0 += P.n_elems;
+        t0 += P.n_tasks;
+        eb += P.n_ent;
+        b0 += P.nb;
+        out.max_rows = std::max(out.max_rows, P.max_rows);
+        out.max_nodes = std::max(out.max_nodes, P.max_nodes);
+        out.max_elems = std::max(out.max_elems, P.max_elems);
+        out.max_nacc = std::max(out.max_nacc, P.max_nacc);
+        out.max_ent = std::max(out.max_ent, P.max_ent);
+    }
+    if (e == hipSuccess) st = up(&out.desc, desc);
+    else st = hip_status(e);
+    if (st != FEM_OK || rows >= (int64_t(1) << 31) || nodes >= (int64_t(1) << 31) ||
+        tasks >= (int64_t(1) << 31)) {
+        free_pairs(&out);
+        return st;
+    }
+    out.nb = int(nb);
+    out.slots = parts[0]->slots;
+    out.n_rows = rows;
+    out.n_nodes = nodes;
+    out.n_elems = elems;
+    out.n_tasks = tasks;
+    out.n_ent = ents;
+    out.h_desc = std::move(desc);
+    out.ok = true;
+    return FEM_OK;
 }
 
 }  // namespace femasm

@@ -57,6 +57,7 @@ _SIGS = {
     "fem_batch_offsets": ([P, I32, P, P, P, P], C.c_int),
     "fem_batch_plan": ([P, I32, C.POINTER(P)], C.c_int),
     "fem_batch_set_params": ([P, I32, I32], C.c_int),
+    "fem_batch_set_kernel": ([P, I32], C.c_int),
     "fem_batch_numeric": ([P, I32, P, P, D, D, P, P], C.c_int),
     "fem_batch_sync_status": ([P, P], C.c_int),
     "fem_batch_destroy": ([P], None),
@@ -193,6 +194,13 @@ def fem_batch_set_params(batch: int, block_threads: int, wg_per_cu: int):
            "fem_batch_set_params")
 
 
+FEM_BATCH_KERNEL = {"rowgather": 0, "pair": 1}
+
+
+def fem_batch_set_kernel(batch: int, kernel: int):
+    _check(load_library().fem_batch_set_kernel(batch, kernel), "fem_batch_set_kernel")
+
+
 def fem_batch_numeric(batch: int, op: int, q_cat: int, w_cat: int | None, lam: float, mu: float,
                       values_cat: int, stream=None):
     _check(load_library().fem_batch_numeric(batch, op, q_cat, w_cat, lam, mu, values_cat,
@@ -313,7 +321,7 @@ class Batch:
         self.device = self.mes[0].device
         self.handle = fem_batch_create(self.d, self.nq, self.nme,
                                        [m.data_ptr() for m in self.mes], stream)
-        self.params = (256, 2)
+        self.params = ("pair", 256, 2)
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -332,8 +340,17 @@ class Batch:
         return fem_batch_plan(self.handle, index)
 
     def set_params(self, block_threads: int, wg_per_cu: int):
+        """Tunables of the row-gather launch (the kernel family is unchanged)."""
         fem_batch_set_params(self.handle, block_threads, wg_per_cu)
-        self.params = (block_threads, wg_per_cu)
+        self.params = (self.params[0], block_threads, wg_per_cu)
+
+    def configure(self, params):
+        """params = (kernel, block_threads, wg_per_cu), kernel 'pair' or
+        'rowgather'; the last two apply to the row-gather launch."""
+        kernel, bt, w = params
+        fem_batch_set_params(self.handle, bt, w)
+        fem_batch_set_kernel(self.handle, FEM_BATCH_KERNEL[kernel])
+        self.params = (kernel, bt, w)
 
     def numeric(self, op, q_cat, w_cat=None, lam=1.0, mu=0.5, out=None, stream=None):
         nnz = self.offsets(op).nnz[-1]

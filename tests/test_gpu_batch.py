@@ -1,10 +1,11 @@
 """Batched assembly: 256 meshes (128 jittered squares, 128 Kuhn cubes,
-element counts log-uniform in [1e3, 2e5]) in one persistent launch.
+element counts log-uniform in [1e3, 2e5]) in persistent launches.
 
 Checks: batched values are bitwise equal to per-mesh fem_assemble_numeric
-values for every mesh and for every tuning parameter set; a subset matches
-the oracle; a captured hipGraph replays to the eager result several times
-with eager work in between.
+values for every mesh, for both kernel families (vertex pairs, row-gather)
+and every tuning parameter set; a subset matches the oracle; a captured
+hipGraph replays to the eager result several times with eager work in
+between.
 """
 import numpy as np
 import pytest
@@ -57,13 +58,14 @@ def test_batch_sizes(batch):
 def test_batched_equals_per_mesh(batch, op):
     B, meshes, ws, q_cat, w_cat = batch
     ref = _per_mesh(B, op, q_cat, w_cat)
-    for params in [(256, 2), (128, 4), (64, 8), (256, 1)]:
-        B.set_params(*params)
+    for params in [("pair", 256, 2), ("rowgather", 256, 2), ("rowgather", 128, 4),
+                   ("rowgather", 64, 8), ("rowgather", 256, 1)]:
+        B.configure(params)
         out = torch.full_like(ref, np.nan)
         B.numeric(op, q_cat, w_cat, out=out)
         B.sync_status()
         assert torch.equal(out, ref), f"{op} batched != per-mesh with params {params}"
-    B.set_params(256, 2)
+    B.configure(("pair", 256, 2))
 
 
 @pytest.mark.parametrize("op", ["MASS_W", "STIFF", "ELAS"])
@@ -82,8 +84,10 @@ def test_batched_vs_oracle_subset(batch, op):
         assert np.array_equal(rp.cpu().numpy(), orp) and np.array_equal(ci.cpu().numpy(), oci)
 
 
-def test_graph_capture_replay(batch):
+@pytest.mark.parametrize("kernel", ["pair", "rowgather"])
+def test_graph_capture_replay(batch, kernel):
     B, meshes, ws, q_cat, w_cat = batch
+    B.configure((kernel, 256, 2))
     offs = B.offsets("STIFF")
     out_s = torch.empty(offs.nnz[-1], dtype=torch.float64, device=DEV)
     out_m = torch.empty(offs.nnz[-1], dtype=torch.float64, device=DEV)
@@ -109,6 +113,7 @@ def test_graph_capture_replay(batch):
         torch.cuda.synchronize()
         assert torch.equal(out_s, ref_s), f"replay {rep} STIFF"
         assert torch.equal(out_m, ref_m), f"replay {rep} MASS_W"
+    B.configure(("pair", 256, 2))
 
 
 def test_autotuner(batch, tmp_path):
@@ -121,7 +126,7 @@ def test_autotuner(batch, tmp_path):
     assert B.params == params
     out = B.numeric("STIFF", q_cat, w_cat)
     assert torch.equal(out, ref)
-    B.set_params(64, 1)
+    B.configure(("rowgather", 64, 1))
     again, _ = autotune.tune(B, "STIFF", q_cat, w_cat, cache_path=cache)   # from the cache
     assert again == params and B.params == params
-    B.set_params(256, 2)
+    B.configure(("pair", 256, 2))
