@@ -11,7 +11,8 @@ Prints one JSON line.  Besides the headline numbers it carries:
                 the 8 TB/s peak (kernel time from HIP events on its stream)
   cpu_baseline  the CPU oracle on a bounded prefix of the same element list
   extra         elasticity on the same mesh, symbolic-phase time, batched vs
-                per-mesh launches, adjoint time (skipped with --no-extra)
+                per-mesh launches, the 2D 2048^2 workload (stiffness, weighted
+                mass, elasticity), adjoint time (skipped with --no-extra)
 """
 from __future__ import annotations
 
@@ -132,6 +133,28 @@ def extras(torch, femasm, mg, plan, q, stream, steps):
                       "batched_ms": tb * 1e3, "per_mesh_ms": tp * 1e3, "speedup": tp / tb,
                       "batched_elements_per_s": 2 * nel / tb, "create_s": t_create,
                       "params": list(batch.params), "tuning_ms": tune_times}
+    # the 2D workload: 2048^2 cells, stiffness / weighted mass / elasticity
+    c2 = mg.config_large_2d()
+    m2 = c2["mesh"]
+    p2 = femasm.Plan(torch.from_numpy(m2.me).to(q.device), m2.nq)
+    q2 = torch.from_numpy(m2.q).to(q.device)
+    w2 = torch.from_numpy(c2["w"]).to(q.device)
+    out["large_2d"] = {"nq": m2.nq, "nme": m2.nme}
+    for op2 in ("STIFF", "MASS_W", "ELAS"):
+        _, nnz2 = p2.query(op2)
+        v2 = torch.empty(nnz2, dtype=torch.float64, device=q.device)
+        code = femasm.FEM_OP[op2]
+        f2 = lambda: femasm.fem_assemble_numeric(p2.handle, code, q2.data_ptr(), w2.data_ptr(),
+                                                 1.0, 0.5, v2.data_ptr(), stream.cuda_stream)
+        _, per = time_launches(f2, stream, 10, 2)
+        t2 = statistics.mean(per) / 1e3
+        ab2 = algorithmic_bytes(2, m2.nq, m2.nme, nnz2, with_w=op2 == "MASS_W")
+        out["large_2d"][op2] = {"ms": t2 * 1e3, "elements_per_s": m2.nme / t2,
+                                "nnz_per_s": nnz2 / t2, "alg_GBps": ab2 / t2 / 1e9,
+                                "frac": ab2 / t2 / 1e9 / PEAK_HBM_GBS}
+        del v2
+    p2.sync_status()
+    del p2
     # adjoint on the 55^3 cube
     ca = mg.config_adjoint()
     m5 = ca["mesh"]

@@ -10,13 +10,17 @@
 // and, since E_mass_w is linear in w with coefficients from the magic
 // formula, with A = sum a, B = sum b, kk = |K| d!/(d+3)!:
 //   dJ/dw_c += kk [ A B + a_c B + A b_c + sum_e a_e b_e + 2 a_c b_c ].
-// One thread per vertex adds the contributions of its incident elements in
-// ascending element number (deterministic, no atomics).
+// Each vertex is handled by kLanes consecutive lanes: lane j adds the
+// contributions of its incidences j, j+kLanes, ... (ascending element
+// number), and the partial sums are combined as ((p0+p1)+(p2+p3)) through
+// lane shuffles, so the result is deterministic without atomics.
 #include "element.h"
 #include "femasm_impl.h"
 #include "rowgather.h"
 
 namespace femasm {
+
+constexpr int kLanes = 4;   // lanes per vertex
 
 template <int D>
 __global__ void __launch_bounds__(256)
@@ -24,16 +28,18 @@ __global__ void __launch_bounds__(256)
                uint32_t mask, double *__restrict__ dJdw, double *__restrict__ dJdq,
                int32_t *status) {
     constexpr int NL = D + 1;
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t gt = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t i = gt / kLanes;
+    const int j = int(gt % kLanes);
     const bool stiff = mask & (1u << FEM_OP_STIFF);
     const bool mass = mask & (1u << FEM_OP_MASS_W);
     int bad = 0;
-    if (i < mv.nq) {
-        double gw = 0.0, gq[D];
+    double gw = 0.0, gq[D];
 #pragma unroll
-        for (int x = 0; x < D; ++x) gq[x] = 0.0;
+    for (int x = 0; x < D; ++x) gq[x] = 0.0;
+    if (i < mv.nq) {
         const int64_t nq = mv.nq;
-        for (int t = mv.inc_ptr[i]; t < mv.inc_ptr[i + 1]; ++t) {
+        for (int t = mv.inc_ptr[i] + j; t < mv.inc_ptr[i + 1]; t += kLanes) {
             const uint32_t ea = mv.inc_elem[t];
             const int64_t e = ea & 0x3fffffffu;
             const int al = int(ea >> 30);
@@ -105,10 +111,19 @@ __global__ void __launch_bounds__(256)
                 gw += kk * (A * B + aa * B + A * bb + ab + 2.0 * aa * bb);
             }
         }
+    }
+    // ((p0 + p1) + (p2 + p3)): every lane of the group ends with the same bits
+#pragma unroll
+    for (int sh = 1; sh < kLanes; sh <<= 1) {
+        gw += __shfl_xor(gw, sh, kLanes);
+#pragma unroll
+        for (int x = 0; x < D; ++x) gq[x] += __shfl_xor(gq[x], sh, kLanes);
+    }
+    if (i < mv.nq && j == 0) {
         if (dJdw) dJdw[i] = gw;
         if (dJdq)
 #pragma unroll
-            for (int x = 0; x < D; ++x) dJdq[x * nq + i] = gq[x];
+            for (int x = 0; x < D; ++x) dJdq[x * mv.nq + i] = gq[x];
     }
     const unsigned long long any = __ballot(bad != 0);
     if (any != 0ull && (threadIdx.x & 63) == __ffsll((long long)any) - 1) atomicOr(status, bad);
@@ -135,7 +150,7 @@ extern "C" fem_status fem_assemble_backward(fem_plan plan, uint32_t op_mask, con
     mv.w = w;
     mv.values = nullptr;
     mv.nq = plan->nq;
-    const unsigned grid = unsigned((plan->nq + 255) / 256);
+    const unsigned grid = unsigned((plan->nq * kLanes + 255) / 256);
     if (plan->d == 2)
         hipLaunchKernelGGL(k_backward<2>, dim3(grid), dim3(256), 0, stream, mv, a, b, op_mask,
                            dJdw, dJdq, plan->status);
