@@ -335,9 +335,9 @@ fem_status upload_blocks(fem_plan_data *p, int d, int64_t nq, int64_t nme, const
         }
     }
     // pair layouts: FEMASM_PAIR_ROWS / FEMASM_ELAS_ROWS rows per block when
-    // set (16..128), else 56 (scalar operators) and 32 in 3D / 64 in 2D
+    // set (16..128), else 56 (scalar operators) and 48 in 3D / 64 in 2D
     // (elasticity); FEMASM_PAIR_SLOTS / FEMASM_ELAS_SLOTS (1, 2 or 4) tasks
-    // of 64 pairs per wavefront, else 2 and 1 (measured on the 128^3 cube).
+    // of 64 pairs per wavefront, else 2 (measured on the 128^3 cube).
     // A block also stops at 512 * slots CSR entries.
     auto env_int = [](const char *name, int dflt, int lo, int hi) {
         const char *e = getenv(name);
@@ -346,8 +346,8 @@ fem_status upload_blocks(fem_plan_data *p, int d, int64_t nq, int64_t nme, const
     auto slots_of = [](int v) { return v >= 4 ? 4 : (v <= 1 ? 1 : 2); };
     const int Rs = env_int("FEMASM_PAIR_ROWS", 56, 16, 128);
     const int Ss = slots_of(env_int("FEMASM_PAIR_SLOTS", 2, 1, 4));
-    const int Re = env_int("FEMASM_ELAS_ROWS", d == 3 ? 32 : 64, 16, 128);
-    const int Se = slots_of(env_int("FEMASM_ELAS_SLOTS", 1, 1, 4));
+    const int Re = env_int("FEMASM_ELAS_ROWS", d == 3 ? 48 : 64, 16, 128);
+    const int Se = slots_of(env_int("FEMASM_ELAS_SLOTS", 2, 1, 4));
     fem_status st = upload_pairs(p->pscal, Rs, Ss, true, d, nq, nme, me, rp, ci, ip, inc_k);
     if (st == FEM_OK) st = upload_pairs(p->pvec, Re, Se, false, d, nq, nme, me, rp, ci, ip, inc_k);
     if (st != FEM_OK) {

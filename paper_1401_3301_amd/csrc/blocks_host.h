@@ -16,7 +16,8 @@
 //     block (record t of row r at t*nrows + r) and padded with ~0u.
 // Blocks grow until they hold R rows or the next vertex would bring the
 // element count above kMaxBlockElems (or, when max_pairs > 0, the number of
-// CSR entries of the block's rows above max_pairs).  A mesh with a row longer than 32
+// CSR entries of the block's rows above max_pairs; when max_nodes > 0, the
+// number of touched vertices above max_nodes).  A mesh with a row longer than 32
 // entries, or a vertex whose own star exceeds the element cap, does not fit
 // these formats (ok == false).
 #pragma once
@@ -50,7 +51,7 @@ constexpr int kMaxRowLen = 32;
 inline BlockHost build_block_host(int d, int64_t nq, int64_t nme, const int32_t *me,
                                   const int32_t *rp, const int32_t *ci, const int64_t *ip,
                                   const int32_t *inc_k, int R, int nthreads,
-                                  int64_t max_pairs = 0) {
+                                  int64_t max_pairs = 0, int max_nodes = 0) {
     BlockHost H;
     const int NL = d + 1;
     for (int64_t i = 0; i < nq; ++i)
@@ -60,6 +61,7 @@ inline BlockHost build_block_host(int d, int64_t nq, int64_t nme, const int32_t 
     std::vector<int32_t> blk_of(nq, -1);
     std::vector<int32_t> queue;
     std::vector<int32_t> estamp(nme, -1);   // block that last counted the element
+    std::vector<int32_t> nstamp(max_nodes > 0 ? nq : 0, -1);   // ... the touched vertex
     queue.reserve(R);
     H.row_ptr.push_back(0);
     auto new_elems = [&](int32_t v, int b) {
@@ -67,9 +69,39 @@ inline BlockHost build_block_host(int d, int64_t nq, int64_t nme, const int32_t 
         for (int64_t t = ip[v]; t < ip[v + 1]; ++t) n += estamp[inc_k[t]] != b;
         return n;
     };
+    // touched vertices the elements of v would add (only when capped)
+    auto new_nodes = [&](int32_t v, int b) {
+        const int32_t prov = -2 - b;   // provisional mark, undone below
+        int n = 0;
+        for (int64_t t = ip[v]; t < ip[v + 1]; ++t) {
+            const int32_t k = inc_k[t];
+            if (estamp[k] == b) continue;
+            for (int a = 0; a < d + 1; ++a) {
+                const int32_t u = me[int64_t(a) * nme + k];
+                if (nstamp[u] != b && nstamp[u] != prov) {
+                    nstamp[u] = prov;
+                    ++n;
+                }
+            }
+        }
+        for (int64_t t = ip[v]; t < ip[v + 1]; ++t) {
+            const int32_t k = inc_k[t];
+            if (estamp[k] == b) continue;
+            for (int a = 0; a < d + 1; ++a) {
+                const int32_t u = me[int64_t(a) * nme + k];
+                if (nstamp[u] == prov) nstamp[u] = -1;
+            }
+        }
+        return n;
+    };
     auto take = [&](int32_t v, int b) {
         blk_of[v] = b;
-        for (int64_t t = ip[v]; t < ip[v + 1]; ++t) estamp[inc_k[t]] = b;
+        for (int64_t t = ip[v]; t < ip[v + 1]; ++t) {
+            const int32_t k = inc_k[t];
+            if (max_nodes > 0 && estamp[k] != b)
+                for (int a = 0; a < d + 1; ++a) nstamp[me[int64_t(a) * nme + k]] = b;
+            estamp[k] = b;
+        }
     };
     for (int64_t seed = 0; seed < nq; ++seed) {
         if (blk_of[seed] != -1 || rp[seed + 1] == rp[seed]) continue;
@@ -79,6 +111,8 @@ inline BlockHost build_block_host(int d, int64_t nq, int64_t nme, const int32_t 
         queue.push_back(int32_t(seed));
         int nel = new_elems(int32_t(seed), b);
         int64_t npairs = rp[seed + 1] - rp[seed];
+        int nnodes = max_nodes > 0 ? new_nodes(int32_t(seed), b) : 0;
+        if (max_nodes > 0 && nnodes > max_nodes) return H;
         take(int32_t(seed), b);
         size_t head = 0;
         bool full = false;
@@ -89,12 +123,15 @@ inline BlockHost build_block_host(int d, int64_t nq, int64_t nme, const int32_t 
                 if (blk_of[j] != -1 || rp[j + 1] == rp[j]) continue;
                 const int add = new_elems(j, b);
                 const int64_t addp = rp[j + 1] - rp[j];
-                if (nel + add > kMaxBlockElems || (max_pairs > 0 && npairs + addp > max_pairs)) {
+                const int addn = max_nodes > 0 ? new_nodes(j, b) : 0;
+                if (nel + add > kMaxBlockElems || (max_pairs > 0 && npairs + addp > max_pairs) ||
+                    (max_nodes > 0 && nnodes + addn > max_nodes)) {
                     full = true;
                     break;
                 }
                 nel += add;
                 npairs += addp;
+                nnodes += addn;
                 take(j, b);
                 queue.push_back(j);
             }

@@ -61,7 +61,7 @@ struct PairPlan {
     int32_t *desc = nullptr;      // [nb*24] block descriptors (pair.hip)
     int4 *rowinfo = nullptr;      // [rows] (rp[row], row length, local offset, 0)
     int32_t *nodes = nullptr;     // touched vertices, grouped by block
-    uint16_t *elem = nullptr;     // 4 local vertex ids per block element
+    uint32_t *elem = nullptr;     // 4 x 8-bit local vertex ids per block element
     int32_t *task_cnt = nullptr;  // entries per lane of each task
     int32_t *task_eoff = nullptr; // first entry of each task, relative to its block
     uint16_t *hdr = nullptr;      // [ntask*64] r | p << 7 per task lane (0xffff: empty)

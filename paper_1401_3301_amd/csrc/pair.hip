@@ -38,7 +38,8 @@ namespace {
 
 constexpr int kPairWG = kPairWaves * 64;
 constexpr int kEntSlots = 8192 / 8 / kPairWG;   // uint4 entry slots per thread: <= 8192 entries
-constexpr int kNodeSlots = 512 / kPairWG;       // touched vertices per thread: <= 512 per block
+constexpr int kNodeSlots = 512 / kPairWG;       // touched vertices per thread
+constexpr int kMaxPairNodes = 256;              // touched vertices per block: 8-bit local ids
 constexpr int kElemSlots = 1024 / kPairWG;      // elements per thread: <= 1023 (+ dummy)
 static_assert(kEntSlots == 2 && kNodeSlots == 1 && kElemSlots == 2, "512-thread workgroups");
 
@@ -46,7 +47,7 @@ struct PairView {
     const int32_t *desc;
     const int4 *rowinfo;
     const int32_t *nodes;
-    const uint2 *elem;
+    const uint32_t *elem;
     const int32_t *task_cnt;
     const int32_t *task_eoff;
     const uint16_t *hdr;
@@ -216,7 +217,7 @@ __global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, doubl
     // ---- prefetch registers
     // entry slots as named registers (an indexed array ends up in scratch)
     uint4 rent0 = make_uint4(0, 0, 0, 0), rent1 = rent0;
-    uint2 rel[kElemSlots];
+    uint32_t rel[kElemSlots];   // 4 x 8-bit local vertex ids per element
     int4 rrow = make_int4(0, 0, 0, 0);
     uint32_t rhd[S], rhd2[S];
     int rcntv = 0, reoffv = 0, rns = 0;   // task entry counts / offsets, lane s = slot s
@@ -257,7 +258,7 @@ __global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, doubl
 #pragma unroll
         for (int u = 0; u < kElemSlots; ++u) {
             const int e = u * kPairWG + tid;
-            rel[u] = e < d.ne ? pv.elem[d.e0 + e] : make_uint2(0u, 0u);
+            rel[u] = e < d.ne ? pv.elem[d.e0 + e] : 0u;
         }
         if (tid < d.nr) rrow = pv.rowinfo[d.r0 + tid];
     };
@@ -322,7 +323,7 @@ __global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, doubl
             cnt[s] = __builtin_amdgcn_readlane(rcntv, s);
             eoff[s] = __builtin_amdgcn_readlane(reoffv, s);
         }
-        uint2 el[kElemSlots];
+        uint32_t el[kElemSlots];
 #pragma unroll
         for (int u = 0; u < kElemSlots; ++u) el[u] = rel[u];
         // lists of the next block, vertex ids of the one after it and the
@@ -342,9 +343,9 @@ __global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, doubl
         for (int u = 0; u < kElemSlots; ++u) {
             const int e = u * kPairWG + tid;
             if (e < dc.ne) {
-                const uint2 vv = el[u];
-                const int v[4] = {int(vv.x & 0xffffu), int(vv.x >> 16), int(vv.y & 0xffffu),
-                                  int(vv.y >> 16)};
+                const uint32_t vv = el[u];
+                const int v[4] = {int(vv & 255u), int((vv >> 8) & 255u), int((vv >> 16) & 255u),
+                                  int(vv >> 24)};
                 double P[NL][D];
                 double wl[NL];
 #pragma unroll
@@ -493,7 +494,7 @@ hipError_t launch_pair_t(const PairPlan &P, const double *q, const double *w, do
     pv.desc = P.desc;
     pv.rowinfo = P.rowinfo;
     pv.nodes = P.nodes;
-    pv.elem = reinterpret_cast<const uint2 *>(P.elem);
+    pv.elem = P.elem;
     pv.task_cnt = P.task_cnt;
     pv.task_eoff = P.task_eoff;
     pv.hdr = P.hdr;
@@ -571,12 +572,17 @@ fem_status upload_pairs(PairPlan &P, int R, int slots, bool tri, int d, int64_t 
     P = PairPlan();
     const int64_t max_pairs = int64_t(64) * kPairWaves * slots;
     BlockHost H = build_block_host(d, nq, nme, me, rp, ci, ip, inc_k, std::min(R, 128), 16,
-                                   max_pairs);
+                                   max_pairs, kMaxPairNodes);
     if (!H.ok || H.nb == 0) return FEM_OK;   // row-gather kernel only
     PairHost PH = build_pair_host(H, d, rp, ci, kPairWaves, slots, 16, tri, dedup);
     if (!PH.ok || PH.max_ent > int64_t(kEntSlots) * kPairWG * 8 ||
-        H.max_nodes > kNodeSlots * kPairWG || H.max_elems + 1 > kElemSlots * kPairWG)
+        H.max_nodes > std::min(kMaxPairNodes, kNodeSlots * kPairWG) ||
+        H.max_elems + 1 > kElemSlots * kPairWG)
         return FEM_OK;
+    std::vector<uint32_t> elem8(H.elem.size() / 4);
+    for (size_t k = 0; k < elem8.size(); ++k)
+        elem8[k] = uint32_t(H.elem[4 * k]) | (uint32_t(H.elem[4 * k + 1]) << 8) |
+                   (uint32_t(H.elem[4 * k + 2]) << 16) | (uint32_t(H.elem[4 * k + 3]) << 24);
     const int nb = H.nb;
     std::vector<int32_t> desc(size_t(nb) * kDescInts), task_eoff(PH.task_ent.size());
     std::vector<int4> rowinfo(H.rows.size());
@@ -617,7 +623,7 @@ fem_status upload_pairs(PairPlan &P, int R, int slots, bool tri, int d, int64_t 
     if (st == FEM_OK) st = up(&P.desc, desc);
     if (st == FEM_OK) st = up(&P.rowinfo, rowinfo);
     if (st == FEM_OK) st = up(&P.nodes, H.nodes);
-    if (st == FEM_OK) st = up(&P.elem, H.elem);
+    if (st == FEM_OK) st = up(&P.elem, elem8);
     if (st == FEM_OK) st = up(&P.task_cnt, PH.task_cnt);
     if (st == FEM_OK) st = up(&P.task_eoff, task_eoff);
     if (st == FEM_OK) st = up(&P.hdr, PH.hdr);
@@ -689,7 +695,7 @@ fem_status concat_pairs(PairPlan &out, const std::vector<const PairPlan *> &part
     };
     alloc(&out.rowinfo, rows);
     alloc(&out.nodes, nodes);
-    alloc(&out.elem, 4 * elems);
+    alloc(&out.elem, elems);
     alloc(&out.task_cnt, tasks);
     alloc(&out.task_eoff, tasks);
     alloc(&out.hdr, 64 * tasks);
@@ -704,7 +710,7 @@ fem_status concat_pairs(PairPlan &out, const std::vector<const PairPlan *> &part
         };
         cp(out.rowinfo + r0, P.rowinfo, P.n_rows);
         cp(out.nodes + n0, P.nodes, P.n_nodes);
-        cp(out.elem + 4 * e0, P.elem, 4 * P.n_elems);
+        cp(out.elem + e0, P.elem, P.n_elems);
         cp(out.task_cnt + t0, P.task_cnt, P.n_tasks);
         cp(out.task_eoff + t0, P.task_eoff, P.n_tasks);
         cp(out.hdr + 64 * t0, P.hdr, 64 * P.n_tasks);
