@@ -1,0 +1,210 @@
+"""CPU checks of the library's host-side layout builders (blocks_host.h).
+
+The vertex-block layout (rows, touched vertices, block elements, 32-bit
+incidence records) and the vertex-pair lists built from it (tasks of 64
+pairs, entries in ascending element order, packed-triangle codes, mirror
+pairs, dummy padding, caps on rows / CSR entries / touched vertices) are
+compared with a brute force over the mesh written here in Python.  The
+builders are compiled from the library's own header through a small shim.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from paper_1401_3301_amd import meshgen as mg
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+PAD = 0xFFFF
+REC_PAD = 0xFFFFFFFF
+
+
+@pytest.fixture(scope="module")
+def shim(tmp_path_factory):
+    out = str(tmp_path_factory.mktemp("shim") / "host_layout_shim.so")
+    subprocess.check_call(["g++", "-O1", "-std=c++17", "-shared", "-fPIC", "-pthread",
+                           os.path.join(HERE, "host_layout_shim.cpp"), "-o", out])
+    return ctypes.CDLL(out)
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _pattern(mesh):
+    d, nq, nme = mesh.d, mesh.nq, mesh.nme
+    me = np.ascontiguousarray(mesh.me, dtype=np.int32)
+    nl = d + 1
+    r = np.repeat(me, nl, axis=0).ravel()
+    c = np.tile(me, (nl, 1)).ravel()
+    a = sp.csr_matrix((np.ones(len(r), np.int8), (r, c)), shape=(nq, nq))
+    a.sort_indices()
+    rp, ci = a.indptr.astype(np.int32), a.indices.astype(np.int32)
+    v = me.ravel()
+    k = np.tile(np.arange(nme, dtype=np.int32), nl)
+    o = np.lexsort((k, v))
+    inc_k = np.ascontiguousarray(k[o])
+    ip = np.zeros(nq + 1, np.int64)
+    ip[1:] = np.cumsum(np.bincount(v, minlength=nq))
+    return me, rp, ci, ip, inc_k
+
+
+def _build(shim, mesh, R, max_pairs=0, max_nodes=0, waves=8, slots=2, tri=False, dedup=True):
+    me, rp, ci, ip, inc_k = _pattern(mesh)
+    sizes = np.zeros(8, np.int64)
+    st = shim.hl_build(mesh.d, ctypes.c_int64(mesh.nq), ctypes.c_int64(mesh.nme), _p(me), _p(rp),
+                       _p(ci), _p(ip), _p(inc_k), R, ctypes.c_int64(max_pairs), max_nodes, waves,
+                       slots, int(tri), int(dedup), _p(sizes))
+    assert st == 0, f"builder refused the mesh (status {st})"
+    nb, nrows, nnodes, nelem, nrec, ntask, nent, _ = (int(x) for x in sizes)
+    B = dict(rows=np.zeros(nrows, np.int32), row_ptr=np.zeros(nb + 1, np.int32),
+             nodes=np.zeros(nnodes, np.int32), node_ptr=np.zeros(nb + 1, np.int32),
+             elem=np.zeros(nelem, np.uint16), elem_ptr=np.zeros(nb + 1, np.int32),
+             rec=np.zeros(nrec, np.uint32), rec_ptr=np.zeros(nb + 1, np.int64),
+             maxdeg=np.zeros(nb, np.int32))
+    shim.hl_blocks(*(_p(B[k]) for k in ("rows", "row_ptr", "nodes", "node_ptr", "elem",
+                                        "elem_ptr", "rec", "rec_ptr", "maxdeg")))
+    Pr = dict(wt=np.zeros(nb * (waves + 1), np.int32), task_cnt=np.zeros(ntask, np.int32),
+              task_ent=np.zeros(ntask, np.int64), hdr=np.zeros(ntask * 64, np.uint16),
+              hdr2=np.zeros(ntask * 64, np.uint16), ent=np.zeros(nent, np.uint16),
+              ent_ptr=np.zeros(nb + 1, np.int64))
+    shim.hl_pairs(*(_p(Pr[k]) for k in ("wt", "task_cnt", "task_ent", "hdr", "hdr2", "ent",
+                                        "ent_ptr")))
+    return (me, rp, ci, ip, inc_k), nb, B, Pr
+
+
+def _tri(a, b, nl):
+    lo, hi = min(a, b), max(a, b)
+    return lo * nl - lo * (lo - 1) // 2 + (hi - lo)
+
+
+def _check(mesh, built, R, max_pairs, max_nodes, waves, slots, tri, dedup):
+    (me, rp, ci, ip, inc_k), nb, B, Pr = built
+    d, nq, nme, nl = mesh.d, mesh.nq, mesh.nme, mesh.d + 1
+    used = np.diff(rp) > 0
+    owner = np.full(nq, -1)
+    covered = np.zeros(len(ci), np.int64)
+    for b in range(nb):
+        rows = B["rows"][B["row_ptr"][b]:B["row_ptr"][b + 1]]
+        assert 0 < len(rows) <= R and np.all(np.diff(rows) > 0)
+        assert np.all(owner[rows] == -1)
+        owner[rows] = b
+        lens = rp[rows + 1] - rp[rows]
+        if max_pairs:
+            assert lens.sum() <= max_pairs
+        # block elements: every element around a row, ascending
+        ks = np.unique(np.concatenate([inc_k[ip[i]:ip[i + 1]] for i in rows]))
+        el = B["elem"][4 * B["elem_ptr"][b]:4 * B["elem_ptr"][b + 1]].reshape(-1, 4)[:, :nl]
+        assert len(el) == len(ks) <= 1023
+        nodes = B["nodes"][B["node_ptr"][b]:B["node_ptr"][b + 1]]
+        assert np.array_equal(nodes[:len(rows)], rows)
+        halo = nodes[len(rows):]
+        assert np.all(np.diff(halo) > 0)
+        assert set(np.unique(me[:, ks])) == set(nodes.tolist())
+        if max_nodes:
+            assert len(nodes) <= max_nodes
+        assert np.array_equal(nodes[el], me[:, ks].T)
+        # incidence records, interleaved t * nrows + r
+        rec = B["rec"][B["rec_ptr"][b]:B["rec_ptr"][b + 1]]
+        nr, deg = len(rows), B["maxdeg"][b]
+        assert len(rec) == nr * deg
+        for r, i in enumerate(rows):
+            inc = inc_k[ip[i]:ip[i + 1]]
+            for t in range(deg):
+                x = int(rec[t * nr + r])
+                if t >= len(inc):
+                    assert x == REC_PAD
+                    continue
+                k = inc[t]
+                assert x & 1023 == np.searchsorted(ks, k)
+                al = (x >> 10) & 3
+                assert me[al, k] == i
+                cols = ci[rp[i]:rp[i + 1]]
+                for a in range(nl):
+                    assert cols[(x >> (12 + 5 * a)) & 31] == me[a, k]
+        # pair tasks: wavefront ranges, headers, entries
+        t0s = Pr["wt"][b * (waves + 1):(b + 1) * (waves + 1)]
+        assert np.all(np.diff(t0s) >= 0) and np.all(np.diff(t0s) <= slots)
+        ne_b = len(ks)
+        for t in range(t0s[0], t0s[-1]):
+            C, base = Pr["task_cnt"][t], Pr["task_ent"][t]
+            assert Pr["ent_ptr"][b] <= base and base + 64 * C <= Pr["ent_ptr"][b + 1]
+            for j in range(64):
+                h = int(Pr["hdr"][t * 64 + j])
+                lst = [int(Pr["ent"][base + u * 64 + j]) for u in range(C)]
+                if h == PAD:
+                    assert all(x == ne_b for x in lst) and Pr["hdr2"][t * 64 + j] == PAD
+                    continue
+                r, p = h & 127, h >> 7
+                i = rows[r]
+                col = ci[rp[i] + p]
+                covered[rp[i] + p] += 1
+                got = [x for x in lst if x != ne_b]
+                assert all(x == ne_b for x in lst[len(got):])
+                want = []
+                for ep, k in enumerate(ks):
+                    vs = list(me[:, k])
+                    if i in vs and col in vs:
+                        a, bb = vs.index(i), vs.index(col)
+                        code = (_tri(a, bb, nl) << 10) if tri else ((a << 10) | (bb << 12))
+                        want.append(ep | code)
+                assert got == want
+                h2 = int(Pr["hdr2"][t * 64 + j])
+                if h2 != PAD:
+                    assert dedup
+                    r2, p2 = h2 & 127, h2 >> 7
+                    assert r2 > r and rows[r2] == col and ci[rp[col] + p2] == i
+                    covered[rp[col] + p2] += 1
+                elif dedup:
+                    assert not (col in rows and np.searchsorted(rows, col) > r)
+    assert np.all(owner[used] >= 0) and np.all(owner[~used] == -1)
+    assert np.all(covered == 1), "every CSR entry is listed or mirrored exactly once"
+
+
+CASES = [
+    # (mesh, R, max_pairs, max_nodes, waves, slots, tri, dedup)
+    ("square12", 16, 0, 0, 8, 2, False, True),
+    ("square12", 40, 512, 60, 4, 4, True, True),
+    ("cube5_perm", 56, 1024, 256, 8, 2, True, True),
+    ("cube5_perm", 20, 512, 0, 8, 1, False, False),
+    ("cube4", 64, 1024, 70, 8, 2, False, True),
+    ("cube4", 8, 0, 0, 4, 1, True, False),
+]
+MESHES = {
+    "square12": lambda: mg.jittered_square(12, 0.2, seed=3),
+    "cube5_perm": lambda: mg.kuhn_cube(5, 0.15, seed=4, perm_seed=9),
+    "cube4": lambda: mg.kuhn_cube(4, 0.0, seed=0),
+}
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}-R{c[1]}-p{c[2]}-n{c[3]}-w{c[4]}s{c[5]}"
+                                              f"-{'tri' if c[6] else 'ab'}-{'dd' if c[7] else 'nodd'}"
+                                              for c in CASES])
+def test_layout_against_brute_force(shim, case):
+    name, R, max_pairs, max_nodes, waves, slots, tri, dedup = case
+    mesh = MESHES[name]()
+    built = _build(shim, mesh, R, max_pairs, max_nodes, waves, slots, tri, dedup)
+    _check(mesh, built, R, max_pairs, max_nodes, waves, slots, tri, dedup)
+
+
+def test_unused_vertices_and_refusals(shim):
+    # a vertex no element uses gets no block; a row longer than 32 entries
+    # (a fan of 40 triangles around vertex 0) makes the builder refuse
+    q = np.array([[0.0, 1.0, 0.0, 5.0], [0.0, 0.0, 1.0, 5.0]])
+    mesh = mg.Mesh(2, q, np.array([[0], [1], [2]], np.int32))
+    built = _build(shim, mesh, 16)
+    _check(mesh, built, 16, 0, 0, 8, 2, False, True)
+    assert built[1] == 1
+    n = 40
+    ang = np.linspace(0, 2 * np.pi, n, endpoint=False)
+    qf = np.vstack([np.r_[0.0, np.cos(ang)], np.r_[0.0, np.sin(ang)]])
+    mef = np.array([[0] * n, list(range(1, n + 1)), [j % n + 1 for j in range(1, n + 1)]],
+                   np.int32)
+    me, rp, ci, ip, inc_k = _pattern(mg.Mesh(2, qf, mef))
+    sizes = np.zeros(8, np.int64)
+    st = shim.hl_build(2, ctypes.c_int64(n + 1), ctypes.c_int64(n), _p(me), _p(rp), _p(ci),
+                       _p(ip), _p(inc_k), 16, ctypes.c_int64(0), 0, 8, 2, 0, 1, _p(sizes))
+    assert st == 1
