@@ -151,16 +151,12 @@ extern "C" fem_status fem_assemble_numeric(fem_plan plan, int32_t op, const doub
     if (plan->launch[M].rows_per_wg == 0) return FEM_ERR_OVERFLOW;
     hipError_t e = hipSuccess;
     // FEMASM_KERNEL=pair|block|rowgather forces one kernel family (A/B
-    // comparisons).  By default: stiffness and elasticity on the pair kernel,
-    // the two mass operators on the record-block kernel (measured faster for
-    // them: their element values are cheap and their incidence records are
-    // half the size of the pair lists), each falling back to the other and
-    // then to the row-gather kernel.
+    // comparisons).  By default the pair kernel (measured fastest for all
+    // four operators), else the record-block kernel (scalar operators), else
+    // the row-gather kernel.
     const char *sel = getenv("FEMASM_KERNEL");
     const bool any = !sel || !*sel;
-    const bool mass = op == FEM_OP_MASS || op == FEM_OP_MASS_W;
     if (plan->nq > 0) {
-        if (any && mass && launch_block(plan, op, q, w, values, stream, &e)) return hip_status(e);
         if ((any || !strcmp(sel, "pair")) && launch_pair(plan, op, q, w, lambda, mu, values, stream, &e))
             return hip_status(e);
         if ((any || !strcmp(sel, "block")) && launch_block(plan, op, q, w, values, stream, &e))
