@@ -48,6 +48,11 @@
  * contribution to J (imaginary step 1e-30, so no truncation or cancellation
  * error), accumulated per vertex in ascending element order.
  *
+ * P_k Lagrange mass (Appendix D): element matrix d! |K| C with the constant
+ * C of the paper's polynomial representation of the basis, evaluated in
+ * exact integer arithmetic; local numbering and the rest at the end of the
+ * file.
+ *
  * Status codes are this file's own and are restated, not included, by the
  * library under test: 0 ok, 1 bad argument, 2 bad index / repeated vertex,
  * 3 degenerate element (det B_k == 0), 4 overflow, 5 out of memory.
@@ -582,4 +587,252 @@ int oracle_element_matrix(int d, int op, const double *P, const double *wloc, do
     for (int i = 0; i < nloc; ++i)
         for (int j = 0; j < nloc; ++j) E_out[i * nloc + j] = E[i][j];
     return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* P_k Lagrange mass matrix (Appendix D).                                     */
+/*                                                                            */
+/* Local numbering I of the multi-indices alpha in N^{d+1}, |alpha| = k        */
+/* (alpha_i is the exponent of the barycentric coordinate of local vertex i): */
+/* local nodes 0..d are the vertices alpha = k e_i, the others follow in      */
+/* decreasing lexicographic order of (alpha_0, ..., alpha_d).                  */
+/*                                                                            */
+/* The basis function of alpha is prod_l prod_{j < alpha_l} (k lambda_l - j)/  */
+/* (j+1), a polynomial in the barycentric coordinates, so alpha! phi_alpha =   */
+/* prod_l p_{alpha_l}(lambda_l) with p_m(x) = prod_{j<m} (k x - j) has integer */
+/* coefficients; the magic formula then gives                                 */
+/*   int_K phi_alpha phi_beta = d! |K| C_{alpha,beta},                         */
+/*   C_{alpha,beta} = sum_{mu,nu} a_mu(alpha) a_nu(beta)                       */
+/*                    prod_i (mu_i + nu_i)! / (d + |mu| + |nu|)!,               */
+/* evaluated here exactly in 128-bit integers over the common denominator     */
+/* (d+2k)! alpha! beta!, and converted to double once at the end.             */
+/* ------------------------------------------------------------------------ */
+
+#define PK_MAXK 6
+#define PK_MAXN 84 /* (3+6)! / (3! 6!) */
+
+typedef __int128 i128;
+
+static int pk_count(int d, int k) {
+    int64_t n = 1;
+    for (int i = 1; i <= d; ++i) n = n * (k + i) / i;
+    return (int)n;
+}
+
+/* multi-indices in local order; returns their number */
+static int pk_enumerate(int d, int k, int alpha[PK_MAXN][MAXNL]) {
+    int all[PK_MAXN][MAXNL], n = 0, cur[MAXNL];
+    /* decreasing lexicographic: odometer from (k,0,..,0) downwards */
+    for (int a0 = k; a0 >= 0; --a0) {
+        cur[0] = a0;
+        if (d == 2) {
+            for (int a1 = k - a0; a1 >= 0; --a1) {
+                cur[1] = a1;
+                cur[2] = k - a0 - a1;
+                memcpy(all[n++], cur, sizeof(int) * MAXNL);
+            }
+        } else {
+            for (int a1 = k - a0; a1 >= 0; --a1)
+                for (int a2 = k - a0 - a1; a2 >= 0; --a2) {
+                    cur[1] = a1;
+                    cur[2] = a2;
+                    cur[3] = k - a0 - a1 - a2;
+                    memcpy(all[n++], cur, sizeof(int) * MAXNL);
+                }
+        }
+    }
+    int m = 0;
+    for (int v = 0; v <= d; ++v) { /* vertices first */
+        for (int i = 0; i <= d; ++i) alpha[m][i] = (i == v) ? k : 0;
+        ++m;
+    }
+    for (int t = 0; t < n; ++t) {
+        int isv = 0;
+        for (int i = 0; i <= d; ++i) isv |= all[t][i] == k;
+        if (!isv) memcpy(alpha[m++], all[t], sizeof(int) * MAXNL);
+    }
+    return m;
+}
+
+static i128 ifact(int n) {
+    i128 f = 1;
+    for (int i = 2; i <= n; ++i) f *= i;
+    return f;
+}
+
+/* pc[m][i] = coefficient of x^i in p_m(x) = prod_{j<m} (k x - j) */
+static void pk_univariate(int k, i128 pc[PK_MAXK + 1][PK_MAXK + 1]) {
+    memset(pc, 0, sizeof(i128) * (PK_MAXK + 1) * (PK_MAXK + 1));
+    pc[0][0] = 1;
+    for (int m = 1; m <= k; ++m)
+        for (int i = 0; i <= m; ++i) {
+            i128 c = -(i128)(m - 1) * pc[m - 1][i];  /* times (-(m-1)) */
+            if (i > 0) c += (i128)k * pc[m - 1][i - 1]; /* times k x */
+            pc[m][i] = c;
+        }
+}
+
+/* C (n x n, row-major, n = pk_count) */
+int oracle_pk_coeff(int d, int k, double *C) {
+    if (d < 2 || d > 3 || k < 1 || k > PK_MAXK || !C) return OR_ERR_ARG;
+    int alpha[PK_MAXN][MAXNL];
+    const int n = pk_enumerate(d, k, alpha);
+    i128 pc[PK_MAXK + 1][PK_MAXK + 1];
+    pk_univariate(k, pc);
+    const i128 top = ifact(d + 2 * k);
+    for (int x = 0; x < n; ++x)
+        for (int y = 0; y < n; ++y) {
+            const int *a = alpha[x], *b = alpha[y];
+            i128 num = 0;
+            int mu[MAXNL] = {0, 0, 0, 0}, nu[MAXNL];
+            /* odometer over mu <= a (componentwise) */
+            for (;;) {
+                i128 am = 1;
+                int smu = 0;
+                for (int i = 0; i <= d; ++i) { am *= pc[a[i]][mu[i]]; smu += mu[i]; }
+                if (am != 0) {
+                    memset(nu, 0, sizeof(nu));
+                    for (;;) {
+                        i128 bn = 1;
+                        int snu = 0;
+                        for (int i = 0; i <= d; ++i) { bn *= pc[b[i]][nu[i]]; snu += nu[i]; }
+                        if (bn != 0) {
+                            i128 w = top / ifact(d + smu + snu);
+                            for (int i = 0; i <= d; ++i) w *= ifact(mu[i] + nu[i]);
+                            num += am * bn * w;
+                        }
+                        int i = 0;
+                        while (i <= d && nu[i] == b[i]) nu[i++] = 0;
+                        if (i > d) break;
+                        nu[i] += 1;
+                    }
+                }
+                int i = 0;
+                while (i <= d && mu[i] == a[i]) mu[i++] = 0;
+                if (i > d) break;
+                mu[i] += 1;
+            }
+            i128 den = top;
+            for (int i = 0; i <= d; ++i) den *= ifact(a[i]) * ifact(b[i]);
+            C[x * n + y] = (double)((long double)num / (long double)den);
+        }
+    return OR_OK;
+}
+
+/* Local multi-indices (n x (d+1), row-major ints) in the numbering above. */
+int oracle_pk_alpha(int d, int k, int32_t *out) {
+    if (d < 2 || d > 3 || k < 1 || k > PK_MAXK || !out) return OR_ERR_ARG;
+    int alpha[PK_MAXN][MAXNL];
+    const int n = pk_enumerate(d, k, alpha);
+    for (int x = 0; x < n; ++x)
+        for (int i = 0; i <= d; ++i) out[x * (d + 1) + i] = alpha[x][i];
+    return OR_OK;
+}
+
+/* P_k mass matrix of a P_k mesh: me is n x nme (n = (d+k)!/(d!k!)), local
+ * nodes 0..d are the element's vertices (their coordinates define K).  Rows
+ * selected as in assemble_core (sel NULL = all nq rows).  Element matrix
+ * d! |K| C, triplets summed by `sparse` in ascending element order. */
+static int pk_core(int d, int k, int64_t nq, int64_t nme, const double *q, const int32_t *me,
+                   const int64_t *sel, int64_t nout, int64_t cap, int64_t *nnz_out,
+                   int64_t *row_ptr, int64_t *col_idx, double *val, double *absval) {
+    if (d < 2 || d > 3 || k < 1 || k > PK_MAXK || nq < 0 || nme < 0) return OR_ERR_ARG;
+    if (nme > 0 && (!me || !q)) return OR_ERR_ARG;
+    const int n = pk_count(d, k);
+    for (int64_t e = 0; e < nme; ++e)
+        for (int a = 0; a < n; ++a) {
+            const int32_t v = me[(int64_t)a * nme + e];
+            if (v < 0 || (int64_t)v >= nq) return OR_ERR_INDEX;
+            for (int b = 0; b < a; ++b)
+                if (me[(int64_t)b * nme + e] == v) return OR_ERR_INDEX;
+        }
+    double *C = (double *)malloc(sizeof(double) * n * n);
+    if (!C) return OR_ERR_NOMEM;
+    oracle_pk_coeff(d, k, C);
+    int64_t ntrip = 0;
+    for (int64_t e = 0; e < nme; ++e)
+        for (int a = 0; a < n; ++a)
+            if (!sel || sel[me[(int64_t)a * nme + e]]) ntrip += n;
+    triplet_t *T = (triplet_t *)malloc(sizeof(triplet_t) * (ntrip > 0 ? ntrip : 1));
+    if (!T) {
+        free(C);
+        return OR_ERR_NOMEM;
+    }
+    int64_t t = 0;
+    const double dfact = factorial(d);
+    for (int64_t e = 0; e < nme; ++e) {
+        int need = 0;
+        for (int a = 0; a < n && !need; ++a) need = !sel || sel[me[(int64_t)a * nme + e]];
+        if (!need) continue;
+        double P[MAXNL][MAXD], vol, G[MAXD][MAXNL];
+        int32_t vid[MAXNL];
+        gather_element(d, nq, nme, q, me, e, P, vid); /* local nodes 0..d: the vertices */
+        if (!element_geometry(d, P, &vol, G)) {
+            free(T);
+            free(C);
+            return OR_ERR_DEGENERATE;
+        }
+        for (int b = 0; b < n; ++b)
+            for (int a = 0; a < n; ++a) {
+                const int64_t r = me[(int64_t)a * nme + e];
+                if (sel && !sel[r]) continue;
+                T[t].row = sel ? sel[r] - 1 : r;
+                T[t].col = me[(int64_t)b * nme + e];
+                T[t].seq = t;
+                T[t].val = dfact * vol * C[a * n + b];
+                T[t].aval = fabs(T[t].val);
+                ++t;
+            }
+    }
+    free(C);
+    qsort(T, (size_t)t, sizeof(triplet_t), cmp_triplet);
+    int64_t nnz = 0;
+    for (int64_t i = 0; i < t; ++i)
+        if (i == 0 || T[i].row != T[i - 1].row || T[i].col != T[i - 1].col) ++nnz;
+    if (nnz > cap) {
+        free(T);
+        return OR_ERR_OVERFLOW;
+    }
+    for (int64_t r = 0; r <= nout; ++r) row_ptr[r] = 0;
+    int64_t s = -1;
+    for (int64_t i = 0; i < t; ++i) {
+        if (i == 0 || T[i].row != T[i - 1].row || T[i].col != T[i - 1].col) {
+            ++s;
+            col_idx[s] = T[i].col;
+            val[s] = 0.0;
+            if (absval) absval[s] = 0.0;
+            row_ptr[T[i].row + 1] += 1;
+        }
+        val[s] += T[i].val;
+        if (absval) absval[s] += T[i].aval;
+    }
+    for (int64_t r = 0; r < nout; ++r) row_ptr[r + 1] += row_ptr[r];
+    *nnz_out = nnz;
+    free(T);
+    return OR_OK;
+}
+
+int oracle_pk_mass(int d, int k, int64_t nq, int64_t nme, const double *q, const int32_t *me,
+                   int64_t cap, int64_t *nnz_out, int64_t *row_ptr, int64_t *col_idx,
+                   double *val, double *absval) {
+    return pk_core(d, k, nq, nme, q, me, NULL, nq, cap, nnz_out, row_ptr, col_idx, val, absval);
+}
+
+int oracle_pk_mass_rows(int d, int k, int64_t nq, int64_t nme, const double *q,
+                        const int32_t *me, int64_t nsel, const int64_t *rows, int64_t cap,
+                        int64_t *nnz_out, int64_t *row_ptr, int64_t *col_idx, double *val,
+                        double *absval) {
+    if (nsel < 0 || nq < 0) return OR_ERR_ARG;
+    int64_t *sel = (int64_t *)calloc((size_t)(nq > 0 ? nq : 1), sizeof(int64_t));
+    if (!sel) return OR_ERR_NOMEM;
+    for (int64_t s = 0; s < nsel; ++s) {
+        if (rows[s] < 0 || rows[s] >= nq || sel[rows[s]]) {
+            free(sel);
+            return OR_ERR_ARG;
+        }
+        sel[rows[s]] = s + 1;
+    }
+    int st = pk_core(d, k, nq, nme, q, me, sel, nsel, cap, nnz_out, row_ptr, col_idx, val, absval);
+    free(sel);
+    return st;
 }

@@ -7,6 +7,7 @@ data (Section 2), 0-based and row-major: q is (d, nq) float64, me is
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 
@@ -60,8 +61,14 @@ def _load():
                                              C.c_double, i64, P, i64, P, P, P, P, P]
         lib.oracle_grad.argtypes = [C.c_int, i64, i64, P, P, P, P, P, P, P, P, P, P]
         lib.oracle_element_matrix.argtypes = [C.c_int, C.c_int, P, P, C.c_double, C.c_double, P]
+        lib.oracle_pk_coeff.argtypes = [C.c_int, C.c_int, P]
+        lib.oracle_pk_alpha.argtypes = [C.c_int, C.c_int, P]
+        lib.oracle_pk_mass.argtypes = [C.c_int, C.c_int, i64, i64, P, P, i64, P, P, P, P, P]
+        lib.oracle_pk_mass_rows.argtypes = [C.c_int, C.c_int, i64, i64, P, P, i64, P, i64, P,
+                                            P, P, P, P]
         for f in (lib.oracle_validate, lib.oracle_assemble, lib.oracle_assemble_rows,
-                  lib.oracle_grad, lib.oracle_element_matrix):
+                  lib.oracle_grad, lib.oracle_element_matrix, lib.oracle_pk_coeff,
+                  lib.oracle_pk_alpha, lib.oracle_pk_mass, lib.oracle_pk_mass_rows):
             f.restype = C.c_int
         _lib = lib
     return _lib
@@ -166,3 +173,76 @@ def element_matrix(P, op: str, wloc=None, lam: float = 1.0, mu: float = 0.5):
     if st:
         raise OracleError(st, "element_matrix")
     return E
+
+
+# ---------------------------------------------------------------------------
+# P_k Lagrange mass (Appendix D)
+# ---------------------------------------------------------------------------
+
+def pk_ndfe(d: int, k: int) -> int:
+    """Local P_k nodes of a d-simplex, (d+k)!/(d! k!)."""
+    return math.comb(d + k, d)
+
+
+def pk_alpha(d: int, k: int) -> np.ndarray:
+    """Multi-indices of the local nodes, (ndfe, d+1), in the oracle's numbering."""
+    out = np.zeros((pk_ndfe(d, k), d + 1), np.int32)
+    st = _load().oracle_pk_alpha(d, k, _ptr(out))
+    if st:
+        raise OracleError(st, "pk_alpha")
+    return out
+
+
+def pk_coeff(d: int, k: int) -> np.ndarray:
+    """C with int_K phi_a phi_b = d! |K| C[a, b] (local numbering of pk_alpha)."""
+    n = pk_ndfe(d, k)
+    out = np.zeros((n, n))
+    st = _load().oracle_pk_coeff(d, k, _ptr(out))
+    if st:
+        raise OracleError(st, "pk_coeff")
+    return out
+
+
+def pk_mass(q, me, k: int, nq: int | None = None):
+    """P_k mass matrix as CSR (row_ptr, col_idx, val, absval); me is (ndfe, nme)."""
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    me = np.ascontiguousarray(me, dtype=np.int32)
+    d = q.shape[0]
+    nq = q.shape[1] if nq is None else nq
+    nme = me.shape[1]
+    cap = max(1, nme * me.shape[0] ** 2)
+    rp = np.zeros(nq + 1, np.int64)
+    ci = np.zeros(cap, np.int64)
+    v = np.zeros(cap, np.float64)
+    av = np.zeros(cap, np.float64)
+    nnz = C.c_int64(0)
+    st = _load().oracle_pk_mass(d, k, nq, nme, _ptr(q), _ptr(me), cap, C.byref(nnz), _ptr(rp),
+                                _ptr(ci), _ptr(v), _ptr(av))
+    if st:
+        raise OracleError(st, "pk_mass")
+    n = nnz.value
+    return rp, ci[:n].copy(), v[:n].copy(), av[:n].copy()
+
+
+def pk_mass_rows(q, me, k: int, rows):
+    """P_k mass matrix restricted to the global rows listed in ``rows``."""
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    me = np.ascontiguousarray(me, dtype=np.int32)
+    d, nq, nme = q.shape[0], q.shape[1], me.shape[1]
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    cap = max(1, len(rows) * 256)
+    while True:
+        rp = np.zeros(len(rows) + 1, np.int64)
+        ci = np.zeros(cap, np.int64)
+        v = np.zeros(cap, np.float64)
+        av = np.zeros(cap, np.float64)
+        nnz = C.c_int64(0)
+        st = _load().oracle_pk_mass_rows(d, k, nq, nme, _ptr(q), _ptr(me), len(rows), _ptr(rows),
+                                         cap, C.byref(nnz), _ptr(rp), _ptr(ci), _ptr(v), _ptr(av))
+        if st == 4:
+            cap *= 4
+            continue
+        if st:
+            raise OracleError(st, "pk_mass_rows")
+        n = nnz.value
+        return rp, ci[:n].copy(), v[:n].copy(), av[:n].copy()

@@ -28,6 +28,18 @@ Rules (all seeds feed ``numpy.random.default_rng``):
   axes, with vertices c, c+e_p0, c+e_p0+e_p1, c+(1,1,1); the permutations are
   taken in lexicographic order, elements cube by cube (cubes in id order).
   ``perm_seed`` optionally permutes the element order (columns of ``me``).
+* P_k meshes ``pk_mesh(mesh, k)`` (Appendix D): the nodal points of P_k
+  Lagrange elements on the straight simplices of a P1 mesh.  Local node
+  ``I(alpha)`` of an element is the multi-index ``alpha`` in N^(d+1),
+  ``|alpha| = k`` (``alpha_i`` pairs with local vertex ``i``): indices
+  ``0..d`` are the vertices ``alpha = k e_i``, the others follow in
+  decreasing lexicographic order of ``(alpha_0, ..., alpha_d)``.  The node of
+  ``alpha`` lies at ``sum_i alpha_i P_i / k``.  Global ids: the P1 vertices
+  keep theirs; every other node is identified by its support (the vertices
+  with ``alpha_i > 0`` and their exponents), so neighbouring elements share
+  it, and numbered after the vertices in increasing order of that support
+  (smallest vertex id first).  Its coordinates are those computed by the
+  lowest-numbered element that has it.
 """
 from __future__ import annotations
 
@@ -40,7 +52,7 @@ import numpy as np
 __all__ = [
     "Mesh", "jittered_square", "kuhn_cube", "lognormal_field", "normal_field",
     "config_small_2d", "config_large_2d", "config_large_3d", "config_batch",
-    "config_adjoint", "interior_mask",
+    "config_adjoint", "interior_mask", "pk_local_indices", "pk_mesh", "config_pk",
 ]
 
 
@@ -147,6 +159,68 @@ def kuhn_cube(n: int, jit: float = 0.0, seed: int = 0,
     return Mesh(3, np.ascontiguousarray(q), me, n, meta)
 
 
+def pk_local_indices(d: int, k: int) -> list[tuple[int, ...]]:
+    """Local numbering of the P_k nodes of a d-simplex: the list of multi-indices
+    alpha (length d+1, sum k), vertices first, then decreasing lexicographic."""
+    if k < 1:
+        raise ValueError("k >= 1")
+    allm = [a for a in itertools.product(range(k, -1, -1), repeat=d + 1) if sum(a) == k]
+    verts = [tuple(k if i == v else 0 for i in range(d + 1)) for v in range(d + 1)]
+    rest = [a for a in allm if a not in verts]     # product order is decreasing lex
+    return verts + rest
+
+
+def pk_mesh(mesh: Mesh, k: int) -> Mesh:
+    """P_k mesh on the simplices of the P1 mesh ``mesh`` (rules in the module
+    docstring).  ``me`` has shape (n_dfe, nme), n_dfe = (d+k)!/(d! k!)."""
+    d, nq1, nme = mesh.d, mesh.nq, mesh.nme
+    loc = pk_local_indices(d, k)
+    ndfe = len(loc)
+    me1 = mesh.me.astype(np.int64)
+    big = np.iinfo(np.int64).max
+    # support key of every (element, non-vertex local node): (vertex, exponent)
+    # pairs sorted by vertex id, padded with (big, 0)
+    keys = np.full((ndfe - d - 1, nme, 2 * (d + 1)), big, dtype=np.int64)
+    for r, a in enumerate(loc[d + 1:]):
+        verts = np.where(np.array(a)[:, None] > 0, me1, big)          # (d+1, nme)
+        expo = np.broadcast_to(np.array(a, dtype=np.int64)[:, None], (d + 1, nme))
+        order = np.argsort(verts, axis=0, kind="stable")
+        vs = np.take_along_axis(verts, order, axis=0)
+        es = np.take_along_axis(expo, order, axis=0)
+        es = np.where(vs == big, 0, es)
+        keys[r, :, 0::2] = vs.T
+        keys[r, :, 1::2] = es.T
+    flat = keys.reshape(-1, 2 * (d + 1))
+    uniq, inv = np.unique(flat, axis=0, return_inverse=True)
+    inv = inv.reshape(ndfe - d - 1, nme)
+    nq = nq1 + len(uniq)
+    me = np.empty((ndfe, nme), dtype=np.int32)
+    me[:d + 1] = mesh.me
+    me[d + 1:] = nq1 + inv
+    q = np.empty((d, nq), dtype=np.float64)
+    q[:, :nq1] = mesh.q
+    # first element (lowest number) holding each new node, and its local row
+    flat_id = inv.ravel()
+    elem_of = np.tile(np.arange(nme), ndfe - d - 1)
+    row_of = np.repeat(np.arange(ndfe - d - 1), nme)
+    first = np.full(len(uniq), np.iinfo(np.int64).max)
+    np.minimum.at(first, flat_id, elem_of * (ndfe - d - 1) + row_of)
+    fe, fr = first // (ndfe - d - 1), first % (ndfe - d - 1)
+    for r, a in enumerate(loc[d + 1:]):
+        sel = fr == r
+        if not np.any(sel):
+            continue
+        e = fe[sel]
+        pts = np.zeros((d, len(e)))
+        for i in range(d + 1):
+            if a[i]:
+                pts += a[i] * mesh.q[:, mesh.me[i, e]]
+        q[:, nq1 + np.nonzero(sel)[0]] = pts / k
+    meta = dict(mesh.meta)
+    meta["k"] = k
+    return Mesh(d, np.ascontiguousarray(q), me, mesh.n, meta)
+
+
 def lognormal_field(nq: int, seed: int, sigma: float = 0.5) -> np.ndarray:
     """Nodal weight w_i = exp(sigma * Z_i), Z ~ N(0,1) (median 1)."""
     z = np.random.default_rng(seed).standard_normal(nq)
@@ -212,6 +286,13 @@ def config_batch(count: int = 256, seed: int = 4) -> dict:
         ws.append(lognormal_field(m.nq, seed=5000 + b))
     return {"name": f"batch{count}_mixed", "meshes": meshes, "w": ws,
             "ops": ("MASS_W", "STIFF")}
+
+
+def config_pk(k: int, n: int, jit: float = 0.15, seed: int = 6) -> dict:
+    """3D P_k mass (Appendix D, Table D.1): P_k nodes on a jittered Kuhn cube
+    of n^3 cubes, elements in cube order."""
+    m = pk_mesh(kuhn_cube(n, jit, seed=seed), k)
+    return {"name": f"cube{n}_3d_p{k}", "mesh": m, "k": k, "ops": ("MASS",)}
 
 
 def config_adjoint(n: int = 55) -> dict:
