@@ -219,6 +219,64 @@ fem_status fem_batch_sync_status(fem_batch batch, hipStream_t stream);
 /* Frees the batch and its plans (NULL is ignored). */
 void fem_batch_destroy(fem_batch batch);
 
+/*
+ * P_k Lagrange mass matrix (Appendix D: the extension of the vectorised
+ * assembly to P_k elements, k >= 1, on straight-sided simplices).
+ *
+ * Mesh arrays of a "P_k mesh": q [d][nq] holds the coordinates of every P_k
+ * node, me [N][nme] (N = (d+k)!/(d! k!)) the N nodes of each element in the
+ * local numbering I of the multi-indices alpha in N^(d+1), |alpha| = k
+ * (alpha_i is the exponent of the barycentric coordinate of local vertex i):
+ * local nodes 0..d are the vertices alpha = k e_i, the remaining
+ * multi-indices follow in decreasing lexicographic order of
+ * (alpha_0, ..., alpha_d).  Node alpha lies at sum_i alpha_i q^i / k; only
+ * the vertex rows 0..d of me are used for geometry.
+ *
+ * The element matrix is d! |K| C with C[a][b] the integral of the product of
+ * the basis functions of local nodes a and b over K divided by d! |K|
+ * (formula of Appendix D, from the polynomial representation of the basis
+ * in barycentric coordinates and the magic formula of Section 2).  Entries
+ * are summed in ascending element number, starting from 0.0 (bitwise
+ * reproducible), into the CSR pattern of all node pairs sharing an element.
+ */
+typedef struct fem_pk_plan_s *fem_pk_plan;
+
+/* Symbolic phase of the P_k mass: validates me, builds the CSR pattern and
+ * the per-entry contribution lists.  Synchronous.
+ *   d    2 or 3;  k  1..6
+ *   nq   number of P_k nodes;  nme  number of elements
+ *   me   device, N*nme int32 (layout above)
+ * Errors: FEM_ERR_ARG, FEM_ERR_INDEX (index out of range or a node repeated
+ * within an element), FEM_ERR_OVERFLOW (nnz >= 2^31, N*nme >= 2^31, or a
+ * tile of 256 consecutive CSR entries drawing on more than 4096 elements or
+ * 65535 contributions), FEM_ERR_NOMEM, FEM_ERR_DEVICE. */
+fem_status fem_pk_symbolic(int32_t d, int32_t k, int64_t nq, int64_t nme, const int32_t *me,
+                           hipStream_t stream, fem_pk_plan *out);
+
+/* Rows (= nq), nnz and N of the plan.  Host out-pointers, any may be NULL. */
+fem_status fem_pk_query(fem_pk_plan plan, int64_t *nrows, int64_t *nnz, int32_t *ndfe);
+
+/* Copies the CSR pattern into row_ptr[nq+1], col_idx[nnz] (device).
+ * Enqueued on `stream`. */
+fem_status fem_pk_pattern(fem_pk_plan plan, int32_t *row_ptr, int32_t *col_idx,
+                          hipStream_t stream);
+
+/* CSR values of the P_k mass matrix for node coordinates q (device, d*nq
+ * doubles) into values (device, nnz doubles, fully overwritten).  Two
+ * kernels on `stream` (element volumes, then the entry sums); no host
+ * synchronisation, no allocation.  A degenerate element (det B_K == 0)
+ * contributes 0 and sets the plan's status word (fem_pk_sync_status).
+ * Concurrent calls with one plan race on its volume work array. */
+fem_status fem_pk_mass(fem_pk_plan plan, const double *q, double *values, hipStream_t stream);
+
+/* Synchronises `stream`, reads and clears the plan's status word:
+ * FEM_ERR_DEGENERATE if a fem_pk_mass call since the last read met a
+ * degenerate element, else FEM_OK. */
+fem_status fem_pk_sync_status(fem_pk_plan plan, hipStream_t stream);
+
+/* Frees the plan (NULL is ignored).  Work using it must have completed. */
+void fem_pk_destroy(fem_pk_plan plan);
+
 #ifdef __cplusplus
 }
 #endif

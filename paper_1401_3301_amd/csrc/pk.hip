@@ -1,0 +1,273 @@
+// P_k Lagrange mass matrix (Appendix D of the paper): symbolic phase and
+// numeric kernels.
+//
+// For P_k Lagrange elements on straight simplices the element mass matrix is
+// d! |K| C, with C an N x N constant (N = (d+k)!/(d! k!)) that follows from
+// writing each basis function as a polynomial in the barycentric coordinates
+// and integrating products with the magic formula of Section 2.  The numeric
+// phase therefore needs, per element, only d! |K| = |det B_K| (from its d+1
+// vertices), and per CSR entry the (element, local entry) pairs that feed it.
+//
+// Local numbering of an element's N nodes (the multi-indices alpha with
+// |alpha| = k, alpha_i the exponent of the barycentric coordinate of local
+// vertex i): local nodes 0..d are the vertices alpha = k e_i, the others
+// follow in decreasing lexicographic order of (alpha_0, ..., alpha_d).
+//
+// Plan (built once from the connectivity, layout in pk_host.h): the CSR
+// pattern, CSR entries cut into tiles of kPkTile consecutive entries with the
+// distinct elements of each tile and per entry its contributions (tile-local
+// element, packed-triangle index of (a, b)) in ascending element number, the
+// vertex rows of the connectivity (geometry) and C (packed upper triangle).
+// Numeric phase: k_pk_vol writes |det B_K| for every element; k_pk_mass, a
+// persistent kernel, keeps C in LDS, and for each tile stages the volumes of
+// its elements in LDS, then every lane sums its entry's items from 0.0 in
+// ascending element order and writes the value (coalesced).
+#include <algorithm>
+#include <cmath>
+#include <memory>
+#include <thread>
+
+#include "element.h"
+#include "femasm_impl.h"
+#include "pk_host.h"
+
+namespace femasm {
+
+struct fem_pk_data {
+    int d = 0, k = 0, n = 0, ntri = 0;
+    int64_t nq = 0, nme = 0, nnz = 0, ntiles = 0, nitems = 0;
+    int max_tile_elems = 0;
+    int device = 0;
+    int32_t *rp = nullptr, *ci = nullptr;
+    int32_t *gme = nullptr;         // (d+1) x nme vertex ids
+    int64_t *tile_item = nullptr;   // [ntiles+1] first item of each tile
+    int32_t *tile_elem_ptr = nullptr;   // [ntiles+1]
+    int32_t *tile_elem = nullptr;   // distinct elements of each tile, ascending
+    uint16_t *coff = nullptr;       // [ntiles*kPkTile] first item of each entry, tile-relative
+    uint32_t *item = nullptr;       // tile-local element | tri code << 16
+    double *ctri = nullptr;         // [ntri]
+    double *vol = nullptr;          // [nme] |det B_K| (work array of the numeric phase)
+    int32_t *status = nullptr;
+};
+
+namespace {
+
+template <class T>
+fem_status pk_upload(T **dst, const std::vector<T> &src) {
+    *dst = nullptr;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(dst), sizeof(T) * std::max<size_t>(src.size(), 1));
+    if (e != hipSuccess) {
+        *dst = nullptr;
+        return hip_status(e);
+    }
+    if (!src.empty()) e = hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
+    return hip_status(e);
+}
+
+void pk_free(fem_pk_data *p) {
+    void *ptrs[] = {p->rp,   p->ci,   p->gme,  p->tile_item, p->tile_elem_ptr, p->tile_elem,
+                    p->coff, p->item, p->ctri, p->vol,       p->status};
+    for (void *x : ptrs)
+        if (x) (void)hipFree(x);
+}
+
+// ---------------------------------------------------------------- kernels
+template <int D>
+__global__ __launch_bounds__(256) void k_pk_vol(const int32_t *__restrict__ gme, int64_t nme,
+                                                const double *__restrict__ q, int64_t nq,
+                                                double *__restrict__ vol, int32_t *status) {
+    const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (e >= nme) return;
+    double P[D + 1][D];
+#pragma unroll
+    for (int a = 0; a <= D; ++a) {
+        const int64_t v = gme[a * nme + e];
+#pragma unroll
+        for (int x = 0; x < D; ++x) P[a][x] = q[x * nq + v];
+    }
+    Elem<D> E;
+    elem_geometry(P, E);
+    vol[e] = fabs(E.det);
+    if (E.det == 0.0) atomicOr(status, 1);
+}
+
+__global__ __launch_bounds__(kPkTile) void k_pk_mass(
+    const int64_t *__restrict__ tile_item, const int32_t *__restrict__ tile_elem_ptr,
+    const int32_t *__restrict__ tile_elem, const uint16_t *__restrict__ coff,
+    const uint32_t *__restrict__ item, const double *__restrict__ ctri, int ntri,
+    const double *__restrict__ vol, int64_t ntiles, int64_t nnz, double *__restrict__ values) {
+    extern __shared__ double lds[];
+    double *sc = lds;               // C, packed triangle
+    double *sv = lds + ntri;        // volumes of the tile's elements
+    for (int t = threadIdx.x; t < ntri; t += kPkTile) sc[t] = ctri[t];
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int32_t e0 = tile_elem_ptr[tile], ne = tile_elem_ptr[tile + 1] - e0;
+        __syncthreads();            // previous tile's reads of sv are done
+        for (int t = threadIdx.x; t < ne; t += kPkTile) sv[t] = vol[tile_elem[e0 + t]];
+        __syncthreads();
+        const int64_t s = tile * kPkTile + threadIdx.x;
+        if (s < nnz) {
+            const int64_t i0 = tile_item[tile];
+            const int c0 = coff[s];
+            const int c1 = threadIdx.x + 1 < kPkTile && s + 1 < nnz ? int(coff[s + 1])
+                                                                     : int(tile_item[tile + 1] - i0);
+            const uint32_t *it = item + i0;
+            double acc = 0.0;
+            int c = c0;
+            for (; c + 4 <= c1; c += 4) {
+                const uint32_t x0 = it[c], x1 = it[c + 1], x2 = it[c + 2], x3 = it[c + 3];
+                acc = fma(sv[x0 & 0xffffu], sc[x0 >> 16], acc);
+                acc = fma(sv[x1 & 0xffffu], sc[x1 >> 16], acc);
+                acc = fma(sv[x2 & 0xffffu], sc[x2 >> 16], acc);
+                acc = fma(sv[x3 & 0xffffu], sc[x3 >> 16], acc);
+            }
+            for (; c < c1; ++c) {
+                const uint32_t x = it[c];
+                acc = fma(sv[x & 0xffffu], sc[x >> 16], acc);
+            }
+            values[s] = acc;
+        }
+    }
+}
+
+int pk_grid(size_t lds, int64_t ntiles) {
+    static thread_local int cached = 0;
+    static thread_local size_t cached_lds = 0;
+    if (cached == 0 || cached_lds != lds) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_pk_mass),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(&k_pk_mass),
+                                                         kPkTile, lds) != hipSuccess || n < 1)
+            n = 1;
+        cached = n;
+        cached_lds = lds;
+    }
+    int dev = 0, cus = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (cus < 1) cus = 1;
+    return int(std::max<int64_t>(1, std::min<int64_t>(ntiles, int64_t(cached) * cus)));
+}
+
+}  // namespace
+}  // namespace femasm
+
+using namespace femasm;
+
+struct fem_pk_plan_s : femasm::fem_pk_data {};
+
+extern "C" fem_status fem_pk_symbolic(int32_t d, int32_t k, int64_t nq, int64_t nme,
+                                      const int32_t *me, hipStream_t stream, fem_pk_plan *out) {
+    if (!out || (d != 2 && d != 3) || k < 1 || k > kPkMaxK || nq < 0 || nme < 0 ||
+        (nme > 0 && !me))
+        return FEM_ERR_ARG;
+    const int n = int(pk_nodes(d, k).size());
+    if (int64_t(n) * nme >= (int64_t(1) << 31) || nq >= (int64_t(1) << 31) - 1)
+        return FEM_ERR_OVERFLOW;
+    std::vector<int32_t> hme(size_t(n) * nme);
+    if (nme > 0) {
+        hipError_t e = hipMemcpyAsync(hme.data(), me, sizeof(int32_t) * hme.size(),
+                                      hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return hip_status(e);
+    }
+    unsigned hc = std::thread::hardware_concurrency();
+    PkHost H = build_pk_host(d, k, nq, nme, hme.data(), int(std::max(1u, std::min(hc ? hc : 4u, 16u))));
+    if (H.status == 2) return FEM_ERR_INDEX;
+    if (H.status != 0) return FEM_ERR_OVERFLOW;
+    std::vector<int32_t> gme(size_t(d + 1) * nme);
+    std::copy(hme.begin(), hme.begin() + gme.size(), gme.begin());
+
+    std::unique_ptr<fem_pk_plan_s> p(new fem_pk_plan_s());
+    p->d = d;
+    p->k = k;
+    p->n = n;
+    p->ntri = H.ntri;
+    p->nq = nq;
+    p->nme = nme;
+    p->nnz = H.nnz;
+    p->ntiles = H.ntiles;
+    p->nitems = int64_t(H.item.size());
+    p->max_tile_elems = H.max_tile_elems;
+    (void)hipGetDevice(&p->device);
+    fem_status st = pk_upload(&p->rp, H.rp);
+    if (st == FEM_OK) st = pk_upload(&p->ci, H.ci);
+    if (st == FEM_OK) st = pk_upload(&p->gme, gme);
+    if (st == FEM_OK) st = pk_upload(&p->tile_item, H.tile_item);
+    if (st == FEM_OK) st = pk_upload(&p->tile_elem_ptr, H.tile_elem_ptr);
+    if (st == FEM_OK) st = pk_upload(&p->tile_elem, H.tile_elem);
+    if (st == FEM_OK) st = pk_upload(&p->coff, H.coff);
+    if (st == FEM_OK) st = pk_upload(&p->item, H.item);
+    if (st == FEM_OK) st = pk_upload(&p->ctri, H.ctri);
+    if (st == FEM_OK) st = pk_upload(&p->vol, std::vector<double>(size_t(nme), 0.0));
+    if (st == FEM_OK) st = pk_upload(&p->status, std::vector<int32_t>(1, 0));
+    if (st != FEM_OK) {
+        pk_free(p.get());
+        return st;
+    }
+    *out = p.release();
+    return FEM_OK;
+}
+
+extern "C" fem_status fem_pk_query(fem_pk_plan plan, int64_t *nrows, int64_t *nnz, int32_t *ndfe) {
+    if (!plan) return FEM_ERR_ARG;
+    if (nrows) *nrows = plan->nq;
+    if (nnz) *nnz = plan->nnz;
+    if (ndfe) *ndfe = plan->n;
+    return FEM_OK;
+}
+
+extern "C" fem_status fem_pk_pattern(fem_pk_plan plan, int32_t *row_ptr, int32_t *col_idx,
+                                     hipStream_t stream) {
+    if (!plan || !row_ptr || (plan->nnz > 0 && !col_idx)) return FEM_ERR_ARG;
+    hipError_t e = hipMemcpyAsync(row_ptr, plan->rp, sizeof(int32_t) * (plan->nq + 1),
+                                  hipMemcpyDeviceToDevice, stream);
+    if (e == hipSuccess && plan->nnz > 0)
+        e = hipMemcpyAsync(col_idx, plan->ci, sizeof(int32_t) * plan->nnz, hipMemcpyDeviceToDevice,
+                           stream);
+    return hip_status(e);
+}
+
+extern "C" fem_status fem_pk_mass(fem_pk_plan plan, const double *q, double *values,
+                                  hipStream_t stream) {
+    if (!plan || (plan->nme > 0 && !q) || (plan->nnz > 0 && !values)) return FEM_ERR_ARG;
+    if (plan->nnz == 0) return FEM_OK;
+    if (plan->nme > 0) {
+        const unsigned g = unsigned((plan->nme + 255) / 256);
+        if (plan->d == 2)
+            hipLaunchKernelGGL(k_pk_vol<2>, dim3(g), dim3(256), 0, stream, plan->gme, plan->nme, q,
+                               plan->nq, plan->vol, plan->status);
+        else
+            hipLaunchKernelGGL(k_pk_vol<3>, dim3(g), dim3(256), 0, stream, plan->gme, plan->nme, q,
+                               plan->nq, plan->vol, plan->status);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_status(e);
+    }
+    const size_t lds = sizeof(double) * (size_t(plan->ntri) + size_t(std::max(plan->max_tile_elems, 1)));
+    if (lds > 160 * 1024) return FEM_ERR_OVERFLOW;
+    const int grid = pk_grid(lds, plan->ntiles);
+    hipLaunchKernelGGL(k_pk_mass, dim3(grid), dim3(kPkTile), lds, stream, plan->tile_item,
+                       plan->tile_elem_ptr, plan->tile_elem, plan->coff, plan->item, plan->ctri,
+                       plan->ntri, plan->vol, plan->ntiles, plan->nnz, values);
+    return hip_status(hipGetLastError());
+}
+
+extern "C" fem_status fem_pk_sync_status(fem_pk_plan plan, hipStream_t stream) {
+    if (!plan) return FEM_ERR_ARG;
+    int32_t word = 0;
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e == hipSuccess) e = hipMemcpy(&word, plan->status, sizeof(int32_t), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && word != 0) {
+        const int32_t zero = 0;
+        e = hipMemcpy(plan->status, &zero, sizeof(int32_t), hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) return hip_status(e);
+    return word ? FEM_ERR_DEGENERATE : FEM_OK;
+}
+
+extern "C" void fem_pk_destroy(fem_pk_plan plan) {
+    if (!plan) return;
+    pk_free(plan);
+    delete plan;
+}

@@ -1,0 +1,321 @@
+// Host side of the P_k mass assembly (Appendix D): local node numbering, the
+// coefficient matrix C, and the plan layout read by the kernels of pk.hip.
+// Plain C++ (no HIP), so the layout can be checked on the CPU.
+//
+// Local numbering of an element's N = (d+k)!/(d! k!) nodes: the
+// multi-indices alpha in N^(d+1) with |alpha| = k (alpha_i is the exponent of
+// the barycentric coordinate of local vertex i); local nodes 0..d are the
+// vertices alpha = k e_i, the others follow in decreasing lexicographic order
+// of (alpha_0, ..., alpha_d).
+//
+// Layout (build_pk_host):
+//   rp, ci        CSR pattern: row i holds every node sharing an element with
+//                 node i, columns ascending
+//   CSR entries are cut into tiles of kPkTile consecutive entries.  Per tile:
+//   tile_item[t]  first contribution item of the tile (items of tile t are
+//                 tile_item[t] .. tile_item[t+1]-1)
+//   tile_elem     the distinct elements its entries draw from, ascending
+//                 (tile t: tile_elem_ptr[t] .. tile_elem_ptr[t+1]-1)
+//   coff[s]       first item of entry s, relative to tile_item[t]
+//   item[u]       one contribution: position of its element in the tile's
+//                 element list (bits 0-15) | index of (min(a,b), max(a,b)) in
+//                 the packed upper triangle of C (bits 16-31), a and b the
+//                 local nodes of the row and column node; the items of an
+//                 entry are in ascending element number
+//   ctri          packed upper triangle of C (row-major, a <= b)
+#pragma once
+
+#include <algorithm>
+#include <array>
+#include <atomic>
+#include <cstdint>
+#include <map>
+#include <thread>
+#include <vector>
+
+namespace femasm {
+
+constexpr int kPkMaxK = 6;
+constexpr int kPkTile = 256;           // CSR entries per tile (one per thread)
+constexpr int kPkMaxTileElems = 4096;  // distinct elements one tile may draw on
+
+using PkMono = std::array<int, 4>;
+using PkPoly = std::map<PkMono, __int128>;
+
+inline std::vector<PkMono> pk_nodes(int d, int k) {
+    std::vector<PkMono> all, out;
+    // every composition of k into d+1 parts, decreasing lexicographic
+    for (int a0 = k; a0 >= 0; --a0)
+        for (int a1 = k - a0; a1 >= 0; --a1) {
+            if (d == 2) {
+                all.push_back({a0, a1, k - a0 - a1, 0});
+                continue;
+            }
+            for (int a2 = k - a0 - a1; a2 >= 0; --a2) all.push_back({a0, a1, a2, k - a0 - a1 - a2});
+        }
+    for (int v = 0; v <= d; ++v) {
+        PkMono a{0, 0, 0, 0};
+        a[v] = k;
+        out.push_back(a);
+    }
+    for (const PkMono &m : all)
+        if (std::find(out.begin(), out.begin() + d + 1, m) == out.begin() + d + 1) out.push_back(m);
+    return out;
+}
+
+inline __int128 pk_fact(int n) {
+    __int128 f = 1;
+    for (int i = 2; i <= n; ++i) f *= i;
+    return f;
+}
+
+// alpha! phi_alpha as a polynomial in the barycentric coordinates: the
+// product over l of prod_{j < alpha_l} (k lambda_l - j).
+inline PkPoly pk_scaled_basis(int d, int k, const PkMono &alpha) {
+    PkPoly p;
+    p[PkMono{0, 0, 0, 0}] = 1;
+    for (int l = 0; l <= d; ++l)
+        for (int j = 0; j < alpha[l]; ++j) {
+            PkPoly r;
+            for (const auto &t : p) {
+                PkMono up = t.first;
+                up[l] += 1;
+                r[up] += t.second * k;              // k lambda_l term
+                if (j) r[t.first] -= t.second * j;  // -j term
+            }
+            p.swap(r);
+        }
+    return p;
+}
+
+// Packed upper triangle of C, C[a][b] = int_K phi_a phi_b / (d! |K|), from
+// the magic formula int_K lambda^m = d! |K| m! / (d + |m|)!, evaluated in
+// integers over the denominator (d+2k)! alpha! beta! and rounded once.
+inline std::vector<double> pk_ctri(int d, int k) {
+    const std::vector<PkMono> nodes = pk_nodes(d, k);
+    const int n = int(nodes.size());
+    std::vector<PkPoly> P(n);
+    for (int a = 0; a < n; ++a) P[a] = pk_scaled_basis(d, k, nodes[a]);
+    const __int128 top = pk_fact(d + 2 * k);
+    std::vector<double> out;
+    out.reserve(size_t(n) * (n + 1) / 2);
+    for (int a = 0; a < n; ++a)
+        for (int b = a; b < n; ++b) {
+            __int128 num = 0;
+            for (const auto &x : P[a])
+                for (const auto &y : P[b]) {
+                    int deg = 0;
+                    __int128 f = 1;
+                    for (int i = 0; i <= d; ++i) {
+                        f *= pk_fact(x.first[i] + y.first[i]);
+                        deg += x.first[i] + y.first[i];
+                    }
+                    num += x.second * y.second * f * (top / pk_fact(d + deg));
+                }
+            __int128 den = top;
+            for (int i = 0; i <= d; ++i) den *= pk_fact(nodes[a][i]) * pk_fact(nodes[b][i]);
+            out.push_back(double(static_cast<long double>(num) / static_cast<long double>(den)));
+        }
+    return out;
+}
+
+inline int pk_tri_index(int n, int a, int b) {
+    const int lo = std::min(a, b), hi = std::max(a, b);
+    return lo * n - lo * (lo - 1) / 2 + (hi - lo);
+}
+
+template <class F>
+void pk_parallel(int64_t n, int nthreads, F fn) {
+    const int nt = std::max(1, nthreads);
+    if (n < 4096 || nt == 1) {
+        fn(int64_t(0), n);
+        return;
+    }
+    std::vector<std::thread> th;
+    const int64_t chunk = (n + nt - 1) / nt;
+    for (int t = 0; t < nt; ++t) {
+        const int64_t b = t * chunk, e = std::min(n, b + chunk);
+        if (b >= e) break;
+        th.emplace_back([=] { fn(b, e); });
+    }
+    for (auto &x : th) x.join();
+}
+
+struct PkHost {
+    int status = 0;   // 0 ok, 2 bad index / repeated node, 4 overflow
+    int n = 0, ntri = 0;
+    int64_t nnz = 0, ntiles = 0;
+    int max_tile_elems = 0;
+    std::vector<int32_t> rp, ci;
+    std::vector<int64_t> tile_item;
+    std::vector<int32_t> tile_elem_ptr, tile_elem;
+    std::vector<uint16_t> coff;
+    std::vector<uint32_t> item;
+    std::vector<double> ctri;
+};
+
+// me: host, N x nme (row-major, me[a*nme + e]).
+inline PkHost build_pk_host(int d, int k, int64_t nq, int64_t nme, const int32_t *me,
+                            int nthreads) {
+    PkHost H;
+    const int n = int(pk_nodes(d, k).size());
+    H.n = n;
+    H.ntri = n * (n + 1) / 2;
+    auto node = [&](int a, int64_t e) { return me[size_t(a) * nme + e]; };
+
+    // validation: indices in range, no node repeated within an element
+    std::atomic<int> bad{0};
+    pk_parallel(nme, nthreads, [&](int64_t b, int64_t e) {
+        std::vector<int32_t> v(n);
+        for (int64_t x = b; x < e && !bad.load(std::memory_order_relaxed); ++x) {
+            for (int a = 0; a < n; ++a) {
+                v[a] = node(a, x);
+                if (v[a] < 0 || v[a] >= nq) bad = 1;
+            }
+            std::sort(v.begin(), v.end());
+            if (std::adjacent_find(v.begin(), v.end()) != v.end()) bad = 1;
+        }
+    });
+    if (bad) {
+        H.status = 2;
+        return H;
+    }
+
+    // incidences node -> (element, local node), ascending element
+    std::vector<int64_t> ip(nq + 1, 0);
+    for (int64_t e = 0; e < nme; ++e)
+        for (int a = 0; a < n; ++a) ip[node(a, e) + 1] += 1;
+    for (int64_t i = 0; i < nq; ++i) ip[i + 1] += ip[i];
+    std::vector<int32_t> inc_e(ip[nq]);
+    std::vector<uint8_t> inc_a(ip[nq]);
+    {
+        std::vector<int64_t> fill(ip.begin(), ip.end() - 1);
+        for (int64_t e = 0; e < nme; ++e)
+            for (int a = 0; a < n; ++a) {
+                const int64_t p = fill[node(a, e)]++;
+                inc_e[p] = int32_t(e);
+                inc_a[p] = uint8_t(a);
+            }
+    }
+
+    // pattern: row i = sorted distinct nodes of the elements around i
+    std::vector<int32_t> rowlen(nq, 0);
+    auto row_cols = [&](int64_t i, std::vector<int32_t> &buf) {
+        buf.clear();
+        for (int64_t t = ip[i]; t < ip[i + 1]; ++t)
+            for (int b = 0; b < n; ++b) buf.push_back(node(b, inc_e[t]));
+        std::sort(buf.begin(), buf.end());
+        buf.erase(std::unique(buf.begin(), buf.end()), buf.end());
+    };
+    pk_parallel(nq, nthreads, [&](int64_t b, int64_t e) {
+        std::vector<int32_t> buf;
+        for (int64_t i = b; i < e; ++i) {
+            row_cols(i, buf);
+            rowlen[i] = int32_t(buf.size());
+        }
+    });
+    H.rp.assign(nq + 1, 0);
+    int64_t nnz = 0;
+    for (int64_t i = 0; i < nq; ++i) {
+        H.rp[i] = int32_t(nnz);
+        nnz += rowlen[i];
+        if (nnz >= (int64_t(1) << 31)) {
+            H.status = 4;
+            return H;
+        }
+    }
+    H.rp[nq] = int32_t(nnz);
+    H.nnz = nnz;
+
+    // contributions of every entry, ascending element: (element, tri code)
+    H.ci.assign(nnz, 0);
+    std::vector<int64_t> cptr(nnz + 1, 0);
+    pk_parallel(nq, nthreads, [&](int64_t b, int64_t e) {
+        std::vector<int32_t> buf;
+        for (int64_t i = b; i < e; ++i) {
+            row_cols(i, buf);
+            std::copy(buf.begin(), buf.end(), H.ci.begin() + H.rp[i]);
+            for (int64_t t = ip[i]; t < ip[i + 1]; ++t)
+                for (int bb = 0; bb < n; ++bb) {
+                    const int32_t j = node(bb, inc_e[t]);
+                    const int64_t pos = std::lower_bound(buf.begin(), buf.end(), j) - buf.begin();
+                    cptr[H.rp[i] + pos + 1] += 1;
+                }
+        }
+    });
+    for (int64_t s = 0; s < nnz; ++s) cptr[s + 1] += cptr[s];
+    const int64_t ncontrib = cptr[nnz];
+    std::vector<int32_t> celem(ncontrib);
+    std::vector<uint16_t> ccode(ncontrib);
+    pk_parallel(nq, nthreads, [&](int64_t b, int64_t e) {
+        std::vector<int64_t> fill;
+        for (int64_t i = b; i < e; ++i) {
+            const int32_t *c0 = H.ci.data() + H.rp[i], *c1 = H.ci.data() + H.rp[i + 1];
+            fill.assign(cptr.begin() + H.rp[i], cptr.begin() + H.rp[i + 1]);
+            for (int64_t t = ip[i]; t < ip[i + 1]; ++t) {
+                const int32_t x = inc_e[t];
+                const int a = inc_a[t];
+                for (int bb = 0; bb < n; ++bb) {
+                    const int64_t pos = std::lower_bound(c0, c1, node(bb, x)) - c0;
+                    const int64_t u = fill[pos]++;
+                    celem[u] = x;
+                    ccode[u] = uint16_t(pk_tri_index(n, a, bb));
+                }
+            }
+        }
+    });
+
+    // tiles of kPkTile entries: distinct elements, tile-relative item offsets
+    const int64_t ntiles = (nnz + kPkTile - 1) / kPkTile;
+    H.ntiles = ntiles;
+    H.tile_item.assign(ntiles + 1, 0);
+    H.tile_elem_ptr.assign(ntiles + 1, 0);
+    std::vector<std::vector<int32_t>> telems(ntiles);
+    H.coff.assign(size_t(ntiles) * kPkTile, 0);
+    H.item.assign(ncontrib, 0);
+    std::atomic<int> too_big{0};
+    pk_parallel(ntiles, nthreads, [&](int64_t b, int64_t e) {
+        std::vector<int32_t> el;
+        for (int64_t t = b; t < e; ++t) {
+            const int64_t s0 = t * kPkTile, s1 = std::min<int64_t>(nnz, s0 + kPkTile);
+            const int64_t i0 = cptr[s0], i1 = cptr[s1];
+            el.assign(celem.begin() + i0, celem.begin() + i1);
+            std::sort(el.begin(), el.end());
+            el.erase(std::unique(el.begin(), el.end()), el.end());
+            if (el.size() > size_t(kPkMaxTileElems) || i1 - i0 > 65535) {
+                too_big = 1;
+                continue;
+            }
+            for (int64_t s = s0; s < s1; ++s) H.coff[s] = uint16_t(cptr[s] - i0);
+            for (int64_t u = i0; u < i1; ++u) {
+                const uint32_t lp =
+                    uint32_t(std::lower_bound(el.begin(), el.end(), celem[u]) - el.begin());
+                H.item[u] = lp | (uint32_t(ccode[u]) << 16);
+            }
+            telems[t] = el;
+        }
+    });
+    if (too_big) {
+        H.status = 4;
+        return H;
+    }
+    int64_t te = 0;
+    for (int64_t t = 0; t < ntiles; ++t) {
+        H.tile_item[t] = cptr[t * kPkTile];
+        H.max_tile_elems = std::max(H.max_tile_elems, int(telems[t].size()));
+        te += int64_t(telems[t].size());
+        if (te >= (int64_t(1) << 31)) {
+            H.status = 4;
+            return H;
+        }
+        H.tile_elem_ptr[t + 1] = int32_t(te);
+    }
+    H.tile_item[ntiles] = ncontrib;
+    H.tile_elem.reserve(te);
+    for (int64_t t = 0; t < ntiles; ++t)
+        H.tile_elem.insert(H.tile_elem.end(), telems[t].begin(), telems[t].end());
+    H.ctri = pk_ctri(d, k);
+    return H;
+}
+
+}  // namespace femasm

@@ -61,6 +61,12 @@ _SIGS = {
     "fem_batch_numeric": ([P, I32, P, P, D, D, P, P], C.c_int),
     "fem_batch_sync_status": ([P, P], C.c_int),
     "fem_batch_destroy": ([P], None),
+    "fem_pk_symbolic": ([I32, I32, I64, I64, P, P, C.POINTER(P)], C.c_int),
+    "fem_pk_query": ([P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I32)], C.c_int),
+    "fem_pk_pattern": ([P, P, P, P], C.c_int),
+    "fem_pk_mass": ([P, P, P, P], C.c_int),
+    "fem_pk_sync_status": ([P, P], C.c_int),
+    "fem_pk_destroy": ([P], None),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -216,6 +222,36 @@ def fem_batch_destroy(batch: int):
         load_library().fem_batch_destroy(batch)
 
 
+def fem_pk_symbolic(d: int, k: int, nq: int, nme: int, me_ptr: int, stream=None) -> int:
+    out = P()
+    _check(load_library().fem_pk_symbolic(d, k, nq, nme, me_ptr, _stream(stream), C.byref(out)),
+           "fem_pk_symbolic")
+    return out.value
+
+
+def fem_pk_query(plan: int):
+    nr, nz, n = I64(), I64(), I32()
+    _check(load_library().fem_pk_query(plan, C.byref(nr), C.byref(nz), C.byref(n)), "fem_pk_query")
+    return nr.value, nz.value, n.value
+
+
+def fem_pk_pattern(plan: int, row_ptr: int, col_idx: int, stream=None):
+    _check(load_library().fem_pk_pattern(plan, row_ptr, col_idx, _stream(stream)), "fem_pk_pattern")
+
+
+def fem_pk_mass(plan: int, q: int, values: int, stream=None):
+    _check(load_library().fem_pk_mass(plan, q, values, _stream(stream)), "fem_pk_mass")
+
+
+def fem_pk_sync_status(plan: int, stream=None) -> int:
+    return load_library().fem_pk_sync_status(plan, _stream(stream))
+
+
+def fem_pk_destroy(plan: int):
+    if plan:
+        load_library().fem_pk_destroy(plan)
+
+
 # ------------------------------------------------------------ torch helpers
 def _op(op) -> int:
     return FEM_OP[op] if isinstance(op, str) else int(op)
@@ -362,3 +398,43 @@ class Batch:
 
     def sync_status(self, stream=None):
         _check(fem_batch_sync_status(self.handle, stream), "fem_batch_sync_status")
+
+
+class PkPlan:
+    """Symbolic plan of the P_k mass matrix of one P_k mesh (``me`` of shape
+    (N, nme), N = (d+k)!/(d! k!), local nodes 0..d the vertices)."""
+
+    def __init__(self, me: torch.Tensor, nq: int, d: int, k: int, stream=None):
+        load_library()
+        if me.dtype != torch.int32 or not me.is_cuda or me.dim() != 2:
+            raise ValueError("me must be a CUDA int32 tensor of shape (N, nme)")
+        self.me = me.contiguous()
+        self.d, self.k = int(d), int(k)
+        self.nq = int(nq)
+        self.nme = int(self.me.shape[1])
+        self.device = self.me.device
+        self.handle = fem_pk_symbolic(self.d, self.k, self.nq, self.nme,
+                                      self.me.data_ptr() if self.nme else 0, stream)
+        _, self.nnz, self.ndfe = fem_pk_query(self.handle)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            fem_pk_destroy(h)
+            self.handle = None
+
+    def pattern(self, stream=None):
+        rp = torch.empty(self.nq + 1, dtype=torch.int32, device=self.device)
+        ci = torch.empty(max(self.nnz, 1), dtype=torch.int32, device=self.device)
+        fem_pk_pattern(self.handle, rp.data_ptr(), ci.data_ptr(), stream)
+        return rp, ci[:self.nnz]
+
+    def mass(self, q, out=None, stream=None):
+        q = _dev_f64(q, self.device)
+        if out is None:
+            out = torch.empty(max(self.nnz, 1), dtype=torch.float64, device=self.device)
+        fem_pk_mass(self.handle, q.data_ptr(), out.data_ptr(), stream)
+        return out[:self.nnz]
+
+    def sync_status(self, stream=None):
+        _check(fem_pk_sync_status(self.handle, stream), "fem_pk_sync_status")
