@@ -247,9 +247,10 @@ typedef struct fem_pk_plan_s *fem_pk_plan;
  *   nq   number of P_k nodes;  nme  number of elements
  *   me   device, N*nme int32 (layout above)
  * Errors: FEM_ERR_ARG, FEM_ERR_INDEX (index out of range or a node repeated
- * within an element), FEM_ERR_OVERFLOW (nnz >= 2^31, N*nme >= 2^31, or a
- * tile of 256 consecutive CSR entries drawing on more than 4096 elements or
- * 65535 contributions), FEM_ERR_NOMEM, FEM_ERR_DEVICE. */
+ * within an element), FEM_ERR_OVERFLOW (nnz >= 2^31, N*nme >= 2^31, more
+ * than 2^(32-b) elements with b the bits of N(N+1)/2-1 (2^26 for P2 in 3D,
+ * 2^20 for P6 in 3D), or 1024 consecutive CSR entries with more than 65535
+ * contributions), FEM_ERR_NOMEM, FEM_ERR_DEVICE. */
 fem_status fem_pk_symbolic(int32_t d, int32_t k, int64_t nq, int64_t nme, const int32_t *me,
                            hipStream_t stream, fem_pk_plan *out);
 

@@ -14,14 +14,15 @@
 // follow in decreasing lexicographic order of (alpha_0, ..., alpha_d).
 //
 // Plan (built once from the connectivity, layout in pk_host.h): the CSR
-// pattern, CSR entries cut into tiles of kPkTile consecutive entries with the
-// distinct elements of each tile and per entry its contributions (tile-local
-// element, packed-triangle index of (a, b)) in ascending element number, the
-// vertex rows of the connectivity (geometry) and C (packed upper triangle).
+// pattern, CSR entries cut into tiles of kPkTile consecutive entries with per
+// entry its contributions (element, packed-triangle index of (a, b)) in
+// ascending element number, the vertex rows of the connectivity (geometry)
+// and C (packed upper triangle).
 // Numeric phase: k_pk_vol writes |det B_K| for every element; k_pk_mass, a
-// persistent kernel, keeps C in LDS, and for each tile stages the volumes of
-// its elements in LDS, then every lane sums its entry's items from 0.0 in
-// ascending element order and writes the value (coalesced).
+// persistent kernel, keeps C in LDS, turns each tile's items (read
+// coalesced) into products in LDS, and every thread sums the products of its
+// entries from 0.0 in ascending element order and writes the values
+// (coalesced).
 #include <algorithm>
 #include <cmath>
 #include <memory>
@@ -34,17 +35,15 @@
 namespace femasm {
 
 struct fem_pk_data {
-    int d = 0, k = 0, n = 0, ntri = 0;
+    int d = 0, k = 0, n = 0, ntri = 0, ebits = 0;
     int64_t nq = 0, nme = 0, nnz = 0, ntiles = 0, nitems = 0;
-    int max_tile_elems = 0;
+    int max_tile_items = 0;
     int device = 0;
     int32_t *rp = nullptr, *ci = nullptr;
     int32_t *gme = nullptr;         // (d+1) x nme vertex ids
     int64_t *tile_item = nullptr;   // [ntiles+1] first item of each tile
-    int32_t *tile_elem_ptr = nullptr;   // [ntiles+1]
-    int32_t *tile_elem = nullptr;   // distinct elements of each tile, ascending
     uint16_t *coff = nullptr;       // [ntiles*kPkTile] first item of each entry, tile-relative
-    uint32_t *item = nullptr;       // tile-local element | tri code << 16
+    uint32_t *item = nullptr;       // element | tri code << ebits
     double *ctri = nullptr;         // [ntri]
     double *vol = nullptr;          // [nme] |det B_K| (work array of the numeric phase)
     int32_t *status = nullptr;
@@ -65,8 +64,8 @@ fem_status pk_upload(T **dst, const std::vector<T> &src) {
 }
 
 void pk_free(fem_pk_data *p) {
-    void *ptrs[] = {p->rp,   p->ci,   p->gme,  p->tile_item, p->tile_elem_ptr, p->tile_elem,
-                    p->coff, p->item, p->ctri, p->vol,       p->status};
+    void *ptrs[] = {p->rp,   p->ci,   p->gme,  p->tile_item, p->coff,
+                    p->item, p->ctri, p->vol,  p->status};
     for (void *x : ptrs)
         if (x) (void)hipFree(x);
 }
@@ -91,43 +90,109 @@ __global__ __launch_bounds__(256) void k_pk_vol(const int32_t *__restrict__ gme,
     if (E.det == 0.0) atomicOr(status, 1);
 }
 
-__global__ __launch_bounds__(kPkTile) void k_pk_mass(
-    const int64_t *__restrict__ tile_item, const int32_t *__restrict__ tile_elem_ptr,
-    const int32_t *__restrict__ tile_elem, const uint16_t *__restrict__ coff,
-    const uint32_t *__restrict__ item, const double *__restrict__ ctri, int ntri,
-    const double *__restrict__ vol, int64_t ntiles, int64_t nnz, double *__restrict__ values) {
+// Items of a tile are staged `chunk` at a time (at most kPkMaxChunk): read
+// coalesced, turned into products |det B_K| * C[code] in LDS, then each
+// thread adds the products of its entries (contiguous, ascending element) in
+// order.  The first chunk and the entry offsets of the next tile are loaded
+// into registers while the current tile is summed.
+constexpr int kPkMaxChunk = 3072;
+constexpr int kPkRegs = kPkMaxChunk / kPkThreads;
+
+__global__ __launch_bounds__(kPkThreads) void k_pk_mass(
+    const int64_t *__restrict__ tile_item, const uint16_t *__restrict__ coff,
+    const uint32_t *__restrict__ item, const double *__restrict__ ctri, int ntri, int ebits,
+    int chunk, const double *__restrict__ vol, int64_t ntiles, int64_t nnz,
+    double *__restrict__ values) {
     extern __shared__ double lds[];
-    double *sc = lds;               // C, packed triangle
-    double *sv = lds + ntri;        // volumes of the tile's elements
-    for (int t = threadIdx.x; t < ntri; t += kPkTile) sc[t] = ctri[t];
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int32_t e0 = tile_elem_ptr[tile], ne = tile_elem_ptr[tile + 1] - e0;
-        __syncthreads();            // previous tile's reads of sv are done
-        for (int t = threadIdx.x; t < ne; t += kPkTile) sv[t] = vol[tile_elem[e0 + t]];
+    double *sc = lds;                    // C, packed triangle
+    double *sp = lds + ntri;             // products of the current chunk
+    const int tid = threadIdx.x;
+    const uint32_t emask = (1u << ebits) - 1u;
+    for (int t = tid; t < ntri; t += kPkThreads) sc[t] = ctri[t];
+
+    int64_t i0 = 0;
+    int ni = 0;
+    int c0[kPkPer], c1[kPkPer];
+    uint32_t x[kPkRegs];
+    auto fetch = [&](int64_t t) {
+        i0 = tile_item[t];
+        ni = int(tile_item[t + 1] - i0);
+#pragma unroll
+        for (int j = 0; j < kPkPer; ++j) {
+            const int l = tid + kPkThreads * j;
+            const int64_t s = t * kPkTile + l;
+            c0[j] = c1[j] = 0;
+            if (s < nnz) {
+                c0[j] = coff[s];
+                c1[j] = (l + 1 < kPkTile && s + 1 < nnz) ? int(coff[s + 1]) : ni;
+            }
+        }
+        const int cn = min(chunk, ni);
+#pragma unroll
+        for (int r = 0; r < kPkRegs; ++r) {
+            const int u = tid + kPkThreads * r;
+            x[r] = u < cn ? item[i0 + u] : 0u;
+        }
+    };
+    int64_t tile = blockIdx.x;
+    if (tile < ntiles) fetch(tile);
+    for (; tile < ntiles; tile += gridDim.x) {
+        const int64_t ti0 = i0;
+        const int tni = ni;
+        int a0[kPkPer], a1[kPkPer];
+#pragma unroll
+        for (int j = 0; j < kPkPer; ++j) {
+            a0[j] = c0[j];
+            a1[j] = c1[j];
+        }
+        __syncthreads();                 // sc ready; the previous tile is done with sp
+        {
+            const int cn = min(chunk, tni);
+#pragma unroll
+            for (int r = 0; r < kPkRegs; ++r) {
+                const int u = tid + kPkThreads * r;
+                if (u < cn) sp[u] = vol[x[r] & emask] * sc[x[r] >> ebits];
+            }
+        }
+        if (tile + gridDim.x < ntiles) fetch(tile + gridDim.x);
         __syncthreads();
-        const int64_t s = tile * kPkTile + threadIdx.x;
-        if (s < nnz) {
-            const int64_t i0 = tile_item[tile];
-            const int c0 = coff[s];
-            const int c1 = threadIdx.x + 1 < kPkTile && s + 1 < nnz ? int(coff[s + 1])
-                                                                     : int(tile_item[tile + 1] - i0);
-            const uint32_t *it = item + i0;
-            double acc = 0.0;
-            int c = c0;
-            for (; c + 4 <= c1; c += 4) {
-                const uint32_t x0 = it[c], x1 = it[c + 1], x2 = it[c + 2], x3 = it[c + 3];
-                acc = fma(sv[x0 & 0xffffu], sc[x0 >> 16], acc);
-                acc = fma(sv[x1 & 0xffffu], sc[x1 >> 16], acc);
-                acc = fma(sv[x2 & 0xffffu], sc[x2 >> 16], acc);
-                acc = fma(sv[x3 & 0xffffu], sc[x3 >> 16], acc);
+        double acc[kPkPer];
+#pragma unroll
+        for (int j = 0; j < kPkPer; ++j) {
+            acc[j] = 0.0;
+            const int hi = min(a1[j], chunk);
+            for (int c = a0[j]; c < hi; ++c) acc[j] += sp[c];
+        }
+        for (int cb = chunk; cb < tni; cb += chunk) {     // tiles with more items than a chunk
+            const int cn = min(chunk, tni - cb);
+            __syncthreads();
+            for (int u = tid; u < cn; u += kPkThreads) {
+                const uint32_t xx = item[ti0 + cb + u];
+                sp[u] = vol[xx & emask] * sc[xx >> ebits];
             }
-            for (; c < c1; ++c) {
-                const uint32_t x = it[c];
-                acc = fma(sv[x & 0xffffu], sc[x >> 16], acc);
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < kPkPer; ++j) {
+                const int lo = max(a0[j], cb), hi = min(a1[j], cb + cn);
+                for (int c = lo; c < hi; ++c) acc[j] += sp[c - cb];
             }
-            values[s] = acc;
+        }
+#pragma unroll
+        for (int j = 0; j < kPkPer; ++j) {
+            const int64_t s = tile * kPkTile + tid + kPkThreads * j;
+            if (s < nnz) values[s] = acc[j];
         }
     }
+}
+
+// Items per chunk: as many as fit next to C in kPkLdsBudget bytes of LDS
+// (a multiple of the workgroup size, between one per thread and kPkMaxChunk).
+constexpr size_t kPkLdsBudget = 40 * 1024;
+inline int pk_chunk(int ntri) {
+    const int64_t room = int64_t(kPkLdsBudget / sizeof(double)) - ntri;
+    const int64_t c = std::max<int64_t>(kPkThreads, std::min<int64_t>(kPkMaxChunk, room)) /
+                      kPkThreads * kPkThreads;
+    return int(c);
 }
 
 int pk_grid(size_t lds, int64_t ntiles) {
@@ -138,7 +203,7 @@ int pk_grid(size_t lds, int64_t ntiles) {
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         int n = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(&k_pk_mass),
-                                                         kPkTile, lds) != hipSuccess || n < 1)
+                                                         kPkThreads, lds) != hipSuccess || n < 1)
             n = 1;
         cached = n;
         cached_lds = lds;
@@ -184,19 +249,18 @@ extern "C" fem_status fem_pk_symbolic(int32_t d, int32_t k, int64_t nq, int64_t 
     p->k = k;
     p->n = n;
     p->ntri = H.ntri;
+    p->ebits = H.ebits;
     p->nq = nq;
     p->nme = nme;
     p->nnz = H.nnz;
     p->ntiles = H.ntiles;
     p->nitems = int64_t(H.item.size());
-    p->max_tile_elems = H.max_tile_elems;
+    p->max_tile_items = H.max_tile_items;
     (void)hipGetDevice(&p->device);
     fem_status st = pk_upload(&p->rp, H.rp);
     if (st == FEM_OK) st = pk_upload(&p->ci, H.ci);
     if (st == FEM_OK) st = pk_upload(&p->gme, gme);
     if (st == FEM_OK) st = pk_upload(&p->tile_item, H.tile_item);
-    if (st == FEM_OK) st = pk_upload(&p->tile_elem_ptr, H.tile_elem_ptr);
-    if (st == FEM_OK) st = pk_upload(&p->tile_elem, H.tile_elem);
     if (st == FEM_OK) st = pk_upload(&p->coff, H.coff);
     if (st == FEM_OK) st = pk_upload(&p->item, H.item);
     if (st == FEM_OK) st = pk_upload(&p->ctri, H.ctri);
@@ -244,12 +308,12 @@ extern "C" fem_status fem_pk_mass(fem_pk_plan plan, const double *q, double *val
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_status(e);
     }
-    const size_t lds = sizeof(double) * (size_t(plan->ntri) + size_t(std::max(plan->max_tile_elems, 1)));
-    if (lds > 160 * 1024) return FEM_ERR_OVERFLOW;
+    const int chunk = pk_chunk(plan->ntri);
+    const size_t lds = sizeof(double) * (size_t(plan->ntri) + size_t(chunk));
     const int grid = pk_grid(lds, plan->ntiles);
-    hipLaunchKernelGGL(k_pk_mass, dim3(grid), dim3(kPkTile), lds, stream, plan->tile_item,
-                       plan->tile_elem_ptr, plan->tile_elem, plan->coff, plan->item, plan->ctri,
-                       plan->ntri, plan->vol, plan->ntiles, plan->nnz, values);
+    hipLaunchKernelGGL(k_pk_mass, dim3(grid), dim3(kPkThreads), lds, stream, plan->tile_item,
+                       plan->coff, plan->item, plan->ctri, plan->ntri, plan->ebits, chunk,
+                       plan->vol, plan->ntiles, plan->nnz, values);
     return hip_status(hipGetLastError());
 }
 

@@ -11,17 +11,15 @@
 // Layout (build_pk_host):
 //   rp, ci        CSR pattern: row i holds every node sharing an element with
 //                 node i, columns ascending
-//   CSR entries are cut into tiles of kPkTile consecutive entries.  Per tile:
-//   tile_item[t]  first contribution item of the tile (items of tile t are
+//   CSR entries are cut into tiles of kPkTile consecutive entries.
+//   tile_item[t]  first contribution item of tile t (its items are
 //                 tile_item[t] .. tile_item[t+1]-1)
-//   tile_elem     the distinct elements its entries draw from, ascending
-//                 (tile t: tile_elem_ptr[t] .. tile_elem_ptr[t+1]-1)
 //   coff[s]       first item of entry s, relative to tile_item[t]
-//   item[u]       one contribution: position of its element in the tile's
-//                 element list (bits 0-15) | index of (min(a,b), max(a,b)) in
-//                 the packed upper triangle of C (bits 16-31), a and b the
-//                 local nodes of the row and column node; the items of an
-//                 entry are in ascending element number
+//   item[u]       one contribution: element number (bits 0 .. ebits-1) |
+//                 index of (min(a,b), max(a,b)) in the packed upper triangle
+//                 of C (bits ebits .. 31), a and b the local nodes of the row
+//                 and column node; ebits = 32 - (bits of ntri-1), and the
+//                 items of an entry are in ascending element number
 //   ctri          packed upper triangle of C (row-major, a <= b)
 #pragma once
 
@@ -36,8 +34,9 @@
 namespace femasm {
 
 constexpr int kPkMaxK = 6;
-constexpr int kPkTile = 256;           // CSR entries per tile (one per thread)
-constexpr int kPkMaxTileElems = 4096;  // distinct elements one tile may draw on
+constexpr int kPkThreads = 256;        // threads of a k_pk_mass workgroup
+constexpr int kPkPer = 4;              // CSR entries per thread and tile
+constexpr int kPkTile = kPkThreads * kPkPer;   // CSR entries per tile
 
 using PkMono = std::array<int, 4>;
 using PkPoly = std::map<PkMono, __int128>;
@@ -141,14 +140,21 @@ void pk_parallel(int64_t n, int nthreads, F fn) {
     for (auto &x : th) x.join();
 }
 
+// Bits of an item that hold the element number, for n local nodes.
+inline int pk_ebits(int n) {
+    const int ntri = n * (n + 1) / 2;
+    int cbits = 1;
+    while ((1 << cbits) < ntri) ++cbits;
+    return 32 - cbits;
+}
+
 struct PkHost {
     int status = 0;   // 0 ok, 2 bad index / repeated node, 4 overflow
-    int n = 0, ntri = 0;
+    int n = 0, ntri = 0, ebits = 0;
     int64_t nnz = 0, ntiles = 0;
-    int max_tile_elems = 0;
+    int max_tile_items = 0;
     std::vector<int32_t> rp, ci;
     std::vector<int64_t> tile_item;
-    std::vector<int32_t> tile_elem_ptr, tile_elem;
     std::vector<uint16_t> coff;
     std::vector<uint32_t> item;
     std::vector<double> ctri;
@@ -161,6 +167,11 @@ inline PkHost build_pk_host(int d, int k, int64_t nq, int64_t nme, const int32_t
     const int n = int(pk_nodes(d, k).size());
     H.n = n;
     H.ntri = n * (n + 1) / 2;
+    H.ebits = pk_ebits(n);
+    if (nme > (int64_t(1) << H.ebits)) {
+        H.status = 4;
+        return H;
+    }
     auto node = [&](int a, int64_t e) { return me[size_t(a) * nme + e]; };
 
     // validation: indices in range, no node repeated within an element
@@ -265,55 +276,28 @@ inline PkHost build_pk_host(int d, int k, int64_t nq, int64_t nme, const int32_t
         }
     });
 
-    // tiles of kPkTile entries: distinct elements, tile-relative item offsets
+    // tiles of kPkTile entries: tile-relative item offsets, packed items
     const int64_t ntiles = (nnz + kPkTile - 1) / kPkTile;
     H.ntiles = ntiles;
     H.tile_item.assign(ntiles + 1, 0);
-    H.tile_elem_ptr.assign(ntiles + 1, 0);
-    std::vector<std::vector<int32_t>> telems(ntiles);
     H.coff.assign(size_t(ntiles) * kPkTile, 0);
     H.item.assign(ncontrib, 0);
-    std::atomic<int> too_big{0};
-    pk_parallel(ntiles, nthreads, [&](int64_t b, int64_t e) {
-        std::vector<int32_t> el;
-        for (int64_t t = b; t < e; ++t) {
-            const int64_t s0 = t * kPkTile, s1 = std::min<int64_t>(nnz, s0 + kPkTile);
-            const int64_t i0 = cptr[s0], i1 = cptr[s1];
-            el.assign(celem.begin() + i0, celem.begin() + i1);
-            std::sort(el.begin(), el.end());
-            el.erase(std::unique(el.begin(), el.end()), el.end());
-            if (el.size() > size_t(kPkMaxTileElems) || i1 - i0 > 65535) {
-                too_big = 1;
-                continue;
+    for (int64_t t = 0; t <= ntiles; ++t) {
+        H.tile_item[t] = cptr[std::min<int64_t>(nnz, t * kPkTile)];
+        if (t > 0) {
+            const int64_t c = H.tile_item[t] - H.tile_item[t - 1];
+            if (c > 65535) {
+                H.status = 4;
+                return H;
             }
-            for (int64_t s = s0; s < s1; ++s) H.coff[s] = uint16_t(cptr[s] - i0);
-            for (int64_t u = i0; u < i1; ++u) {
-                const uint32_t lp =
-                    uint32_t(std::lower_bound(el.begin(), el.end(), celem[u]) - el.begin());
-                H.item[u] = lp | (uint32_t(ccode[u]) << 16);
-            }
-            telems[t] = el;
+            H.max_tile_items = std::max(H.max_tile_items, int(c));
         }
+    }
+    for (int64_t s = 0; s < nnz; ++s) H.coff[s] = uint16_t(cptr[s] - H.tile_item[s / kPkTile]);
+    pk_parallel(ncontrib, nthreads, [&](int64_t b, int64_t e) {
+        for (int64_t u = b; u < e; ++u)
+            H.item[u] = uint32_t(celem[u]) | (uint32_t(ccode[u]) << H.ebits);
     });
-    if (too_big) {
-        H.status = 4;
-        return H;
-    }
-    int64_t te = 0;
-    for (int64_t t = 0; t < ntiles; ++t) {
-        H.tile_item[t] = cptr[t * kPkTile];
-        H.max_tile_elems = std::max(H.max_tile_elems, int(telems[t].size()));
-        te += int64_t(telems[t].size());
-        if (te >= (int64_t(1) << 31)) {
-            H.status = 4;
-            return H;
-        }
-        H.tile_elem_ptr[t + 1] = int32_t(te);
-    }
-    H.tile_item[ntiles] = ncontrib;
-    H.tile_elem.reserve(te);
-    for (int64_t t = 0; t < ntiles; ++t)
-        H.tile_elem.insert(H.tile_elem.end(), telems[t].begin(), telems[t].end());
     H.ctri = pk_ctri(d, k);
     return H;
 }

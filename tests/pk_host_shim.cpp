@@ -16,9 +16,9 @@ extern "C" int pkh_build(int d, int k, int64_t nq, int64_t nme, const int32_t *m
     sizes[0] = g_h.nnz;
     sizes[1] = g_h.ntiles;
     sizes[2] = int64_t(g_h.item.size());
-    sizes[3] = int64_t(g_h.tile_elem.size());
+    sizes[3] = g_h.ebits;
     sizes[4] = g_h.ntri;
-    sizes[5] = g_h.max_tile_elems;
+    sizes[5] = g_h.max_tile_items;
     return 0;
 }
 
@@ -27,13 +27,11 @@ static void put(void *dst, const std::vector<T> &v) {
     if (!v.empty()) std::memcpy(dst, v.data(), v.size() * sizeof(T));
 }
 
-extern "C" void pkh_get(int32_t *rp, int32_t *ci, int64_t *tile_item, int32_t *tile_elem_ptr,
-                        int32_t *tile_elem, uint16_t *coff, uint32_t *item, double *ctri) {
+extern "C" void pkh_get(int32_t *rp, int32_t *ci, int64_t *tile_item, uint16_t *coff,
+                        uint32_t *item, double *ctri) {
     put(rp, g_h.rp);
     put(ci, g_h.ci);
     put(tile_item, g_h.tile_item);
-    put(tile_elem_ptr, g_h.tile_elem_ptr);
-    put(tile_elem, g_h.tile_elem);
     put(coff, g_h.coff);
     put(item, g_h.item);
     put(ctri, g_h.ctri);

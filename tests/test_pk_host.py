@@ -19,7 +19,7 @@ from helpers import floored_err
 from paper_1401_3301_amd import meshgen as mg
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-TILE = 256
+TILE = 1024
 
 
 @pytest.fixture(scope="module")
@@ -40,13 +40,11 @@ def _build(shim, m, k):
     st = shim.pkh_build(m.d, k, ctypes.c_int64(m.nq), ctypes.c_int64(m.nme), _p(me), _p(sizes))
     if st:
         return st, None
-    nnz, ntiles, nitems, ntel, ntri, _ = (int(x) for x in sizes)
+    nnz, ntiles, nitems, ebits, ntri, _ = (int(x) for x in sizes)
     L = dict(rp=np.zeros(m.nq + 1, np.int32), ci=np.zeros(nnz, np.int32),
-             tile_item=np.zeros(ntiles + 1, np.int64), tile_elem_ptr=np.zeros(ntiles + 1, np.int32),
-             tile_elem=np.zeros(ntel, np.int32), coff=np.zeros(ntiles * TILE, np.uint16),
-             item=np.zeros(nitems, np.uint32), ctri=np.zeros(ntri))
-    shim.pkh_get(*(_p(L[x]) for x in ("rp", "ci", "tile_item", "tile_elem_ptr", "tile_elem",
-                                      "coff", "item", "ctri")))
+             tile_item=np.zeros(ntiles + 1, np.int64), coff=np.zeros(ntiles * TILE, np.uint16),
+             item=np.zeros(nitems, np.uint32), ctri=np.zeros(ntri), ebits=ebits)
+    shim.pkh_get(*(_p(L[x]) for x in ("rp", "ci", "tile_item", "coff", "item", "ctri")))
     return 0, L
 
 
@@ -60,9 +58,9 @@ def _entry_items(L, s, nnz):
     i0 = L["tile_item"][t]
     c0 = int(L["coff"][s])
     c1 = int(L["coff"][s + 1]) if (s + 1) % TILE and s + 1 < nnz else int(L["tile_item"][t + 1] - i0)
-    it = L["item"][i0 + c0:i0 + c1]
-    el = L["tile_elem"][L["tile_elem_ptr"][t]:L["tile_elem_ptr"][t + 1]]
-    return el[it & 0xFFFF], it >> 16
+    it = L["item"][i0 + c0:i0 + c1].astype(np.int64)
+    eb = L["ebits"]
+    return it & ((1 << eb) - 1), it >> eb
 
 
 CASES = [(2, 2, 3), (2, 3, 2), (2, 5, 1), (3, 2, 2), (3, 3, 1), (3, 1, 2)]
@@ -93,9 +91,7 @@ def test_layout_against_brute_force(shim, d, k, n):
         i = int(np.searchsorted(rp, s, side="right") - 1)
         els, codes = _entry_items(L, s, nnz)
         assert list(zip(els.tolist(), codes.tolist())) == contrib[(i, int(ci[s]))]
-    for t in range(len(L["tile_item"]) - 1):
-        el = L["tile_elem"][L["tile_elem_ptr"][t]:L["tile_elem_ptr"][t + 1]]
-        assert np.all(np.diff(el) > 0)
+    assert L["ebits"] == 32 - math.ceil(math.log2(N * (N + 1) // 2))
 
 
 @pytest.mark.parametrize("d,k", [(d, k) for d in (2, 3) for k in range(1, 7)])
@@ -111,7 +107,7 @@ def test_library_coefficients_match_oracle(shim, d, k):
 
 @pytest.mark.parametrize("d,k,n", [(2, 3, 4), (3, 2, 3)])
 def test_kernel_sum_replayed_on_cpu(shim, d, k, n):
-    """The sum k_pk_mass performs (volumes |det B_K| times C, items in
+    """The sum k_pk_mass performs (products |det B_K| * C added in item
     order) replayed in numpy on the library layout equals the oracle."""
     m1 = mg.jittered_square(n, 0.2, seed=8) if d == 2 else mg.kuhn_cube(n, 0.15, seed=9)
     m = mg.pk_mesh(m1, k)
