@@ -12,7 +12,9 @@ Prints one JSON line.  Besides the headline numbers it carries:
   cpu_baseline  the CPU oracle on a bounded prefix of the same element list
   extra         elasticity on the same mesh, symbolic-phase time, batched vs
                 per-mesh launches, the 2D 2048^2 workload (stiffness, weighted
-                mass, elasticity), adjoint time (skipped with --no-extra)
+                mass, elasticity), adjoint time, the 3D P_k mass for k = 1..6
+                on about 1e6 nodes (skipped with --no-extra)
+With --pk K only the P_k mass of degree K is timed (its own JSON line).
 """
 from __future__ import annotations
 
@@ -169,7 +171,45 @@ def extras(torch, femasm, mg, plan, q, stream, steps):
     _, per = time_launches(fnb, stream, 20, 3)
     out["adjoint_3d"] = {"elements": m5.nme, "ms": statistics.mean(per),
                          "elements_per_s": m5.nme / (statistics.mean(per) / 1e3)}
+    del p5
+    # P_k mass (Appendix D, Table D.1): 3D, about 1e6 nodes, k = 1..6
+    out["pk_mass_3d"] = {}
+    for k in sorted(PK_CUBES):
+        print(f"[bench] P{k} mass ...", file=sys.stderr, flush=True)
+        out["pk_mass_3d"][f"P{k}"] = pk_run(torch, femasm, mg, k, stream, 10, 2)
     return out
+
+
+# 3D P_k meshes of about a million nodes (the largest size of Table D.1):
+# cubes per side for each degree k
+PK_CUBES = {1: 99, 2: 50, 3: 33, 4: 25, 5: 20, 6: 16}
+
+
+def pk_algorithmic_bytes(mesh, nnz):
+    """Bytes the P_k mass must move: the vertex coordinates and vertex rows of
+    me (the geometry), then the CSR values once."""
+    import numpy as np
+    nv = len(np.unique(mesh.me[:mesh.d + 1]))
+    return 8 * mesh.d * nv + 4 * (mesh.d + 1) * mesh.nme + 8 * nnz
+
+
+def pk_run(torch, femasm, mg, k, stream, steps, warmup):
+    m = mg.config_pk(k, PK_CUBES[k])["mesh"]
+    me = torch.from_numpy(m.me).to("cuda:0")
+    q = torch.from_numpy(m.q).to("cuda:0")
+    t0 = time.perf_counter()
+    plan = femasm.PkPlan(me, m.nq, m.d, k)
+    t_sym = time.perf_counter() - t0
+    vals = torch.empty(max(plan.nnz, 1), dtype=torch.float64, device="cuda:0")
+    fn = lambda: femasm.fem_pk_mass(plan.handle, q.data_ptr(), vals.data_ptr(), stream.cuda_stream)
+    wall, per = time_launches(fn, stream, steps, warmup)
+    plan.sync_status()
+    t = statistics.mean(per) / 1e3
+    ab = pk_algorithmic_bytes(m, plan.nnz)
+    return {"k": k, "nq": m.nq, "nme": m.nme, "nnz": plan.nnz, "ms": t * 1e3,
+            "wall_ms_per_step": wall / steps * 1e3, "nnz_per_s": plan.nnz / t,
+            "elements_per_s": m.nme / t, "alg_GBps": ab / t / 1e9,
+            "frac": ab / t / 1e9 / PEAK_HBM_GBS, "algorithmic_bytes": ab, "symbolic_s": t_sym}
 
 
 def main():
@@ -184,6 +224,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (HBM counter calibration)")
+    ap.add_argument("--pk", type=int, choices=sorted(PK_CUBES), default=None,
+                    help="only time the 3D P_k mass of degree K on about 1e6 nodes")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the assembly is measured on one MI355X; "
@@ -209,6 +251,18 @@ def main():
 
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
+    if args.pk is not None:
+        r = pk_run(torch, femasm, mg, args.pk, stream, args.steps, args.warmup)
+        print(json.dumps({"metric": f"P{args.pk} mass CSR entries assembled/s (3D, FP64)",
+                          "value": r["nnz_per_s"], "unit": "nnz/s", "n_gpus": 1,
+                          "steps": args.steps, "warmup": args.warmup,
+                          "ms_per_step": r["wall_ms_per_step"], "higher_is_better": True,
+                          "dtype": "f64", "data": "synthetic",
+                          "config": {"workload": f"3D P{args.pk} mass, unit cube "
+                                                 f"{PK_CUBES[args.pk]}^3 cubes x 6 Kuhn tets, "
+                                                 f"jitter 0.15h", **{x: r[x] for x in ("nq", "nme", "nnz")}},
+                          "pk": r}), flush=True)
+        return
     cfg = mg.config_large_3d(args.n)
     mesh = cfg["mesh"]
     me = torch.from_numpy(mesh.me).to(dev)
