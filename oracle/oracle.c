@@ -22,7 +22,9 @@
  *   - elasticity through the lemma of Section 5.1 / Appendix B:
  *     lambda <g_b, Q^{n,l} g_a> + mu <g_b, S^{n,l} g_a>, with the Voigt
  *     matrices B_l, C_0, C_1 written out, times |K| (constant Lame
- *     parameters: the P1 interpolant of a constant is that constant).
+ *     parameters: the P1 interpolant of a constant is that constant), or
+ *     with nodal Lame fields, times |K|/(d+1) and the vertex sums lambda^s,
+ *     mu^s of the fields (the P1-interpolated coefficients of Section 5.1).
  * and the language-level `sparse` of Section 3: triplets (I, J, K) with
  * duplicates summed.  Here the triplets are sorted by (row, column, element
  * number) and summed in that order, so every global entry is the sum of its
@@ -361,6 +363,7 @@ static void gather_element(int d, int64_t nq, int64_t nme, const double *q, cons
  * rows in output-position order.  cap bounds the number of nonzeros. */
 static int assemble_core(int d, int64_t nq, int64_t nme, const double *q, const int32_t *me,
                          int op, const double *w, double lam, double mu,
+                         const double *lam_nodal, const double *mu_nodal,
                          const int64_t *sel, int64_t nout,
                          int64_t cap, int64_t *nnz_out, int64_t *row_ptr, int64_t *col_idx,
                          double *val, double *absval) {
@@ -399,7 +402,19 @@ static int assemble_core(int d, int64_t nq, int64_t nme, const double *q, const 
         gather_element(d, nq, nme, q, me, k, P, vid);
         if (op == OR_MASS_W)
             for (int a = 0; a < nl; ++a) wloc[a] = w[vid[a]];
-        if (!element_matrix(d, op, P, wloc, lam, mu, E, Ea)) {
+        double lamk = lam, muk = mu;
+        if (lam_nodal) {
+            /* P1 interpolants of the Lame fields (Section 5.1): the integral
+             * of lambda_h over K is |K| lambda^s / (d+1) */
+            double ls = 0.0, ms = 0.0;
+            for (int a = 0; a < nl; ++a) {
+                ls += lam_nodal[vid[a]];
+                ms += mu_nodal[vid[a]];
+            }
+            lamk = ls / (double)nl;
+            muk = ms / (double)nl;
+        }
+        if (!element_matrix(d, op, P, wloc, lamk, muk, E, Ea)) {
             free(T);
             return OR_ERR_DEGENERATE;
         }
@@ -453,8 +468,37 @@ int oracle_assemble(int d, int64_t nq, int64_t nme, const double *q, const int32
                     double *absval) {
     if (d < 2 || d > 3) return OR_ERR_ARG;
     const int m = (op == OR_ELAS) ? d : 1;
-    return assemble_core(d, nq, nme, q, me, op, w, lam, mu, NULL, (int64_t)m * nq, cap,
-                         nnz_out, row_ptr, col_idx, val, absval);
+    return assemble_core(d, nq, nme, q, me, op, w, lam, mu, NULL, NULL, NULL, (int64_t)m * nq,
+                         cap, nnz_out, row_ptr, col_idx, val, absval);
+}
+
+/* Elasticity with nodal (P1) Lame fields lam_nodal[nq], mu_nodal[nq]:
+ * element matrix |K|/(d+1) (lambda^s <g_b, Q g_a> + mu^s <g_b, S g_a>),
+ * lambda^s the sum of the field over the element's vertices (Section 5.1).
+ * rows: NULL for all d*nq rows, else nsel distinct global rows. */
+int oracle_assemble_lame(int d, int64_t nq, int64_t nme, const double *q, const int32_t *me,
+                         const double *lam_nodal, const double *mu_nodal, int64_t nsel,
+                         const int64_t *rows, int64_t cap, int64_t *nnz_out, int64_t *row_ptr,
+                         int64_t *col_idx, double *val, double *absval) {
+    if (d < 2 || d > 3 || !lam_nodal || !mu_nodal) return OR_ERR_ARG;
+    if (!rows)
+        return assemble_core(d, nq, nme, q, me, OR_ELAS, NULL, 0.0, 0.0, lam_nodal, mu_nodal,
+                             NULL, (int64_t)d * nq, cap, nnz_out, row_ptr, col_idx, val, absval);
+    const int64_t nrows = (int64_t)d * nq;
+    if (nsel < 0) return OR_ERR_ARG;
+    int64_t *sel = (int64_t *)calloc((size_t)(nrows > 0 ? nrows : 1), sizeof(int64_t));
+    if (!sel) return OR_ERR_NOMEM;
+    for (int64_t s = 0; s < nsel; ++s) {
+        if (rows[s] < 0 || rows[s] >= nrows || sel[rows[s]]) {
+            free(sel);
+            return OR_ERR_ARG;
+        }
+        sel[rows[s]] = s + 1;
+    }
+    int st = assemble_core(d, nq, nme, q, me, OR_ELAS, NULL, 0.0, 0.0, lam_nodal, mu_nodal, sel,
+                           nsel, cap, nnz_out, row_ptr, col_idx, val, absval);
+    free(sel);
+    return st;
 }
 
 /* Selected rows only (sampled checks on large meshes).  rows[0..nsel) are
@@ -475,8 +519,8 @@ int oracle_assemble_rows(int d, int64_t nq, int64_t nme, const double *q, const 
         }
         sel[rows[s]] = s + 1;
     }
-    int st = assemble_core(d, nq, nme, q, me, op, w, lam, mu, sel, nsel, cap, nnz_out, row_ptr,
-                           col_idx, val, absval);
+    int st = assemble_core(d, nq, nme, q, me, op, w, lam, mu, NULL, NULL, sel, nsel, cap, nnz_out,
+                           row_ptr, col_idx, val, absval);
     free(sel);
     return st;
 }

@@ -61,6 +61,8 @@ def _load():
                                              C.c_double, i64, P, i64, P, P, P, P, P]
         lib.oracle_grad.argtypes = [C.c_int, i64, i64, P, P, P, P, P, P, P, P, P, P]
         lib.oracle_element_matrix.argtypes = [C.c_int, C.c_int, P, P, C.c_double, C.c_double, P]
+        lib.oracle_assemble_lame.argtypes = [C.c_int, i64, i64, P, P, P, P, i64, P, i64, P, P, P,
+                                             P, P]
         lib.oracle_pk_coeff.argtypes = [C.c_int, C.c_int, P]
         lib.oracle_pk_alpha.argtypes = [C.c_int, C.c_int, P]
         lib.oracle_pk_mass.argtypes = [C.c_int, C.c_int, i64, i64, P, P, i64, P, P, P, P, P]
@@ -68,7 +70,8 @@ def _load():
                                             P, P, P, P]
         for f in (lib.oracle_validate, lib.oracle_assemble, lib.oracle_assemble_rows,
                   lib.oracle_grad, lib.oracle_element_matrix, lib.oracle_pk_coeff,
-                  lib.oracle_pk_alpha, lib.oracle_pk_mass, lib.oracle_pk_mass_rows):
+                  lib.oracle_pk_alpha, lib.oracle_pk_mass, lib.oracle_pk_mass_rows,
+                  lib.oracle_assemble_lame):
             f.restype = C.c_int
         _lib = lib
     return _lib
@@ -135,6 +138,34 @@ def assemble_rows(q, me, op: str, rows, w=None, lam: float = 1.0, mu: float = 0.
             continue
         if st:
             raise OracleError(st, "assemble_rows")
+        n = nnz.value
+        return rp, ci[:n].copy(), v[:n].copy(), av[:n].copy()
+
+
+def assemble_lame(q, me, lam, mu, rows=None):
+    """Elasticity with nodal Lame fields lam, mu (nq,) as CSR over the d*nq
+    dof rows (or only the global dof rows listed in ``rows``)."""
+    d, q, me = _mesh_arrays(q, me)
+    nq, nme = q.shape[1], me.shape[1]
+    lam = np.ascontiguousarray(lam, np.float64)
+    mu = np.ascontiguousarray(mu, np.float64)
+    rsel = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    nout = d * nq if rsel is None else len(rsel)
+    cap = max(1, nme * ((d + 1) * d) ** 2) if rsel is None else max(1, len(rsel) * 64 * d * 4)
+    while True:
+        rp = np.zeros(nout + 1, np.int64)
+        ci = np.zeros(cap, np.int64)
+        v = np.zeros(cap, np.float64)
+        av = np.zeros(cap, np.float64)
+        nnz = C.c_int64(0)
+        st = _load().oracle_assemble_lame(d, nq, nme, _ptr(q), _ptr(me), _ptr(lam), _ptr(mu),
+                                          0 if rsel is None else len(rsel), _ptr(rsel), cap,
+                                          C.byref(nnz), _ptr(rp), _ptr(ci), _ptr(v), _ptr(av))
+        if st == 4 and rsel is not None:
+            cap *= 4
+            continue
+        if st:
+            raise OracleError(st, "assemble_lame")
         n = nnz.value
         return rp, ci[:n].copy(), v[:n].copy(), av[:n].copy()
 
