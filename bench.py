@@ -10,7 +10,8 @@ Prints one JSON line.  Besides the headline numbers it carries:
   roofline      achieved algorithmic HBM GB/s of the numeric kernel against
                 the 8 TB/s peak (kernel time from HIP events on its stream)
   cpu_baseline  the CPU oracle on a bounded prefix of the same element list
-  extra         elasticity on the same mesh, symbolic-phase time, batched vs
+  extra         elasticity on the same mesh (constant and nodal Lame
+                parameters), symbolic-phase time, batched vs
                 per-mesh launches, the 2D 2048^2 workload (stiffness, weighted
                 mass, elasticity), adjoint time, the 3D P_k mass for k = 1..6
                 on about 1e6 nodes (skipped with --no-extra)
@@ -96,7 +97,19 @@ def extras(torch, femasm, mg, plan, q, stream, steps):
     ab = algorithmic_bytes(3, plan.nq, plan.nme, nnz_e)
     out["elas_3d"] = {"elements_per_s": plan.nme / t, "nnz_per_s": nnz_e / t,
                       "ms": t * 1e3, "alg_GBps": ab / t / 1e9, "frac": ab / t / 1e9 / PEAK_HBM_GBS}
-    del vals
+    # elasticity with nodal (P1) Lame fields on the same plan
+    lam_f = torch.from_numpy(mg.lognormal_field(plan.nq, 82)).to(q.device)
+    mu_f = torch.from_numpy(0.5 * mg.lognormal_field(plan.nq, 83)).to(q.device)
+    fn = lambda: femasm.fem_assemble_elasticity_nodal(plan.handle, q.data_ptr(), lam_f.data_ptr(),
+                                                     mu_f.data_ptr(), vals.data_ptr(),
+                                                     stream.cuda_stream)
+    _, per = time_launches(fn, stream, max(3, steps // 4), 2)
+    t = statistics.mean(per) / 1e3
+    ab = algorithmic_bytes(3, plan.nq, plan.nme, nnz_e) + 2 * 8 * plan.nq
+    out["elas_nodal_3d"] = {"elements_per_s": plan.nme / t, "nnz_per_s": nnz_e / t,
+                            "ms": t * 1e3, "alg_GBps": ab / t / 1e9,
+                            "frac": ab / t / 1e9 / PEAK_HBM_GBS}
+    del vals, lam_f, mu_f
     # batched vs per-mesh launches (256 meshes, weighted mass + stiffness)
     cfg = mg.config_batch()
     meshes = cfg["meshes"]

@@ -130,6 +130,25 @@ fem_status fem_assemble_numeric(fem_plan plan, int32_t op, const double *q, cons
                                 double lambda, double mu, double *values, hipStream_t stream);
 
 /*
+ * Elasticity with nodal Lame fields (Section 5.1: the Lame parameters
+ * replaced by their P1 interpolants): element matrix
+ *   |K|/(d+1) (lambda^s <g_b, Q^{n,l} g_a> + mu^s <g_b, S^{n,l} g_a>),
+ * lambda^s, mu^s the sums of the fields over the element's vertices.  Output
+ * in the FEM_OP_ELAS pattern and numbering (d*nq rows, r = d*i + l), exactly
+ * symmetric, entries summed in ascending element number.
+ *   q       device, d*nq doubles
+ *   lam, mu device, nq doubles each (nodal values)
+ *   values  device, d*d*nnz doubles, fully overwritten
+ * Asynchronous, no allocation.  Runs on the vertex-pair kernel only:
+ * FEM_ERR_OVERFLOW for a mesh without that layout (a vertex with more than
+ * 32 neighbours, or more than 1023 elements around a vertex) or vector nnz
+ * >= 2^31; FEM_ERR_ARG for null arrays.  Degenerate elements as in
+ * fem_assemble_numeric.
+ */
+fem_status fem_assemble_elasticity_nodal(fem_plan plan, const double *q, const double *lam,
+                                         const double *mu, double *values, hipStream_t stream);
+
+/*
  * Adjoint of J(q, w) = a^T (S(q) + M_w(q)) b: the sum over elements of
  * a_K^T (E_stiff(K) + E_mass_w(K)) b_K, differentiated through the element
  * Jacobians (the gradient systems of Appendix C.1 give

@@ -117,6 +117,14 @@ __device__ __forceinline__ double elas_combine(double xln, double xnl, double tr
     return fma(lam, xln, mu * (diag ? tr + xnl : xnl));
 }
 
+// Nodal (P1) Lame fields: with per-element means lambda_K = lambda^s/(d+1),
+// mu_K = mu^s/(d+1) the sums XL = sum lambda_K X_K, XM = sum mu_K X_K give
+// the entry (l, n) of a vertex pair as XL_ln + (tr XM delta_ln + XM_nl).
+__device__ __forceinline__ double elas_combine_nodal(double xl_ln, double xm_nl, double trm,
+                                                     bool diag) {
+    return xl_ln + (diag ? trm + xm_nl : xm_nl);
+}
+
 template <int D>
 struct Fact {
     static constexpr double dfact = D == 2 ? 2.0 : 6.0;           // d!

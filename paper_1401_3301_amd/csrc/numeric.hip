@@ -181,6 +181,20 @@ extern "C" fem_status fem_assemble_numeric(fem_plan plan, int32_t op, const doub
     return hip_status(e);
 }
 
+extern "C" fem_status fem_assemble_elasticity_nodal(fem_plan plan, const double *q,
+                                                   const double *lam, const double *mu,
+                                                   double *values, hipStream_t stream) {
+    if (!plan) return FEM_ERR_ARG;
+    const int64_t nnz = int64_t(plan->d) * plan->d * plan->nnz;
+    if (nnz >= (int64_t(1) << 31)) return FEM_ERR_OVERFLOW;
+    if (nnz > 0 && (!q || !lam || !mu || !values)) return FEM_ERR_ARG;
+    if (nnz == 0) return FEM_OK;
+    hipError_t e = hipSuccess;
+    if (launch_pair(plan, kOpElasNodal, q, lam, 0.0, 0.0, values, stream, &e, mu))
+        return hip_status(e);
+    return FEM_ERR_OVERFLOW;   // no vertex-pair layout for this mesh
+}
+
 extern "C" fem_status fem_plan_pattern(fem_plan plan, int32_t op, int32_t *row_ptr,
                                        int32_t *col_idx, hipStream_t stream) {
     if (!plan || op < FEM_OP_MASS || op > FEM_OP_ELAS || !row_ptr) return FEM_ERR_ARG;

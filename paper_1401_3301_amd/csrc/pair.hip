@@ -55,21 +55,28 @@ struct PairView {
     const uint16_t *ent;
     const double *q;
     const double *w;
+    const double *w2;     // mu field (nodal Lame elasticity; w is the lambda field)
     double *values;
     int32_t nb, max_nodes;
     uint32_t off_w, off_row, off_rowof, off_ev, off_ent;
 };
 
 // Per-element values kept in LDS (odd slot size: consecutive elements fall on
-// different banks).  ELAS: scaled cofactors ch_a; the scalar operators: the
-// packed upper triangle of the element matrix, entry (a, b), a <= b, at
-// a*(d+1) - a*(a-1)/2 + (b-a) (the pair entries carry that index).
+// different banks).  ELAS: scaled cofactors ch_a (and, with nodal Lame
+// fields, the element means lambda_K, mu_K after them); the scalar
+// operators: the packed upper triangle of the element matrix, entry (a, b),
+// a <= b, at a*(d+1) - a*(a-1)/2 + (b-a) (the pair entries carry that index).
+constexpr bool is_elas(int op) { return op == FEM_OP_ELAS || op == kOpElasNodal; }
+
 template <int D, int OP>
 struct PairOp {
     static constexpr int NL = D + 1;
-    static constexpr int NV0 = OP == FEM_OP_ELAS ? NL * D : NL * (NL + 1) / 2;
+    static constexpr int NV0 = OP == FEM_OP_ELAS      ? NL * D
+                               : OP == kOpElasNodal ? NL * D + 2
+                                                    : NL * (NL + 1) / 2;
     static constexpr int NV = NV0 | 1;
-    static constexpr int M = OP == FEM_OP_ELAS ? D : 1;
+    static constexpr int M = is_elas(OP) ? D : 1;
+    static constexpr int NX = OP == kOpElasNodal ? 2 * M * M : M * M;   // register sums per pair
 };
 
 template <int NL>
@@ -133,7 +140,7 @@ __device__ __forceinline__ int wave_task(uint64_t wp, int w) {
 
 template <int D, int OP>
 __device__ __forceinline__ void element_values(const double (&P)[D + 1][D], const double *wl,
-                                               double *out, int &bad) {
+                                               const double *wl2, double *out, int &bad) {
     constexpr int NL = D + 1;
     if constexpr (OP == FEM_OP_MASS || OP == FEM_OP_MASS_W) {
         // the same operations as the row-gather kernel: (1+delta) k, and
@@ -181,6 +188,17 @@ __device__ __forceinline__ void element_values(const double (&P)[D + 1][D], cons
             for (int a = 0; a < NL; ++a)
 #pragma unroll
                 for (int x = 0; x < D; ++x) out[a * D + x] = E.c[a][x] * sc;
+            if constexpr (OP == kOpElasNodal) {
+                // means of the P1 Lame fields over K: int_K lambda_h = |K| lambda^s/(d+1)
+                double ls = wl[0], ms = wl2[0];
+#pragma unroll
+                for (int a = 1; a < NL; ++a) {
+                    ls += wl[a];
+                    ms += wl2[a];
+                }
+                out[NL * D] = ls / double(NL);
+                out[NL * D + 1] = ms / double(NL);
+            }
         }
     }
 }
@@ -193,7 +211,9 @@ __global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, doubl
     constexpr int NV = O::NV;
     constexpr int M = O::M;
     constexpr int M2 = M * M;
-    constexpr bool kW = OP == FEM_OP_MASS_W;
+    constexpr int NX = O::NX;
+    constexpr bool kW = OP == FEM_OP_MASS_W || OP == kOpElasNodal;
+    constexpr bool kW2 = OP == kOpElasNodal;
     extern __shared__ __align__(16) unsigned char smem[];
     double *crd = reinterpret_cast<double *>(smem);
     double *wv = reinterpret_cast<double *>(smem + pv.off_w);
@@ -222,7 +242,7 @@ __global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, doubl
     uint32_t rhd[S], rhd2[S];
     int rcntv = 0, reoffv = 0, rns = 0;   // task entry counts / offsets, lane s = slot s
     double rq[kNodeSlots][D];
-    double rw[kNodeSlots];
+    double rw[kNodeSlots], rw2[kNodeSlots];
     int nid[kNodeSlots];
 
     auto load_nodes = [&](const Desc &d) {
@@ -239,6 +259,7 @@ __global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, doubl
 #pragma unroll
                 for (int x = 0; x < D; ++x) rq[u][x] = pv.q[d.qo + x * d.nq + nid[u]];
                 if constexpr (kW) rw[u] = pv.w[d.wo + nid[u]];
+                if constexpr (kW2) rw2[u] = pv.w2[d.wo + nid[u]];
             }
         }
     };
@@ -291,6 +312,7 @@ __global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, doubl
 #pragma unroll
                 for (int x = 0; x < D; ++x) crd[x * MN + n] = rq[u][x];
                 if constexpr (kW) wv[n] = rw[u];
+                if constexpr (kW2) wv[MN + n] = rw2[u];
             }
         }
         // L2: coordinates of the next block in flight
@@ -347,14 +369,15 @@ __global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, doubl
                 const int v[4] = {int(vv & 255u), int((vv >> 8) & 255u), int((vv >> 16) & 255u),
                                   int(vv >> 24)};
                 double P[NL][D];
-                double wl[NL];
+                double wl[NL], wl2[NL];
 #pragma unroll
                 for (int a = 0; a < NL; ++a) {
 #pragma unroll
                     for (int x = 0; x < D; ++x) P[a][x] = crd[x * MN + v[a]];
                     if constexpr (kW) wl[a] = wv[v[a]];
+                    if constexpr (kW2) wl2[a] = wv[MN + v[a]];
                 }
-                element_values<D, OP>(P, wl, ev + e * NV, bad);
+                element_values<D, OP>(P, wl, wl2, ev + e * NV, bad);
             } else if (e == dc.ne) {
 #pragma unroll
                 for (int t = 0; t < NV; ++t) ev[e * NV + t] = 0.0;
@@ -362,11 +385,11 @@ __global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, doubl
         }
         __syncthreads();
         // L10: pair sums
-        double X[S][M2];
+        double X[S][NX];
 #pragma unroll
         for (int s = 0; s < S; ++s) {
 #pragma unroll
-            for (int t = 0; t < M2; ++t) X[s][t] = 0.0;
+            for (int t = 0; t < NX; ++t) X[s][t] = 0.0;
             if (s < ns) {
                 const uint16_t *lst = ent + eoff[s] + lane;
                 const int C = cnt[s];
@@ -388,6 +411,23 @@ __global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, doubl
 #pragma unroll
                             for (int n = 0; n < D; ++n)
                                 X[s][l * D + n] = fma(A[l], B[n], X[s][l * D + n]);
+                    } else if constexpr (OP == kOpElasNodal) {
+                        const int a = int((x >> 10) & 3u), b = int((x >> 12) & 3u);
+                        double A[D], B[D];
+#pragma unroll
+                        for (int c = 0; c < D; ++c) {
+                            A[c] = Ee[a * D + c];
+                            B[c] = Ee[b * D + c];
+                        }
+                        const double lk = Ee[NL * D], mk = Ee[NL * D + 1];
+#pragma unroll
+                        for (int l = 0; l < D; ++l)
+#pragma unroll
+                            for (int n = 0; n < D; ++n) {
+                                const double xln = A[l] * B[n];
+                                X[s][l * D + n] = fma(lk, xln, X[s][l * D + n]);
+                                X[s][M2 + l * D + n] = fma(mk, xln, X[s][M2 + l * D + n]);
+                            }
                     } else {
                         X[s][0] += Ee[(x >> 10) & 15u];
                     }
@@ -412,7 +452,20 @@ __global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, doubl
                     o2 = outb + M2 * r2.z + M * int(hd2[s] >> 7);
                     len2 = r2.y;
                 }
-                if constexpr (OP == FEM_OP_ELAS) {
+                if constexpr (OP == kOpElasNodal) {
+                    double trm = X[s][M2];
+#pragma unroll
+                    for (int m = 1; m < D; ++m) trm += X[s][M2 + m * D + m];
+#pragma unroll
+                    for (int l = 0; l < D; ++l)
+#pragma unroll
+                        for (int n = 0; n < D; ++n) {
+                            const double v = elas_combine_nodal(X[s][l * D + n],
+                                                                X[s][M2 + n * D + l], trm, l == n);
+                            o[l * D * ri.y + n] = v;
+                            if (o2) o2[n * D * len2 + l] = v;
+                        }
+                } else if constexpr (OP == FEM_OP_ELAS) {
                     double tr = X[s][0];
 #pragma unroll
                     for (int m = 1; m < D; ++m) tr += X[s][m * D + m];
@@ -473,6 +526,7 @@ PairLds pair_lds(const PairPlan &P) {
     size_t o = size_t(D) * P.max_nodes * sizeof(double);
     pv.off_w = align16(o);
     if (OP == FEM_OP_MASS_W) o = pv.off_w + size_t(P.max_nodes) * sizeof(double);
+    if (OP == kOpElasNodal) o = pv.off_w + 2 * size_t(P.max_nodes) * sizeof(double);
     pv.off_row = align16(o);
     o = pv.off_row + size_t(P.max_rows) * sizeof(int4);
     pv.off_rowof = align16(o);
@@ -486,8 +540,8 @@ PairLds pair_lds(const PairPlan &P) {
 }
 
 template <int D, int OP, int S>
-hipError_t launch_pair_t(const PairPlan &P, const double *q, const double *w, double lam,
-                         double mu, double *values, int32_t *status, hipStream_t s) {
+hipError_t launch_pair_t(const PairPlan &P, const double *q, const double *w, const double *w2,
+                         double lam, double mu, double *values, int32_t *status, hipStream_t s) {
     PairLds L = pair_lds<D, OP>(P);
     if (L.bytes > 160 * 1024) return hipErrorNotSupported;   // caller falls back
     PairView pv = L.pv;
@@ -502,13 +556,14 @@ hipError_t launch_pair_t(const PairPlan &P, const double *q, const double *w, do
     pv.ent = P.ent;
     pv.q = q;
     pv.w = w;
+    pv.w2 = w2;
     pv.values = values;
     pv.nb = P.nb;
     pv.max_nodes = P.max_nodes;
     const void *fn = reinterpret_cast<const void *>(&k_pair<D, OP, S>);
     // persistent grid: resident workgroups per CU x CUs, a multiple of the 8 XCDs
-    static thread_local int cached[2][4][3] = {};
-    static thread_local size_t cached_lds[2][4][3] = {};
+    static thread_local int cached[2][5][3] = {};
+    static thread_local size_t cached_lds[2][5][3] = {};
     const int si = S == 1 ? 0 : (S == 2 ? 1 : 2);
     int &occ = cached[D - 2][OP][si];
     if (occ == 0 || cached_lds[D - 2][OP][si] != L.bytes) {
@@ -533,23 +588,27 @@ hipError_t launch_pair_t(const PairPlan &P, const double *q, const double *w, do
 }
 
 template <int D, int OP>
-hipError_t launch_pair_s(const PairPlan &P, const double *q, const double *w, double lam,
-                         double mu, double *values, int32_t *status, hipStream_t s) {
-    if (P.slots == 4) return launch_pair_t<D, OP, 4>(P, q, w, lam, mu, values, status, s);
-    if (P.slots == 1) return launch_pair_t<D, OP, 1>(P, q, w, lam, mu, values, status, s);
-    return launch_pair_t<D, OP, 2>(P, q, w, lam, mu, values, status, s);
+hipError_t launch_pair_s(const PairPlan &P, const double *q, const double *w, const double *w2,
+                         double lam, double mu, double *values, int32_t *status, hipStream_t s) {
+    if (P.slots == 4) return launch_pair_t<D, OP, 4>(P, q, w, w2, lam, mu, values, status, s);
+    if (P.slots == 1) return launch_pair_t<D, OP, 1>(P, q, w, w2, lam, mu, values, status, s);
+    return launch_pair_t<D, OP, 2>(P, q, w, w2, lam, mu, values, status, s);
 }
 
 template <int D>
-hipError_t launch_pair_d(const PairPlan &P, int op, const double *q, const double *w, double lam,
-                         double mu, double *values, int32_t *status, hipStream_t s) {
+hipError_t launch_pair_d(const PairPlan &P, int op, const double *q, const double *w,
+                         const double *w2, double lam, double mu, double *values,
+                         int32_t *status, hipStream_t s) {
     switch (op) {
-        case FEM_OP_MASS: return launch_pair_s<D, FEM_OP_MASS>(P, q, w, lam, mu, values, status, s);
+        case FEM_OP_MASS:
+            return launch_pair_s<D, FEM_OP_MASS>(P, q, w, w2, lam, mu, values, status, s);
         case FEM_OP_MASS_W:
-            return launch_pair_s<D, FEM_OP_MASS_W>(P, q, w, lam, mu, values, status, s);
+            return launch_pair_s<D, FEM_OP_MASS_W>(P, q, w, w2, lam, mu, values, status, s);
         case FEM_OP_STIFF:
-            return launch_pair_s<D, FEM_OP_STIFF>(P, q, w, lam, mu, values, status, s);
-        default: return launch_pair_s<D, FEM_OP_ELAS>(P, q, w, lam, mu, values, status, s);
+            return launch_pair_s<D, FEM_OP_STIFF>(P, q, w, w2, lam, mu, values, status, s);
+        case kOpElasNodal:
+            return launch_pair_s<D, kOpElasNodal>(P, q, w, w2, lam, mu, values, status, s);
+        default: return launch_pair_s<D, FEM_OP_ELAS>(P, q, w, w2, lam, mu, values, status, s);
     }
 }
 
@@ -652,16 +711,16 @@ fem_status upload_pairs(PairPlan &P, int R, int slots, bool tri, int d, int64_t 
 
 hipError_t launch_pair_layout(const PairPlan &P, int d, int op, const double *q, const double *w,
                               double lam, double mu, double *values, int32_t *status,
-                              hipStream_t s) {
-    return d == 2 ? launch_pair_d<2>(P, op, q, w, lam, mu, values, status, s)
-                  : launch_pair_d<3>(P, op, q, w, lam, mu, values, status, s);
+                              hipStream_t s, const double *w2) {
+    return d == 2 ? launch_pair_d<2>(P, op, q, w, w2, lam, mu, values, status, s)
+                  : launch_pair_d<3>(P, op, q, w, w2, lam, mu, values, status, s);
 }
 
 bool launch_pair(const fem_plan_data *p, int op, const double *q, const double *w, double lam,
-                 double mu, double *values, hipStream_t s, hipError_t *err) {
-    const PairPlan &P = op == FEM_OP_ELAS ? p->pvec : p->pscal;
+                 double mu, double *values, hipStream_t s, hipError_t *err, const double *w2) {
+    const PairPlan &P = is_elas(op) ? p->pvec : p->pscal;
     if (!P.ok) return false;
-    const hipError_t e = launch_pair_layout(P, p->d, op, q, w, lam, mu, values, p->status, s);
+    const hipError_t e = launch_pair_layout(P, p->d, op, q, w, lam, mu, values, p->status, s, w2);
     if (e == hipErrorNotSupported) return false;
     *err = e;
     return true;

@@ -49,6 +49,7 @@ _SIGS = {
     "fem_plan_pattern": ([P, I32, P, P, P], C.c_int),
     "fem_plan_slot_map": ([P, P, P], C.c_int),
     "fem_assemble_numeric": ([P, I32, P, P, D, D, P, P], C.c_int),
+    "fem_assemble_elasticity_nodal": ([P, P, P, P, P, P], C.c_int),
     "fem_assemble_backward": ([P, U32, P, P, P, P, P, P, P], C.c_int),
     "fem_csr_bilinear": ([P, I32, P, P, P, P, P], C.c_int),
     "fem_plan_sync_status": ([P, P], C.c_int),
@@ -149,6 +150,11 @@ def fem_assemble_numeric(plan: int, op: int, q: int, w: int | None, lam: float, 
                          values: int, stream=None):
     _check(load_library().fem_assemble_numeric(plan, op, q, w, lam, mu, values, _stream(stream)),
            "fem_assemble_numeric")
+
+
+def fem_assemble_elasticity_nodal(plan: int, q: int, lam: int, mu: int, values: int, stream=None):
+    _check(load_library().fem_assemble_elasticity_nodal(plan, q, lam, mu, values, _stream(stream)),
+           "fem_assemble_elasticity_nodal")
 
 
 def fem_assemble_backward(plan: int, op_mask: int, q: int, w: int | None, a: int, b: int,
@@ -310,6 +316,16 @@ class Plan:
             out = torch.empty(max(nnz, 1), dtype=torch.float64, device=self.device)
         fem_assemble_numeric(self.handle, _op(op), q.data_ptr(), _ptr(w), float(lam), float(mu),
                              out.data_ptr(), stream)
+        return out[:nnz]
+
+    def elasticity_nodal(self, q, lam, mu, out=None, stream=None):
+        """Elasticity with nodal Lame fields lam, mu (nq values each)."""
+        _, nnz = self.query("ELAS")
+        q, lam, mu = (_dev_f64(x, self.device) for x in (q, lam, mu))
+        if out is None:
+            out = torch.empty(max(nnz, 1), dtype=torch.float64, device=self.device)
+        fem_assemble_elasticity_nodal(self.handle, q.data_ptr(), lam.data_ptr(), mu.data_ptr(),
+                                      out.data_ptr(), stream)
         return out[:nnz]
 
     def backward(self, q, w, a, b, op_mask=("STIFF", "MASS_W"), want_w=True, want_q=True,
