@@ -50,6 +50,9 @@
  * contribution to J (imaginary step 1e-30, so no truncation or cancellation
  * error), accumulated per vertex in ascending element order.
  *
+ * General second-order operator of the introduction with constant
+ * coefficients (weak form, full non-symmetric matrix): see the end of the file.
+ *
  * P_k Lagrange mass (Appendix D): element matrix d! |K| C with the constant
  * C of the paper's polynomial representation of the basis, evaluated in
  * exact integer arithmetic; local numbering and the rest at the end of the
@@ -879,4 +882,142 @@ int oracle_pk_mass_rows(int d, int k, int64_t nq, int64_t nme, const double *q,
     int st = pk_core(d, k, nq, nme, q, me, sel, nsel, cap, nnz_out, row_ptr, col_idx, val, absval);
     free(sel);
     return st;
+}
+
+
+/* ------------------------------------------------------------------------ */
+/* General second-order operator (the PDE of the introduction):              */
+/*   -div(A grad u) + div(b u) + c . grad u + a0 u                            */
+/* with constant A (d x d, row-major), b, c (d) and a0, in the weak form      */
+/* obtained by testing with v and integrating the divergence terms by parts   */
+/* (boundary terms left out):                                                 */
+/*   int A grad u . grad v  -  int u b . grad v  +  int (c . grad u) v        */
+/*   +  int a0 u v.                                                           */
+/* Element matrix, row a (test lambda_a), column b (trial lambda_b):          */
+/*   |K| g_a^T A g_b - |K|/(d+1) b.g_a + |K|/(d+1) c.g_b                       */
+/*   + a0 |K| d! (1+delta_ab)/(d+2)!   (magic formula for int lambda).        */
+/* Not symmetric in general: the full matrix is assembled (OptV, not OptVS).  */
+/* coef = [A (d*d), b (d), c (d), a0].                                        */
+/* ------------------------------------------------------------------------ */
+
+static int general_element(int d, const double P[MAXNL][MAXD], const double *coef,
+                           double E[MAXNL][MAXNL], double Ea[MAXNL][MAXNL]) {
+    double vol, G[MAXD][MAXNL];
+    if (!element_geometry(d, P, &vol, G)) return 0;
+    const int nl = d + 1;
+    const double *A = coef, *bv = coef + d * d, *cv = coef + d * d + d;
+    const double a0v = coef[d * d + 2 * d];
+    double anorm = 0.0, bn = 0.0, cn = 0.0, gmax = 0.0;
+    for (int i = 0; i < d * d; ++i) anorm += fabs(A[i]);
+    for (int i = 0; i < d; ++i) { bn += fabs(bv[i]); cn += fabs(cv[i]); }
+    for (int a = 0; a < nl; ++a) {
+        double g = 0.0;
+        for (int i = 0; i < d; ++i) g += fabs(G[i][a]);
+        if (g > gmax) gmax = g;
+    }
+    for (int a = 0; a < nl; ++a)
+        for (int b = 0; b < nl; ++b) {
+            double diff = 0.0;
+            for (int i = 0; i < d; ++i)
+                for (int j = 0; j < d; ++j) diff += G[i][a] * A[i * d + j] * G[j][b];
+            double conv_b = 0.0, conv_c = 0.0;
+            for (int i = 0; i < d; ++i) {
+                conv_b += bv[i] * G[i][a];
+                conv_c += cv[i] * G[i][b];
+            }
+            int ex[MAXNL] = {0, 0, 0, 0};
+            ex[a] += 1;
+            ex[b] += 1;
+            const double mass = magic_factor(d, ex);
+            E[a][b] = vol * diff - vol / nl * conv_b + vol / nl * conv_c + a0v * vol * mass;
+            Ea[a][b] = vol * (anorm * gmax * gmax + (bn + cn) * gmax / nl + fabs(a0v) * mass);
+        }
+    return 1;
+}
+
+/* Full CSR of the general operator (nrows = nq), or of the nsel global rows
+ * listed in rows (rows NULL: all). */
+int oracle_assemble_general(int d, int64_t nq, int64_t nme, const double *q, const int32_t *me,
+                            const double *coef, int64_t nsel, const int64_t *rows, int64_t cap,
+                            int64_t *nnz_out, int64_t *row_ptr, int64_t *col_idx, double *val,
+                            double *absval) {
+    if (d < 2 || d > 3 || !coef || nsel < 0) return OR_ERR_ARG;
+    int st = oracle_validate(d, nq, nme, me);
+    if (st != OR_OK) return st;
+    if (nme > 0 && !q) return OR_ERR_ARG;
+    int64_t *sel = NULL;
+    int64_t nout = nq;
+    if (rows) {
+        sel = (int64_t *)calloc((size_t)(nq > 0 ? nq : 1), sizeof(int64_t));
+        if (!sel) return OR_ERR_NOMEM;
+        for (int64_t s = 0; s < nsel; ++s) {
+            if (rows[s] < 0 || rows[s] >= nq || sel[rows[s]]) {
+                free(sel);
+                return OR_ERR_ARG;
+            }
+            sel[rows[s]] = s + 1;
+        }
+        nout = nsel;
+    }
+    const int nl = d + 1;
+    int64_t ntrip = 0;
+    for (int64_t k = 0; k < nme; ++k)
+        for (int a = 0; a < nl; ++a)
+            if (!sel || sel[me[(int64_t)a * nme + k]]) ntrip += nl;
+    triplet_t *T = (triplet_t *)malloc(sizeof(triplet_t) * (ntrip > 0 ? ntrip : 1));
+    if (!T) {
+        free(sel);
+        return OR_ERR_NOMEM;
+    }
+    int64_t t = 0;
+    for (int64_t k = 0; k < nme; ++k) {
+        int need = 0;
+        for (int a = 0; a < nl && !need; ++a) need = !sel || sel[me[(int64_t)a * nme + k]];
+        if (!need) continue;
+        int32_t vid[MAXNL];
+        double P[MAXNL][MAXD], E[MAXNL][MAXNL], Ea[MAXNL][MAXNL];
+        gather_element(d, nq, nme, q, me, k, P, vid);
+        if (!general_element(d, P, coef, E, Ea)) {
+            free(T);
+            free(sel);
+            return OR_ERR_DEGENERATE;
+        }
+        for (int b = 0; b < nl; ++b)
+            for (int a = 0; a < nl; ++a) {
+                const int64_t r = vid[a];
+                if (sel && !sel[r]) continue;
+                T[t].row = sel ? sel[r] - 1 : r;
+                T[t].col = vid[b];
+                T[t].seq = t;
+                T[t].val = E[a][b];
+                T[t].aval = Ea[a][b];
+                ++t;
+            }
+    }
+    free(sel);
+    qsort(T, (size_t)t, sizeof(triplet_t), cmp_triplet);
+    int64_t nnz = 0;
+    for (int64_t i = 0; i < t; ++i)
+        if (i == 0 || T[i].row != T[i - 1].row || T[i].col != T[i - 1].col) ++nnz;
+    if (nnz > cap) {
+        free(T);
+        return OR_ERR_OVERFLOW;
+    }
+    for (int64_t r = 0; r <= nout; ++r) row_ptr[r] = 0;
+    int64_t s = -1;
+    for (int64_t i = 0; i < t; ++i) {
+        if (i == 0 || T[i].row != T[i - 1].row || T[i].col != T[i - 1].col) {
+            ++s;
+            col_idx[s] = T[i].col;
+            val[s] = 0.0;
+            if (absval) absval[s] = 0.0;
+            row_ptr[T[i].row + 1] += 1;
+        }
+        val[s] += T[i].val;
+        if (absval) absval[s] += T[i].aval;
+    }
+    for (int64_t r = 0; r < nout; ++r) row_ptr[r + 1] += row_ptr[r];
+    *nnz_out = nnz;
+    free(T);
+    return OR_OK;
 }

@@ -63,6 +63,8 @@ def _load():
         lib.oracle_element_matrix.argtypes = [C.c_int, C.c_int, P, P, C.c_double, C.c_double, P]
         lib.oracle_assemble_lame.argtypes = [C.c_int, i64, i64, P, P, P, P, i64, P, i64, P, P, P,
                                              P, P]
+        lib.oracle_assemble_general.argtypes = [C.c_int, i64, i64, P, P, P, i64, P, i64, P, P, P,
+                                                P, P]
         lib.oracle_pk_coeff.argtypes = [C.c_int, C.c_int, P]
         lib.oracle_pk_alpha.argtypes = [C.c_int, C.c_int, P]
         lib.oracle_pk_mass.argtypes = [C.c_int, C.c_int, i64, i64, P, P, i64, P, P, P, P, P]
@@ -71,7 +73,7 @@ def _load():
         for f in (lib.oracle_validate, lib.oracle_assemble, lib.oracle_assemble_rows,
                   lib.oracle_grad, lib.oracle_element_matrix, lib.oracle_pk_coeff,
                   lib.oracle_pk_alpha, lib.oracle_pk_mass, lib.oracle_pk_mass_rows,
-                  lib.oracle_assemble_lame):
+                  lib.oracle_assemble_lame, lib.oracle_assemble_general):
             f.restype = C.c_int
         _lib = lib
     return _lib
@@ -166,6 +168,42 @@ def assemble_lame(q, me, lam, mu, rows=None):
             continue
         if st:
             raise OracleError(st, "assemble_lame")
+        n = nnz.value
+        return rp, ci[:n].copy(), v[:n].copy(), av[:n].copy()
+
+
+def general_coef(d, A=None, b=None, c=None, a0=0.0):
+    """Packed coefficients [A (d*d, row-major), b (d), c (d), a0]."""
+    A = np.zeros((d, d)) if A is None else np.asarray(A, float).reshape(d, d)
+    b = np.zeros(d) if b is None else np.asarray(b, float).reshape(d)
+    c = np.zeros(d) if c is None else np.asarray(c, float).reshape(d)
+    return np.ascontiguousarray(np.concatenate([A.ravel(), b, c, [float(a0)]]))
+
+
+def assemble_general(q, me, coef, rows=None):
+    """General operator -div(A grad u) + div(b u) + c.grad u + a0 u (constant
+    coefficients, weak form) as CSR over the nq rows (or the listed rows)."""
+    d, q, me = _mesh_arrays(q, me)
+    nq, nme = q.shape[1], me.shape[1]
+    coef = np.ascontiguousarray(coef, np.float64)
+    assert coef.shape == (d * d + 2 * d + 1,)
+    rsel = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    nout = nq if rsel is None else len(rsel)
+    cap = max(1, nme * (d + 1) ** 2) if rsel is None else max(1, len(rsel) * 64)
+    while True:
+        rp = np.zeros(nout + 1, np.int64)
+        ci = np.zeros(cap, np.int64)
+        v = np.zeros(cap, np.float64)
+        av = np.zeros(cap, np.float64)
+        nnz = C.c_int64(0)
+        st = _load().oracle_assemble_general(d, nq, nme, _ptr(q), _ptr(me), _ptr(coef),
+                                             0 if rsel is None else len(rsel), _ptr(rsel), cap,
+                                             C.byref(nnz), _ptr(rp), _ptr(ci), _ptr(v), _ptr(av))
+        if st == 4 and rsel is not None:
+            cap *= 4
+            continue
+        if st:
+            raise OracleError(st, "assemble_general")
         n = nnz.value
         return rp, ci[:n].copy(), v[:n].copy(), av[:n].copy()
 
