@@ -11,7 +11,8 @@ Prints one JSON line.  Besides the headline numbers it carries:
                 the 8 TB/s peak (kernel time from HIP events on its stream)
   cpu_baseline  the CPU oracle on a bounded prefix of the same element list
   extra         elasticity on the same mesh (constant and nodal Lame
-                parameters), symbolic-phase time, batched vs
+                parameters), the general second-order operator, symbolic-phase
+                time, batched vs
                 per-mesh launches, the 2D 2048^2 workload (stiffness, weighted
                 mass, elasticity), adjoint time, the 3D P_k mass for k = 1..6
                 on about 1e6 nodes (skipped with --no-extra)
@@ -109,7 +110,18 @@ def extras(torch, femasm, mg, plan, q, stream, steps):
     out["elas_nodal_3d"] = {"elements_per_s": plan.nme / t, "nnz_per_s": nnz_e / t,
                             "ms": t * 1e3, "alg_GBps": ab / t / 1e9,
                             "frac": ab / t / 1e9 / PEAK_HBM_GBS}
-    del vals, lam_f, mu_f
+    # the general second-order operator (constant coefficients, non-symmetric)
+    _, nnz_s = plan.query("STIFF")
+    vals_s = torch.empty(nnz_s, dtype=torch.float64, device=q.device)
+    coef = [2.0, 0.3, -0.1, 0.2, 1.5, 0.4, -0.2, 0.1, 1.0, 0.5, -0.4, 0.3, 0.2, 0.6, -0.7, 0.8]
+    fn = lambda: femasm.fem_assemble_general(plan.handle, q.data_ptr(), coef, vals_s.data_ptr(),
+                                            stream.cuda_stream)
+    _, per = time_launches(fn, stream, max(3, steps // 4), 2)
+    t = statistics.mean(per) / 1e3
+    ab = algorithmic_bytes(3, plan.nq, plan.nme, nnz_s)
+    out["general_3d"] = {"elements_per_s": plan.nme / t, "nnz_per_s": nnz_s / t, "ms": t * 1e3,
+                         "alg_GBps": ab / t / 1e9, "frac": ab / t / 1e9 / PEAK_HBM_GBS}
+    del vals, lam_f, mu_f, vals_s
     # batched vs per-mesh launches (256 meshes, weighted mass + stiffness)
     cfg = mg.config_batch()
     meshes = cfg["meshes"]

@@ -149,6 +149,29 @@ fem_status fem_assemble_elasticity_nodal(fem_plan plan, const double *q, const d
                                          const double *mu, double *values, hipStream_t stream);
 
 /*
+ * General second-order operator of the paper's introduction,
+ *   -div(A grad u) + div(b u) + c . grad u + a0 u,
+ * with constant coefficients, in the weak form obtained by testing with the
+ * P1 basis and integrating the divergence terms by parts (boundary terms
+ * left out):  int A grad u.grad v - int u b.grad v + int (c.grad u) v
+ * + int a0 u v.  Element matrix, row a (test), column b (trial):
+ *   |K| g_a^T A g_b - |K|/(d+1) b.g_a + |K|/(d+1) c.g_b
+ *   + a0 |K| d! (1 + delta_ab) / (d+2)!      (magic formula, Section 2).
+ * Not symmetric in general: the full matrix (OptV rather than OptVS) is
+ * written into the scalar pattern of the plan (nq rows, fem_plan_pattern
+ * with FEM_OP_STIFF), entries summed in ascending element number.
+ *   q       device, d*nq doubles
+ *   coef    HOST array of d*d + 2*d + 1 doubles: A row-major (A[i*d+j]
+ *           multiplies d u/d x_j in component i of the flux), b, c, a0
+ *   values  device, nnz doubles, fully overwritten
+ * Asynchronous, no allocation.  Runs on the vertex-pair kernel only:
+ * FEM_ERR_OVERFLOW for a mesh without that layout; FEM_ERR_ARG for null
+ * arrays.  Degenerate elements as in fem_assemble_numeric.
+ */
+fem_status fem_assemble_general(fem_plan plan, const double *q, const double *coef,
+                                double *values, hipStream_t stream);
+
+/*
  * Adjoint of J(q, w) = a^T (S(q) + M_w(q)) b: the sum over elements of
  * a_K^T (E_stiff(K) + E_mass_w(K)) b_K, differentiated through the element
  * Jacobians (the gradient systems of Appendix C.1 give

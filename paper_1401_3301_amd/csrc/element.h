@@ -128,6 +128,7 @@ __device__ __forceinline__ double elas_combine_nodal(double xl_ln, double xm_nl,
 template <int D>
 struct Fact {
     static constexpr double dfact = D == 2 ? 2.0 : 6.0;           // d!
+    static constexpr double d1fact = D == 2 ? 6.0 : 24.0;         // (d+1)!
     static constexpr double mass_den = D == 2 ? 24.0 : 120.0;     // (d+2)!
     static constexpr double massw_den = D == 2 ? 120.0 : 720.0;   // (d+3)!
 };

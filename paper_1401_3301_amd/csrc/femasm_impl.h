@@ -74,6 +74,10 @@ constexpr int kPairWaves = 8;     // wavefronts per workgroup of the pair kernel
 // Internal operator code of elasticity with nodal (P1) Lame fields
 // (fem_assemble_elasticity_nodal); the vertex-pair kernel only.
 constexpr int kOpElasNodal = 4;
+// Internal operator code of the general second-order operator
+// (fem_assemble_general); the vertex-pair kernel only.
+constexpr int kOpGeneral = 5;
+constexpr int kGeneralCoef = 16;   // A (d*d), b (d), c (d), a0, padded
 
 struct fem_plan_data {
     int d = 0;
@@ -115,14 +119,16 @@ fem_status upload_pairs(PairPlan &P, int R, int slots, bool tri, int d, int64_t 
 // Launches the pair kernel; returns false (nothing launched) when the plan
 // has no pair layout for this operator.
 // w2: the mu field of kOpElasNodal (w is then the lambda field).
+// gco: host coefficients of kOpGeneral (kGeneralCoef doubles).
 bool launch_pair(const fem_plan_data *p, int op, const double *q, const double *w, double lam,
                  double mu, double *values, hipStream_t s, hipError_t *err,
-                 const double *w2 = nullptr);
+                 const double *w2 = nullptr, const double *gco = nullptr);
 // Launches the pair kernel over a layout of dimension d (hipErrorNotSupported:
 // its LDS need exceeds the workgroup limit, nothing launched).
 hipError_t launch_pair_layout(const PairPlan &P, int d, int op, const double *q, const double *w,
                               double lam, double mu, double *values, int32_t *status,
-                              hipStream_t s, const double *w2 = nullptr);
+                              hipStream_t s, const double *w2 = nullptr,
+                              const double *gco = nullptr);
 // Concatenates per-mesh pair layouts into one (block descriptors carry each
 // mesh's coordinate / weight / value offsets and vertex count).  out.ok is
 // false when some part has no layout or the slot counts differ.

@@ -195,6 +195,20 @@ extern "C" fem_status fem_assemble_elasticity_nodal(fem_plan plan, const double 
     return FEM_ERR_OVERFLOW;   // no vertex-pair layout for this mesh
 }
 
+extern "C" fem_status fem_assemble_general(fem_plan plan, const double *q, const double *coef,
+                                          double *values, hipStream_t stream) {
+    if (!plan || !coef) return FEM_ERR_ARG;
+    if (plan->nnz > 0 && (!q || !values)) return FEM_ERR_ARG;
+    if (plan->nnz == 0) return FEM_OK;
+    const int d = plan->d;
+    double gco[kGeneralCoef] = {};
+    for (int i = 0; i < d * d + 2 * d + 1; ++i) gco[i] = coef[i];
+    hipError_t e = hipSuccess;
+    if (launch_pair(plan, kOpGeneral, q, nullptr, 0.0, 0.0, values, stream, &e, nullptr, gco))
+        return hip_status(e);
+    return FEM_ERR_OVERFLOW;   // no vertex-pair layout for this mesh
+}
+
 extern "C" fem_status fem_plan_pattern(fem_plan plan, int32_t op, int32_t *row_ptr,
                                        int32_t *col_idx, hipStream_t stream) {
     if (!plan || op < FEM_OP_MASS || op > FEM_OP_ELAS || !row_ptr) return FEM_ERR_ARG;

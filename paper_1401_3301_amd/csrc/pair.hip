@@ -56,6 +56,7 @@ struct PairView {
     const double *q;
     const double *w;
     const double *w2;     // mu field (nodal Lame elasticity; w is the lambda field)
+    double gco[kGeneralCoef];   // general operator: A (d x d, row-major), b, c, a0
     double *values;
     int32_t nb, max_nodes;
     uint32_t off_w, off_row, off_rowof, off_ev, off_ent;
@@ -73,10 +74,13 @@ struct PairOp {
     static constexpr int NL = D + 1;
     static constexpr int NV0 = OP == FEM_OP_ELAS      ? NL * D
                                : OP == kOpElasNodal ? NL * D + 2
+                               : OP == kOpGeneral   ? NL * NL
                                                     : NL * (NL + 1) / 2;
     static constexpr int NV = NV0 | 1;
     static constexpr int M = is_elas(OP) ? D : 1;
-    static constexpr int NX = OP == kOpElasNodal ? 2 * M * M : M * M;   // register sums per pair
+    // register sums per pair (the general operator also sums its mirror's
+    // transposed entries)
+    static constexpr int NX = OP == kOpElasNodal ? 2 * M * M : OP == kOpGeneral ? 2 : M * M;
 };
 
 template <int NL>
@@ -140,7 +144,8 @@ __device__ __forceinline__ int wave_task(uint64_t wp, int w) {
 
 template <int D, int OP>
 __device__ __forceinline__ void element_values(const double (&P)[D + 1][D], const double *wl,
-                                               const double *wl2, double *out, int &bad) {
+                                               const double *wl2, const double *gco, double *out,
+                                               int &bad) {
     constexpr int NL = D + 1;
     if constexpr (OP == FEM_OP_MASS || OP == FEM_OP_MASS_W) {
         // the same operations as the row-gather kernel: (1+delta) k, and
@@ -182,6 +187,44 @@ __device__ __forceinline__ void element_values(const double (&P)[D + 1][D], cons
             for (int a = 0; a < NL; ++a)
 #pragma unroll
                 for (int b = a; b < NL; ++b) out[tri_index<NL>(a, b)] = cdot<D>(E.c[a], E.c[b]) * inv;
+        } else if constexpr (OP == kOpGeneral) {
+            // full element matrix, row a (test), column b (trial), with
+            // g = c/det and |K| = |det|/d!:
+            //   |K| g_a^T A g_b        = c_a^T A c_b / (d! |det|)
+            //   |K|/(d+1) b.g_a        = sign(det) b.c_a / (d+1)!
+            //   |K|/(d+1) c.g_b        = sign(det) c.c_b / (d+1)!
+            //   a0 |K| d!(1+delta)/(d+2)! = a0 |det| (1+delta) / (d+2)!
+            const double *A = gco;
+            double bv[D], cv[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                bv[i] = gco[D * D + i];
+                cv[i] = gco[D * D + D + i];
+            }
+            const double a0 = gco[D * D + 2 * D];
+            const double ad = fabs(E.det);
+            const double inv = deg ? 0.0 : 1.0 / (Fact<D>::dfact * ad);
+            const double f1 = deg ? 0.0 : (E.det > 0.0 ? 1.0 : -1.0) / Fact<D>::d1fact;
+            const double fm = deg ? 0.0 : a0 * ad / Fact<D>::mass_den;
+            double Ac[NL][D], tb[NL], tc[NL];
+#pragma unroll
+            for (int b = 0; b < NL; ++b) {
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    double s = A[i * D] * E.c[b][0];
+#pragma unroll
+                    for (int j = 1; j < D; ++j) s = fma(A[i * D + j], E.c[b][j], s);
+                    Ac[b][i] = s;
+                }
+                tb[b] = cdot<D>(bv, E.c[b]) * f1;
+                tc[b] = cdot<D>(cv, E.c[b]) * f1;
+            }
+#pragma unroll
+            for (int a = 0; a < NL; ++a)
+#pragma unroll
+                for (int b = 0; b < NL; ++b)
+                    out[a * NL + b] = ((cdot<D>(E.c[a], Ac[b]) * inv - tb[a]) + tc[b]) +
+                                      (a == b ? 2.0 * fm : fm);
         } else {
             const double sc = deg ? 0.0 : elas_scale<D>(E.det);
 #pragma unroll
@@ -377,7 +420,7 @@ __global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, doubl
                     if constexpr (kW) wl[a] = wv[v[a]];
                     if constexpr (kW2) wl2[a] = wv[MN + v[a]];
                 }
-                element_values<D, OP>(P, wl, wl2, ev + e * NV, bad);
+                element_values<D, OP>(P, wl, wl2, pv.gco, ev + e * NV, bad);
             } else if (e == dc.ne) {
 #pragma unroll
                 for (int t = 0; t < NV; ++t) ev[e * NV + t] = 0.0;
@@ -428,6 +471,10 @@ __global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, doubl
                                 X[s][l * D + n] = fma(lk, xln, X[s][l * D + n]);
                                 X[s][M2 + l * D + n] = fma(mk, xln, X[s][M2 + l * D + n]);
                             }
+                    } else if constexpr (OP == kOpGeneral) {
+                        const int a = int((x >> 10) & 3u), b = int((x >> 12) & 3u);
+                        X[s][0] += Ee[a * NL + b];
+                        X[s][1] += Ee[b * NL + a];
                     } else {
                         X[s][0] += Ee[(x >> 10) & 15u];
                     }
@@ -478,6 +525,9 @@ __global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, doubl
                             o[l * D * ri.y + n] = v;
                             if (o2) o2[n * D * len2 + l] = v;
                         }
+                } else if constexpr (OP == kOpGeneral) {
+                    o[0] = X[s][0];
+                    if (o2) o2[0] = X[s][1];
                 } else {
                     o[0] = X[s][0];
                     if (o2) o2[0] = X[s][0];
@@ -541,7 +591,8 @@ PairLds pair_lds(const PairPlan &P) {
 
 template <int D, int OP, int S>
 hipError_t launch_pair_t(const PairPlan &P, const double *q, const double *w, const double *w2,
-                         double lam, double mu, double *values, int32_t *status, hipStream_t s) {
+                         const double *gco, double lam, double mu, double *values,
+                         int32_t *status, hipStream_t s) {
     PairLds L = pair_lds<D, OP>(P);
     if (L.bytes > 160 * 1024) return hipErrorNotSupported;   // caller falls back
     PairView pv = L.pv;
@@ -557,13 +608,14 @@ hipError_t launch_pair_t(const PairPlan &P, const double *q, const double *w, co
     pv.q = q;
     pv.w = w;
     pv.w2 = w2;
+    for (int i = 0; i < kGeneralCoef; ++i) pv.gco[i] = gco ? gco[i] : 0.0;
     pv.values = values;
     pv.nb = P.nb;
     pv.max_nodes = P.max_nodes;
     const void *fn = reinterpret_cast<const void *>(&k_pair<D, OP, S>);
     // persistent grid: resident workgroups per CU x CUs, a multiple of the 8 XCDs
-    static thread_local int cached[2][5][3] = {};
-    static thread_local size_t cached_lds[2][5][3] = {};
+    static thread_local int cached[2][6][3] = {};
+    static thread_local size_t cached_lds[2][6][3] = {};
     const int si = S == 1 ? 0 : (S == 2 ? 1 : 2);
     int &occ = cached[D - 2][OP][si];
     if (occ == 0 || cached_lds[D - 2][OP][si] != L.bytes) {
@@ -589,26 +641,30 @@ hipError_t launch_pair_t(const PairPlan &P, const double *q, const double *w, co
 
 template <int D, int OP>
 hipError_t launch_pair_s(const PairPlan &P, const double *q, const double *w, const double *w2,
-                         double lam, double mu, double *values, int32_t *status, hipStream_t s) {
-    if (P.slots == 4) return launch_pair_t<D, OP, 4>(P, q, w, w2, lam, mu, values, status, s);
-    if (P.slots == 1) return launch_pair_t<D, OP, 1>(P, q, w, w2, lam, mu, values, status, s);
-    return launch_pair_t<D, OP, 2>(P, q, w, w2, lam, mu, values, status, s);
+                         const double *gco, double lam, double mu, double *values,
+                         int32_t *status, hipStream_t s) {
+    if (P.slots == 4) return launch_pair_t<D, OP, 4>(P, q, w, w2, gco, lam, mu, values, status, s);
+    if (P.slots == 1) return launch_pair_t<D, OP, 1>(P, q, w, w2, gco, lam, mu, values, status, s);
+    return launch_pair_t<D, OP, 2>(P, q, w, w2, gco, lam, mu, values, status, s);
 }
 
 template <int D>
 hipError_t launch_pair_d(const PairPlan &P, int op, const double *q, const double *w,
-                         const double *w2, double lam, double mu, double *values,
-                         int32_t *status, hipStream_t s) {
+                         const double *w2, const double *gco, double lam, double mu,
+                         double *values, int32_t *status, hipStream_t s) {
     switch (op) {
         case FEM_OP_MASS:
-            return launch_pair_s<D, FEM_OP_MASS>(P, q, w, w2, lam, mu, values, status, s);
+            return launch_pair_s<D, FEM_OP_MASS>(P, q, w, w2, gco, lam, mu, values, status, s);
         case FEM_OP_MASS_W:
-            return launch_pair_s<D, FEM_OP_MASS_W>(P, q, w, w2, lam, mu, values, status, s);
+            return launch_pair_s<D, FEM_OP_MASS_W>(P, q, w, w2, gco, lam, mu, values, status, s);
         case FEM_OP_STIFF:
-            return launch_pair_s<D, FEM_OP_STIFF>(P, q, w, w2, lam, mu, values, status, s);
+            return launch_pair_s<D, FEM_OP_STIFF>(P, q, w, w2, gco, lam, mu, values, status, s);
         case kOpElasNodal:
-            return launch_pair_s<D, kOpElasNodal>(P, q, w, w2, lam, mu, values, status, s);
-        default: return launch_pair_s<D, FEM_OP_ELAS>(P, q, w, w2, lam, mu, values, status, s);
+            return launch_pair_s<D, kOpElasNodal>(P, q, w, w2, gco, lam, mu, values, status, s);
+        case kOpGeneral:
+            return launch_pair_s<D, kOpGeneral>(P, q, w, w2, gco, lam, mu, values, status, s);
+        default:
+            return launch_pair_s<D, FEM_OP_ELAS>(P, q, w, w2, gco, lam, mu, values, status, s);
     }
 }
 
@@ -711,16 +767,19 @@ fem_status upload_pairs(PairPlan &P, int R, int slots, bool tri, int d, int64_t 
 
 hipError_t launch_pair_layout(const PairPlan &P, int d, int op, const double *q, const double *w,
                               double lam, double mu, double *values, int32_t *status,
-                              hipStream_t s, const double *w2) {
-    return d == 2 ? launch_pair_d<2>(P, op, q, w, w2, lam, mu, values, status, s)
-                  : launch_pair_d<3>(P, op, q, w, w2, lam, mu, values, status, s);
+                              hipStream_t s, const double *w2, const double *gco) {
+    return d == 2 ? launch_pair_d<2>(P, op, q, w, w2, gco, lam, mu, values, status, s)
+                  : launch_pair_d<3>(P, op, q, w, w2, gco, lam, mu, values, status, s);
 }
 
 bool launch_pair(const fem_plan_data *p, int op, const double *q, const double *w, double lam,
-                 double mu, double *values, hipStream_t s, hipError_t *err, const double *w2) {
-    const PairPlan &P = is_elas(op) ? p->pvec : p->pscal;
+                 double mu, double *values, hipStream_t s, hipError_t *err, const double *w2,
+                 const double *gco) {
+    // the (a, b)-coded layout serves elasticity and the non-symmetric operator
+    const PairPlan &P = is_elas(op) || op == kOpGeneral ? p->pvec : p->pscal;
     if (!P.ok) return false;
-    const hipError_t e = launch_pair_layout(P, p->d, op, q, w, lam, mu, values, p->status, s, w2);
+    const hipError_t e =
+        launch_pair_layout(P, p->d, op, q, w, lam, mu, values, p->status, s, w2, gco);
     if (e == hipErrorNotSupported) return false;
     *err = e;
     return true;

@@ -50,6 +50,7 @@ _SIGS = {
     "fem_plan_slot_map": ([P, P, P], C.c_int),
     "fem_assemble_numeric": ([P, I32, P, P, D, D, P, P], C.c_int),
     "fem_assemble_elasticity_nodal": ([P, P, P, P, P, P], C.c_int),
+    "fem_assemble_general": ([P, P, P, P, P], C.c_int),
     "fem_assemble_backward": ([P, U32, P, P, P, P, P, P, P], C.c_int),
     "fem_csr_bilinear": ([P, I32, P, P, P, P, P], C.c_int),
     "fem_plan_sync_status": ([P, P], C.c_int),
@@ -155,6 +156,13 @@ def fem_assemble_numeric(plan: int, op: int, q: int, w: int | None, lam: float, 
 def fem_assemble_elasticity_nodal(plan: int, q: int, lam: int, mu: int, values: int, stream=None):
     _check(load_library().fem_assemble_elasticity_nodal(plan, q, lam, mu, values, _stream(stream)),
            "fem_assemble_elasticity_nodal")
+
+
+def fem_assemble_general(plan: int, q: int, coef, values: int, stream=None):
+    """coef: host sequence of d*d + 2*d + 1 doubles (A row-major, b, c, a0)."""
+    arr = (D * len(coef))(*[float(x) for x in coef])
+    _check(load_library().fem_assemble_general(plan, q, arr, values, _stream(stream)),
+           "fem_assemble_general")
 
 
 def fem_assemble_backward(plan: int, op_mask: int, q: int, w: int | None, a: int, b: int,
@@ -326,6 +334,17 @@ class Plan:
             out = torch.empty(max(nnz, 1), dtype=torch.float64, device=self.device)
         fem_assemble_elasticity_nodal(self.handle, q.data_ptr(), lam.data_ptr(), mu.data_ptr(),
                                       out.data_ptr(), stream)
+        return out[:nnz]
+
+    def general(self, q, coef, out=None, stream=None):
+        """General operator with constant coefficients coef = [A, b, c, a0]."""
+        _, nnz = self.query("STIFF")
+        if len(coef) != self.d * self.d + 2 * self.d + 1:
+            raise ValueError("coef must hold d*d + 2*d + 1 values")
+        q = _dev_f64(q, self.device)
+        if out is None:
+            out = torch.empty(max(nnz, 1), dtype=torch.float64, device=self.device)
+        fem_assemble_general(self.handle, q.data_ptr(), list(coef), out.data_ptr(), stream)
         return out[:nnz]
 
     def backward(self, q, w, a, b, op_mask=("STIFF", "MASS_W"), want_w=True, want_q=True,
