@@ -50,6 +50,10 @@
  * contribution to J (imaginary step 1e-30, so no truncation or cancellation
  * error), accumulated per vertex in ascending element order.
  *
+ * Mass and weighted mass on boundary facets ((d-1)-simplices, the Neumann /
+ * Robin terms of the remark after Algorithm AssemblyMassWP1): measure from
+ * the Gram determinant; see the end of the file.
+ *
  * General second-order operator of the introduction with constant
  * coefficients (weak form, full non-symmetric matrix): see the end of the file.
  *
@@ -1017,6 +1021,114 @@ int oracle_assemble_general(int d, int64_t nq, int64_t nme, const double *q, con
         if (absval) absval[s] += T[i].aval;
     }
     for (int64_t r = 0; r < nout; ++r) row_ptr[r + 1] += row_ptr[r];
+    *nnz_out = nnz;
+    free(T);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Mass and weighted mass on a mesh of n-simplices embedded in R^d, n < d   */
+/* (boundary facets, n = d-1: Neumann / Robin terms).  The closed forms of   */
+/* Section 4.1 hold with d replaced by n and |K| the n-dimensional measure,  */
+/* sqrt(det(B^T B)) / n! for the d x n edge matrix B (Gram determinant):     */
+/*   mass      n! |K| (1+delta_ab) / (n+2)!                                  */
+/*   weighted  sum_g w_g int lambda_g lambda_a lambda_b (magic formula).     */
+/* facets is (n+1) x nf, w NULL for the plain mass.                           */
+/* ------------------------------------------------------------------------ */
+
+static double gram_measure(int d, int n, const double P[MAXNL][MAXD]) {
+    double B[MAXD][MAXD], G[MAXD][MAXD];
+    for (int i = 0; i < d; ++i)
+        for (int c = 0; c < n; ++c) B[i][c] = P[c + 1][i] - P[0][i];
+    for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) {
+            double s = 0.0;
+            for (int i = 0; i < d; ++i) s += B[i][a] * B[i][b];
+            G[a][b] = s;
+        }
+    double det;
+    if (n == 1) det = G[0][0];
+    else det = G[0][0] * G[1][1] - G[0][1] * G[1][0];
+    if (det <= 0.0) return 0.0;
+    return sqrt(det) / factorial(n);
+}
+
+int oracle_boundary_mass(int d, int64_t nq, int64_t nf, const double *q, const int32_t *facets,
+                         const double *w, int64_t cap, int64_t *nnz_out, int64_t *row_ptr,
+                         int64_t *col_idx, double *val, double *absval) {
+    if (d < 2 || d > 3 || nq < 0 || nf < 0 || (nf > 0 && (!q || !facets))) return OR_ERR_ARG;
+    const int n = d - 1, nl = n + 1;
+    for (int64_t k = 0; k < nf; ++k)
+        for (int a = 0; a < nl; ++a) {
+            const int32_t v = facets[(int64_t)a * nf + k];
+            if (v < 0 || (int64_t)v >= nq) return OR_ERR_INDEX;
+            for (int b = 0; b < a; ++b)
+                if (facets[(int64_t)b * nf + k] == v) return OR_ERR_INDEX;
+        }
+    const int64_t ntrip = nf * nl * nl;
+    triplet_t *T = (triplet_t *)malloc(sizeof(triplet_t) * (ntrip > 0 ? ntrip : 1));
+    if (!T) return OR_ERR_NOMEM;
+    int64_t t = 0;
+    for (int64_t k = 0; k < nf; ++k) {
+        double P[MAXNL][MAXD];
+        int32_t vid[MAXNL];
+        for (int a = 0; a < nl; ++a) {
+            vid[a] = facets[(int64_t)a * nf + k];
+            for (int i = 0; i < d; ++i) P[a][i] = q[(int64_t)i * nq + vid[a]];
+        }
+        const double vol = gram_measure(d, n, P);
+        if (vol == 0.0) {
+            free(T);
+            return OR_ERR_DEGENERATE;
+        }
+        for (int b = 0; b < nl; ++b)
+            for (int a = 0; a < nl; ++a) {
+                double s = 0.0, sa = 0.0;
+                if (!w) {
+                    int ex[MAXNL] = {0, 0, 0, 0};
+                    ex[a] += 1;
+                    ex[b] += 1;
+                    s = sa = magic_factor(n, ex);
+                } else {
+                    for (int g = 0; g < nl; ++g) {
+                        int ex[MAXNL] = {0, 0, 0, 0};
+                        ex[a] += 1;
+                        ex[b] += 1;
+                        ex[g] += 1;
+                        s += w[vid[g]] * magic_factor(n, ex);
+                        sa += fabs(w[vid[g]]) * magic_factor(n, ex);
+                    }
+                }
+                T[t].row = vid[a];
+                T[t].col = vid[b];
+                T[t].seq = t;
+                T[t].val = vol * s;
+                T[t].aval = vol * sa;
+                ++t;
+            }
+    }
+    qsort(T, (size_t)t, sizeof(triplet_t), cmp_triplet);
+    int64_t nnz = 0;
+    for (int64_t i = 0; i < t; ++i)
+        if (i == 0 || T[i].row != T[i - 1].row || T[i].col != T[i - 1].col) ++nnz;
+    if (nnz > cap) {
+        free(T);
+        return OR_ERR_OVERFLOW;
+    }
+    for (int64_t r = 0; r <= nq; ++r) row_ptr[r] = 0;
+    int64_t s = -1;
+    for (int64_t i = 0; i < t; ++i) {
+        if (i == 0 || T[i].row != T[i - 1].row || T[i].col != T[i - 1].col) {
+            ++s;
+            col_idx[s] = T[i].col;
+            val[s] = 0.0;
+            if (absval) absval[s] = 0.0;
+            row_ptr[T[i].row + 1] += 1;
+        }
+        val[s] += T[i].val;
+        if (absval) absval[s] += T[i].aval;
+    }
+    for (int64_t r = 0; r < nq; ++r) row_ptr[r + 1] += row_ptr[r];
     *nnz_out = nnz;
     free(T);
     return OR_OK;

@@ -65,6 +65,7 @@ def _load():
                                              P, P]
         lib.oracle_assemble_general.argtypes = [C.c_int, i64, i64, P, P, P, i64, P, i64, P, P, P,
                                                 P, P]
+        lib.oracle_boundary_mass.argtypes = [C.c_int, i64, i64, P, P, P, i64, P, P, P, P, P]
         lib.oracle_pk_coeff.argtypes = [C.c_int, C.c_int, P]
         lib.oracle_pk_alpha.argtypes = [C.c_int, C.c_int, P]
         lib.oracle_pk_mass.argtypes = [C.c_int, C.c_int, i64, i64, P, P, i64, P, P, P, P, P]
@@ -73,7 +74,8 @@ def _load():
         for f in (lib.oracle_validate, lib.oracle_assemble, lib.oracle_assemble_rows,
                   lib.oracle_grad, lib.oracle_element_matrix, lib.oracle_pk_coeff,
                   lib.oracle_pk_alpha, lib.oracle_pk_mass, lib.oracle_pk_mass_rows,
-                  lib.oracle_assemble_lame, lib.oracle_assemble_general):
+                  lib.oracle_assemble_lame, lib.oracle_assemble_general,
+                  lib.oracle_boundary_mass):
             f.restype = C.c_int
         _lib = lib
     return _lib
@@ -206,6 +208,28 @@ def assemble_general(q, me, coef, rows=None):
             raise OracleError(st, "assemble_general")
         n = nnz.value
         return rp, ci[:n].copy(), v[:n].copy(), av[:n].copy()
+
+
+def boundary_mass(q, facets, w=None):
+    """Mass (w None) or weighted mass on (d-1)-simplices ``facets`` ((d, nf)
+    int32) embedded in R^d; CSR over the nq vertices."""
+    q = np.ascontiguousarray(q, np.float64)
+    facets = np.ascontiguousarray(facets, np.int32)
+    d, nq = q.shape
+    nf = facets.shape[1]
+    cap = max(1, nf * d * d)
+    rp = np.zeros(nq + 1, np.int64)
+    ci = np.zeros(cap, np.int64)
+    v = np.zeros(cap, np.float64)
+    av = np.zeros(cap, np.float64)
+    nnz = C.c_int64(0)
+    wv = None if w is None else np.ascontiguousarray(w, np.float64)
+    st = _load().oracle_boundary_mass(d, nq, nf, _ptr(q), _ptr(facets), _ptr(wv), cap,
+                                      C.byref(nnz), _ptr(rp), _ptr(ci), _ptr(v), _ptr(av))
+    if st:
+        raise OracleError(st, "boundary_mass")
+    k = nnz.value
+    return rp, ci[:k].copy(), v[:k].copy(), av[:k].copy()
 
 
 def grad(q, me, w, a, b, want_w: bool = True, want_q: bool = True, with_abs: bool = False):

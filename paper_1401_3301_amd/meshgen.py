@@ -53,6 +53,7 @@ __all__ = [
     "Mesh", "jittered_square", "kuhn_cube", "lognormal_field", "normal_field",
     "config_small_2d", "config_large_2d", "config_large_3d", "config_batch",
     "config_adjoint", "interior_mask", "pk_local_indices", "pk_mesh", "config_pk",
+    "boundary_facets",
 ]
 
 
@@ -219,6 +220,20 @@ def pk_mesh(mesh: Mesh, k: int) -> Mesh:
     meta = dict(mesh.meta)
     meta["k"] = k
     return Mesh(d, np.ascontiguousarray(q), me, mesh.n, meta)
+
+
+def boundary_facets(mesh: Mesh) -> np.ndarray:
+    """The (d-1)-simplices that belong to exactly one element (the boundary of
+    a conforming mesh), as a (d, nf) int32 array; each facet lists its
+    vertices in ascending id, facets in ascending order of that tuple."""
+    d, me = mesh.d, mesh.me.astype(np.int64)
+    faces = []
+    for drop in range(d + 1):
+        keep = [a for a in range(d + 1) if a != drop]
+        faces.append(np.sort(me[keep].T, axis=1))
+    f = np.concatenate(faces)
+    uniq, cnt = np.unique(f, axis=0, return_counts=True)
+    return np.ascontiguousarray(uniq[cnt == 1].T.astype(np.int32))
 
 
 def lognormal_field(nq: int, seed: int, sigma: float = 0.5) -> np.ndarray:
