@@ -11,8 +11,8 @@ Prints one JSON line.  Besides the headline numbers it carries:
                 the 8 TB/s peak (kernel time from HIP events on its stream)
   cpu_baseline  the CPU oracle on a bounded prefix of the same element list
   extra         elasticity on the same mesh (constant and nodal Lame
-                parameters), the general second-order operator, symbolic-phase
-                time, batched vs
+                parameters), the general second-order operator, the boundary
+                weighted mass of the cube's surface, symbolic-phase time, batched vs
                 per-mesh launches, the 2D 2048^2 workload (stiffness, weighted
                 mass, elasticity), adjoint time, the 3D P_k mass for k = 1..6
                 on about 1e6 nodes (skipped with --no-extra)
@@ -86,7 +86,7 @@ def cpu_baseline(mesh, nsample=3_000_000):
                       f"(all vertices), full oracle assembly incl. CSR emission, {dt:.1f} s"}
 
 
-def extras(torch, femasm, mg, plan, q, stream, steps):
+def extras(torch, femasm, mg, plan, q, stream, steps, mesh):
     out = {}
     # elasticity on the same plan
     nrows, nnz_e = plan.query("ELAS")
@@ -122,6 +122,19 @@ def extras(torch, femasm, mg, plan, q, stream, steps):
     out["general_3d"] = {"elements_per_s": plan.nme / t, "nnz_per_s": nnz_s / t, "ms": t * 1e3,
                          "alg_GBps": ab / t / 1e9, "frac": ab / t / 1e9 / PEAK_HBM_GBS}
     del vals, lam_f, mu_f, vals_s
+    # boundary (Robin) weighted mass on the surface of the cube
+    facets = torch.from_numpy(mg.boundary_facets(mesh)).to(q.device)
+    bplan = femasm.BoundaryPlan(facets, plan.nq)
+    wb = torch.from_numpy(mg.lognormal_field(plan.nq, 120)).to(q.device)
+    vb = torch.empty(max(bplan.nnz, 1), dtype=torch.float64, device=q.device)
+    fn = lambda: femasm.fem_boundary_mass(bplan.handle, q.data_ptr(), wb.data_ptr(),
+                                         vb.data_ptr(), stream.cuda_stream)
+    _, per = time_launches(fn, stream, 20, 3)
+    bplan.sync_status()
+    t = statistics.mean(per) / 1e3
+    out["boundary_mass_w_3d"] = {"facets": bplan.nf, "nnz": bplan.nnz, "ms": t * 1e3,
+                                 "facets_per_s": bplan.nf / t}
+    del bplan, vb, wb, facets
     # batched vs per-mesh launches (256 meshes, weighted mass + stiffness)
     cfg = mg.config_batch()
     meshes = cfg["meshes"]
@@ -341,7 +354,7 @@ def main():
         line["cpu_baseline"] = cpu_baseline(mesh)
     if not args.no_extra and args.op == "STIFF":
         print("[bench] extras ...", file=sys.stderr, flush=True)
-        line["extra"] = extras(torch, femasm, mg, plan, q, stream, args.steps)
+        line["extra"] = extras(torch, femasm, mg, plan, q, stream, args.steps, mesh)
     print(json.dumps(line), flush=True)
 
 

@@ -320,6 +320,35 @@ fem_status fem_pk_sync_status(fem_pk_plan plan, hipStream_t stream);
 /* Frees the plan (NULL is ignored).  Work using it must have completed. */
 void fem_pk_destroy(fem_pk_plan plan);
 
+/*
+ * Boundary terms (Neumann / Robin): mass and weighted mass on a mesh of
+ * (d-1)-simplices embedded in R^d, typically the boundary facets of a
+ * volume mesh.  The paper notes (remark after the weighted-mass algorithm
+ * of Section 4.1) that the weighted-mass assembly applies to n-simplices
+ * with n <= d; here n = d-1, |K| is the n-dimensional measure (segment
+ * length, triangle area) and the element matrices are
+ *   mass      n! |K| (1 + delta_ab) / (n+2)!
+ *   weighted  n! |K| (1 + delta_ab) (w^s + w_a + w_b) / (n+3)!
+ * (magic formula with d replaced by n).  The plan is a fem_pk_plan (query,
+ * pattern, status and destroy as above): nq rows over all vertices, rows of
+ * vertices on no facet empty.
+ *   d       2 (facets are segments) or 3 (triangles)
+ *   facets  device, d*nf int32, facets[a*nf + f] = vertex a of facet f
+ * Errors as fem_pk_symbolic.  Synchronous.
+ */
+fem_status fem_boundary_symbolic(int32_t d, int64_t nq, int64_t nf, const int32_t *facets,
+                                 hipStream_t stream, fem_pk_plan *out);
+
+/* Values of the boundary mass (w NULL) or weighted mass (w device, nq
+ * doubles) for vertex coordinates q (device, d*nq doubles) into values
+ * (device, nnz doubles, fully overwritten).  Two kernels on `stream` (facet
+ * matrices into a plan-owned work array, then the entry sums); no host
+ * synchronisation, no allocation.  A facet of zero measure sets the plan's
+ * status word.  FEM_ERR_ARG for a plan not made by fem_boundary_symbolic
+ * (and fem_pk_mass refuses boundary plans). */
+fem_status fem_boundary_mass(fem_pk_plan plan, const double *q, const double *w, double *values,
+                             hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

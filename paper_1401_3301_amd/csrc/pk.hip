@@ -36,6 +36,7 @@ namespace femasm {
 
 struct fem_pk_data {
     int d = 0, k = 0, n = 0, ntri = 0, ebits = 0;
+    bool boundary = false;          // facets of dimension d-1 embedded in R^d (k = 1)
     int64_t nq = 0, nme = 0, nnz = 0, ntiles = 0, nitems = 0;
     int max_tile_items = 0;
     int device = 0;
@@ -46,6 +47,7 @@ struct fem_pk_data {
     uint32_t *item = nullptr;       // element | tri code << ebits
     double *ctri = nullptr;         // [ntri]
     double *vol = nullptr;          // [nme] |det B_K| (work array of the numeric phase)
+    double *ev = nullptr;           // boundary plans: [nme*ntri] element matrices (work array)
     int32_t *status = nullptr;
 };
 
@@ -64,8 +66,8 @@ fem_status pk_upload(T **dst, const std::vector<T> &src) {
 }
 
 void pk_free(fem_pk_data *p) {
-    void *ptrs[] = {p->rp,   p->ci,   p->gme,  p->tile_item, p->coff,
-                    p->item, p->ctri, p->vol,  p->status};
+    void *ptrs[] = {p->rp,   p->ci,   p->gme, p->tile_item, p->coff,
+                    p->item, p->ctri, p->vol, p->ev,        p->status};
     for (void *x : ptrs)
         if (x) (void)hipFree(x);
 }
@@ -98,11 +100,71 @@ __global__ __launch_bounds__(256) void k_pk_vol(const int32_t *__restrict__ gme,
 constexpr int kPkMaxChunk = 3072;
 constexpr int kPkRegs = kPkMaxChunk / kPkThreads;
 
+// Boundary facets ((D-1)-simplices in R^D): the packed element matrix of
+// the mass (ctri times n!|K|) or of the weighted mass
+// n!|K| (1+delta) (w^s + w_a + w_b) / (n+3)!, n = D-1, with n!|K| the
+// length of a segment (D = 2) or |e1 x e2| of a triangle (D = 3).
+template <int D, bool W>
+__global__ __launch_bounds__(256) void k_bnd_elem(const int32_t *__restrict__ gme, int64_t nf,
+                                                  const double *__restrict__ q, int64_t nq,
+                                                  const double *__restrict__ w,
+                                                  const double *__restrict__ ctri,
+                                                  double *__restrict__ ev, int32_t *status) {
+    constexpr int NL = D;                       // vertices of a facet
+    constexpr int NT = NL * (NL + 1) / 2;
+    constexpr double kDen = D == 2 ? 24.0 : 120.0;   // (n+3)!
+    const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (e >= nf) return;
+    double P[NL][D];
+    int64_t v[NL];
+#pragma unroll
+    for (int a = 0; a < NL; ++a) {
+        v[a] = gme[a * nf + e];
+#pragma unroll
+        for (int x = 0; x < D; ++x) P[a][x] = q[x * nq + v[a]];
+    }
+    double m;
+    if constexpr (D == 2) {
+        const double dx = P[1][0] - P[0][0], dy = P[1][1] - P[0][1];
+        m = sqrt(fma(dx, dx, dy * dy));
+    } else {
+        double e1[3], e2[3];
+#pragma unroll
+        for (int x = 0; x < 3; ++x) {
+            e1[x] = P[1][x] - P[0][x];
+            e2[x] = P[2][x] - P[0][x];
+        }
+        const double cx = fma(e1[1], e2[2], -(e1[2] * e2[1]));
+        const double cy = fma(e1[2], e2[0], -(e1[0] * e2[2]));
+        const double cz = fma(e1[0], e2[1], -(e1[1] * e2[0]));
+        m = sqrt(fma(cx, cx, fma(cy, cy, cz * cz)));
+    }
+    if (m == 0.0) atomicOr(status, 1);
+    double *out = ev + e * NT;
+    if constexpr (!W) {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) out[t] = m * ctri[t];
+    } else {
+        double wl[NL];
+#pragma unroll
+        for (int a = 0; a < NL; ++a) wl[a] = w[v[a]];
+        double ws = wl[0];
+#pragma unroll
+        for (int a = 1; a < NL; ++a) ws += wl[a];
+        const double k = m / kDen;
+        int t = 0;
+#pragma unroll
+        for (int a = 0; a < NL; ++a)
+#pragma unroll
+            for (int b = a; b < NL; ++b, ++t) out[t] = (a == b ? 2.0 * k : k) * (ws + (wl[a] + wl[b]));
+    }
+}
+
 __global__ __launch_bounds__(kPkThreads) void k_pk_mass(
     const int64_t *__restrict__ tile_item, const uint16_t *__restrict__ coff,
     const uint32_t *__restrict__ item, const double *__restrict__ ctri, int ntri, int ebits,
-    int chunk, const double *__restrict__ vol, int64_t ntiles, int64_t nnz,
-    double *__restrict__ values) {
+    int chunk, const double *__restrict__ vol, const double *__restrict__ ev, int64_t ntiles,
+    int64_t nnz, double *__restrict__ values) {
     extern __shared__ double lds[];
     double *sc = lds;                    // C, packed triangle
     double *sp = lds + ntri;             // products of the current chunk
@@ -151,7 +213,9 @@ __global__ __launch_bounds__(kPkThreads) void k_pk_mass(
 #pragma unroll
             for (int r = 0; r < kPkRegs; ++r) {
                 const int u = tid + kPkThreads * r;
-                if (u < cn) sp[u] = vol[x[r] & emask] * sc[x[r] >> ebits];
+                if (u < cn)
+                    sp[u] = ev ? ev[int64_t(x[r] & emask) * ntri + (x[r] >> ebits)]
+                               : vol[x[r] & emask] * sc[x[r] >> ebits];
             }
         }
         if (tile + gridDim.x < ntiles) fetch(tile + gridDim.x);
@@ -168,7 +232,8 @@ __global__ __launch_bounds__(kPkThreads) void k_pk_mass(
             __syncthreads();
             for (int u = tid; u < cn; u += kPkThreads) {
                 const uint32_t xx = item[ti0 + cb + u];
-                sp[u] = vol[xx & emask] * sc[xx >> ebits];
+                sp[u] = ev ? ev[int64_t(xx & emask) * ntri + (xx >> ebits)]
+                           : vol[xx & emask] * sc[xx >> ebits];
             }
             __syncthreads();
 #pragma unroll
@@ -222,12 +287,13 @@ using namespace femasm;
 
 struct fem_pk_plan_s : femasm::fem_pk_data {};
 
-extern "C" fem_status fem_pk_symbolic(int32_t d, int32_t k, int64_t nq, int64_t nme,
-                                      const int32_t *me, hipStream_t stream, fem_pk_plan *out) {
-    if (!out || (d != 2 && d != 3) || k < 1 || k > kPkMaxK || nq < 0 || nme < 0 ||
-        (nme > 0 && !me))
-        return FEM_ERR_ARG;
-    const int n = int(pk_nodes(d, k).size());
+namespace {
+
+// Plan over an N x nme connectivity of sdim-simplices (sdim = d for P_k
+// meshes, d - 1 for boundary facets) with d coordinates per node.
+fem_status pk_build(int sdim, int d, int k, bool boundary, int64_t nq, int64_t nme,
+                    const int32_t *me, hipStream_t stream, fem_pk_plan *out) {
+    const int n = int(pk_nodes(sdim, k).size());
     if (int64_t(n) * nme >= (int64_t(1) << 31) || nq >= (int64_t(1) << 31) - 1)
         return FEM_ERR_OVERFLOW;
     std::vector<int32_t> hme(size_t(n) * nme);
@@ -238,16 +304,18 @@ extern "C" fem_status fem_pk_symbolic(int32_t d, int32_t k, int64_t nq, int64_t 
         if (e != hipSuccess) return hip_status(e);
     }
     unsigned hc = std::thread::hardware_concurrency();
-    PkHost H = build_pk_host(d, k, nq, nme, hme.data(), int(std::max(1u, std::min(hc ? hc : 4u, 16u))));
+    PkHost H = build_pk_host(sdim, k, nq, nme, hme.data(),
+                             int(std::max(1u, std::min(hc ? hc : 4u, 16u))));
     if (H.status == 2) return FEM_ERR_INDEX;
     if (H.status != 0) return FEM_ERR_OVERFLOW;
-    std::vector<int32_t> gme(size_t(d + 1) * nme);
+    std::vector<int32_t> gme(size_t(sdim + 1) * nme);   // the vertex rows
     std::copy(hme.begin(), hme.begin() + gme.size(), gme.begin());
 
     std::unique_ptr<fem_pk_plan_s> p(new fem_pk_plan_s());
     p->d = d;
     p->k = k;
     p->n = n;
+    p->boundary = boundary;
     p->ntri = H.ntri;
     p->ebits = H.ebits;
     p->nq = nq;
@@ -264,7 +332,9 @@ extern "C" fem_status fem_pk_symbolic(int32_t d, int32_t k, int64_t nq, int64_t 
     if (st == FEM_OK) st = pk_upload(&p->coff, H.coff);
     if (st == FEM_OK) st = pk_upload(&p->item, H.item);
     if (st == FEM_OK) st = pk_upload(&p->ctri, H.ctri);
-    if (st == FEM_OK) st = pk_upload(&p->vol, std::vector<double>(size_t(nme), 0.0));
+    if (st == FEM_OK && !boundary) st = pk_upload(&p->vol, std::vector<double>(size_t(nme), 0.0));
+    if (st == FEM_OK && boundary)
+        st = pk_upload(&p->ev, std::vector<double>(size_t(nme) * H.ntri, 0.0));
     if (st == FEM_OK) st = pk_upload(&p->status, std::vector<int32_t>(1, 0));
     if (st != FEM_OK) {
         pk_free(p.get());
@@ -272,6 +342,60 @@ extern "C" fem_status fem_pk_symbolic(int32_t d, int32_t k, int64_t nq, int64_t 
     }
     *out = p.release();
     return FEM_OK;
+}
+
+fem_status pk_sum(fem_pk_plan plan, double *values, hipStream_t stream) {
+    const int chunk = pk_chunk(plan->ntri);
+    const size_t lds = sizeof(double) * (size_t(plan->ntri) + size_t(chunk));
+    const int grid = pk_grid(lds, plan->ntiles);
+    hipLaunchKernelGGL(k_pk_mass, dim3(grid), dim3(kPkThreads), lds, stream, plan->tile_item,
+                       plan->coff, plan->item, plan->ctri, plan->ntri, plan->ebits, chunk,
+                       plan->boundary ? nullptr : plan->vol, plan->boundary ? plan->ev : nullptr,
+                       plan->ntiles, plan->nnz, values);
+    return hip_status(hipGetLastError());
+}
+
+}  // namespace
+
+extern "C" fem_status fem_pk_symbolic(int32_t d, int32_t k, int64_t nq, int64_t nme,
+                                      const int32_t *me, hipStream_t stream, fem_pk_plan *out) {
+    if (!out || (d != 2 && d != 3) || k < 1 || k > kPkMaxK || nq < 0 || nme < 0 ||
+        (nme > 0 && !me))
+        return FEM_ERR_ARG;
+    return pk_build(d, d, k, false, nq, nme, me, stream, out);
+}
+
+extern "C" fem_status fem_boundary_symbolic(int32_t d, int64_t nq, int64_t nf,
+                                            const int32_t *facets, hipStream_t stream,
+                                            fem_pk_plan *out) {
+    if (!out || (d != 2 && d != 3) || nq < 0 || nf < 0 || (nf > 0 && !facets)) return FEM_ERR_ARG;
+    return pk_build(d - 1, d, 1, true, nq, nf, facets, stream, out);
+}
+
+extern "C" fem_status fem_boundary_mass(fem_pk_plan plan, const double *q, const double *w,
+                                        double *values, hipStream_t stream) {
+    if (!plan || !plan->boundary || (plan->nme > 0 && !q) || (plan->nnz > 0 && !values))
+        return FEM_ERR_ARG;
+    if (plan->nnz == 0) return FEM_OK;
+    const unsigned g = unsigned((plan->nme + 255) / 256);
+    if (plan->d == 2) {
+        if (w)
+            hipLaunchKernelGGL((k_bnd_elem<2, true>), dim3(g), dim3(256), 0, stream, plan->gme,
+                               plan->nme, q, plan->nq, w, plan->ctri, plan->ev, plan->status);
+        else
+            hipLaunchKernelGGL((k_bnd_elem<2, false>), dim3(g), dim3(256), 0, stream, plan->gme,
+                               plan->nme, q, plan->nq, w, plan->ctri, plan->ev, plan->status);
+    } else {
+        if (w)
+            hipLaunchKernelGGL((k_bnd_elem<3, true>), dim3(g), dim3(256), 0, stream, plan->gme,
+                               plan->nme, q, plan->nq, w, plan->ctri, plan->ev, plan->status);
+        else
+            hipLaunchKernelGGL((k_bnd_elem<3, false>), dim3(g), dim3(256), 0, stream, plan->gme,
+                               plan->nme, q, plan->nq, w, plan->ctri, plan->ev, plan->status);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_status(e);
+    return pk_sum(plan, values, stream);
 }
 
 extern "C" fem_status fem_pk_query(fem_pk_plan plan, int64_t *nrows, int64_t *nnz, int32_t *ndfe) {
@@ -295,7 +419,8 @@ extern "C" fem_status fem_pk_pattern(fem_pk_plan plan, int32_t *row_ptr, int32_t
 
 extern "C" fem_status fem_pk_mass(fem_pk_plan plan, const double *q, double *values,
                                   hipStream_t stream) {
-    if (!plan || (plan->nme > 0 && !q) || (plan->nnz > 0 && !values)) return FEM_ERR_ARG;
+    if (!plan || plan->boundary || (plan->nme > 0 && !q) || (plan->nnz > 0 && !values))
+        return FEM_ERR_ARG;
     if (plan->nnz == 0) return FEM_OK;
     if (plan->nme > 0) {
         const unsigned g = unsigned((plan->nme + 255) / 256);
@@ -308,13 +433,7 @@ extern "C" fem_status fem_pk_mass(fem_pk_plan plan, const double *q, double *val
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_status(e);
     }
-    const int chunk = pk_chunk(plan->ntri);
-    const size_t lds = sizeof(double) * (size_t(plan->ntri) + size_t(chunk));
-    const int grid = pk_grid(lds, plan->ntiles);
-    hipLaunchKernelGGL(k_pk_mass, dim3(grid), dim3(kPkThreads), lds, stream, plan->tile_item,
-                       plan->coff, plan->item, plan->ctri, plan->ntri, plan->ebits, chunk,
-                       plan->vol, plan->ntiles, plan->nnz, values);
-    return hip_status(hipGetLastError());
+    return pk_sum(plan, values, stream);
 }
 
 extern "C" fem_status fem_pk_sync_status(fem_pk_plan plan, hipStream_t stream) {

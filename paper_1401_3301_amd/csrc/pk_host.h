@@ -41,17 +41,23 @@ constexpr int kPkTile = kPkThreads * kPkPer;   // CSR entries per tile
 using PkMono = std::array<int, 4>;
 using PkPoly = std::map<PkMono, __int128>;
 
+// Local nodes of a d-simplex (d = 1, 2, 3) in the numbering above.
 inline std::vector<PkMono> pk_nodes(int d, int k) {
     std::vector<PkMono> all, out;
     // every composition of k into d+1 parts, decreasing lexicographic
-    for (int a0 = k; a0 >= 0; --a0)
-        for (int a1 = k - a0; a1 >= 0; --a1) {
-            if (d == 2) {
-                all.push_back({a0, a1, k - a0 - a1, 0});
-                continue;
-            }
-            for (int a2 = k - a0 - a1; a2 >= 0; --a2) all.push_back({a0, a1, a2, k - a0 - a1 - a2});
+    PkMono cur{0, 0, 0, 0};
+    auto rec = [&](auto &&self, int i, int left) -> void {
+        if (i == d) {
+            cur[i] = left;
+            all.push_back(cur);
+            return;
         }
+        for (int a = left; a >= 0; --a) {
+            cur[i] = a;
+            self(self, i + 1, left - a);
+        }
+    };
+    rec(rec, 0, k);
     for (int v = 0; v <= d; ++v) {
         PkMono a{0, 0, 0, 0};
         a[v] = k;
@@ -160,7 +166,8 @@ struct PkHost {
     std::vector<double> ctri;
 };
 
-// me: host, N x nme (row-major, me[a*nme + e]).
+// me: host, N x nme (row-major, me[a*nme + e]); d is the simplex dimension
+// (1 for boundary segments, 2 for boundary triangles or 2D meshes, 3).
 inline PkHost build_pk_host(int d, int k, int64_t nq, int64_t nme, const int32_t *me,
                             int nthreads) {
     PkHost H;

@@ -69,6 +69,8 @@ _SIGS = {
     "fem_pk_mass": ([P, P, P, P], C.c_int),
     "fem_pk_sync_status": ([P, P], C.c_int),
     "fem_pk_destroy": ([P], None),
+    "fem_boundary_symbolic": ([I32, I64, I64, P, P, C.POINTER(P)], C.c_int),
+    "fem_boundary_mass": ([P, P, P, P, P], C.c_int),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -264,6 +266,18 @@ def fem_pk_sync_status(plan: int, stream=None) -> int:
 def fem_pk_destroy(plan: int):
     if plan:
         load_library().fem_pk_destroy(plan)
+
+
+def fem_boundary_symbolic(d: int, nq: int, nf: int, facets_ptr: int, stream=None) -> int:
+    out = P()
+    _check(load_library().fem_boundary_symbolic(d, nq, nf, facets_ptr, _stream(stream),
+                                                C.byref(out)), "fem_boundary_symbolic")
+    return out.value
+
+
+def fem_boundary_mass(plan: int, q: int, w: int | None, values: int, stream=None):
+    _check(load_library().fem_boundary_mass(plan, q, w, values, _stream(stream)),
+           "fem_boundary_mass")
 
 
 # ------------------------------------------------------------ torch helpers
@@ -469,6 +483,47 @@ class PkPlan:
         if out is None:
             out = torch.empty(max(self.nnz, 1), dtype=torch.float64, device=self.device)
         fem_pk_mass(self.handle, q.data_ptr(), out.data_ptr(), stream)
+        return out[:self.nnz]
+
+    def sync_status(self, stream=None):
+        _check(fem_pk_sync_status(self.handle, stream), "fem_pk_sync_status")
+
+
+class BoundaryPlan:
+    """Plan of the boundary mass / weighted mass over (d-1)-simplices
+    ``facets`` (shape (d, nf)) embedded in R^d."""
+
+    def __init__(self, facets: torch.Tensor, nq: int, stream=None):
+        load_library()
+        if facets.dtype != torch.int32 or not facets.is_cuda or facets.dim() != 2:
+            raise ValueError("facets must be a CUDA int32 tensor of shape (d, nf)")
+        self.facets = facets.contiguous()
+        self.d = int(self.facets.shape[0])
+        self.nq = int(nq)
+        self.nf = int(self.facets.shape[1])
+        self.device = self.facets.device
+        self.handle = fem_boundary_symbolic(self.d, self.nq, self.nf,
+                                            self.facets.data_ptr() if self.nf else 0, stream)
+        _, self.nnz, _ = fem_pk_query(self.handle)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and _lib is not None:
+            fem_pk_destroy(h)
+            self.handle = None
+
+    def pattern(self, stream=None):
+        rp = torch.empty(self.nq + 1, dtype=torch.int32, device=self.device)
+        ci = torch.empty(max(self.nnz, 1), dtype=torch.int32, device=self.device)
+        fem_pk_pattern(self.handle, rp.data_ptr(), ci.data_ptr(), stream)
+        return rp, ci[:self.nnz]
+
+    def mass(self, q, w=None, out=None, stream=None):
+        q = _dev_f64(q, self.device)
+        w = _dev_f64(w, self.device)
+        if out is None:
+            out = torch.empty(max(self.nnz, 1), dtype=torch.float64, device=self.device)
+        fem_boundary_mass(self.handle, q.data_ptr(), _ptr(w), out.data_ptr(), stream)
         return out[:self.nnz]
 
     def sync_status(self, stream=None):

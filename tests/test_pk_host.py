@@ -137,3 +137,37 @@ def test_refusals(shim):
     bad = m.me.copy()
     bad[5, 0] = m.nq
     assert _build(shim, mg.Mesh(2, m.q, bad), 2)[0] == 2
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_boundary_facet_layout(shim, d):
+    """Boundary facets ((d-1)-simplices, k = 1): pattern and items against a
+    brute force, and C of the segment / triangle mass."""
+    m1 = mg.jittered_square(5, 0.2, seed=6) if d == 2 else mg.kuhn_cube(3, 0.1, seed=7)
+    f = mg.boundary_facets(m1)
+    fm = mg.Mesh(d - 1, m1.q, f)
+    me = np.ascontiguousarray(f, np.int32)
+    sizes = np.zeros(6, np.int64)
+    st = shim.pkh_build(d - 1, 1, ctypes.c_int64(m1.nq), ctypes.c_int64(f.shape[1]), _p(me),
+                        _p(sizes))
+    assert st == 0
+    nnz, ntiles, nitems, ebits, ntri, _ = (int(x) for x in sizes)
+    L = dict(rp=np.zeros(m1.nq + 1, np.int32), ci=np.zeros(nnz, np.int32),
+             tile_item=np.zeros(ntiles + 1, np.int64), coff=np.zeros(ntiles * TILE, np.uint16),
+             item=np.zeros(nitems, np.uint32), ctri=np.zeros(ntri), ebits=ebits)
+    shim.pkh_get(*(_p(L[x]) for x in ("rp", "ci", "tile_item", "coff", "item", "ctri")))
+    N = d
+    contrib = {}
+    for e in range(f.shape[1]):
+        for a in range(N):
+            for b in range(N):
+                contrib.setdefault((int(f[a, e]), int(f[b, e])), []).append((e, _tri(N, a, b)))
+    assert nnz == len(contrib)
+    for s in range(nnz):
+        i = int(np.searchsorted(L["rp"], s, side="right") - 1)
+        els, codes = _entry_items(L, s, nnz)
+        assert list(zip(els.tolist(), codes.tolist())) == contrib[(i, int(L["ci"][s]))]
+    n = d - 1
+    C = (1 + np.eye(N)) / math.factorial(n + 2)
+    np.testing.assert_allclose(L["ctri"], C[np.triu_indices(N)], rtol=1e-15)
+    assert fm.nme == f.shape[1]
