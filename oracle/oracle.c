@@ -50,6 +50,10 @@
  * contribution to J (imaginary step 1e-30, so no truncation or cancellation
  * error), accumulated per vertex in ascending element order.
  *
+ * Derivatives of the assembly map (JVP and VJP of the mass, weighted mass
+ * and stiffness operators) by complex-step differentiation of each element
+ * matrix: see the end of the file.
+ *
  * Mass and weighted mass on boundary facets ((d-1)-simplices, the Neumann /
  * Robin terms of the remark after Algorithm AssemblyMassWP1): measure from
  * the Gram determinant; see the end of the file.
@@ -1131,5 +1135,194 @@ int oracle_boundary_mass(int d, int64_t nq, int64_t nf, const double *q, const i
     for (int64_t r = 0; r < nq; ++r) row_ptr[r + 1] += row_ptr[r];
     *nnz_out = nnz;
     free(T);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Derivatives of the assembly map (q, w) -> A for the mass, weighted mass   */
+/* and stiffness operators, by complex-step differentiation of each element  */
+/* matrix (imaginary step 1e-30: no truncation or cancellation error).       */
+/*   JVP: dA = sum_K P_K^T dE(K) P_K, dE = Im E(q + i h dq, w + i h dw) / h,  */
+/*        summed by `sparse` as the assembly is;                              */
+/*   VJP: for L = sum_s G_s A_s, dL/dq and dL/dw accumulated per vertex in    */
+/*        ascending element number, G_s read at the CSR entry of each local   */
+/*        (row, column) pair (rp, ci: the operator's pattern).                 */
+/* ------------------------------------------------------------------------ */
+
+/* E (nl x nl) of MASS, MASS_W or STIFF in complex arithmetic. */
+static int element_matrix_c(int d, int op, double complex P[MAXNL][MAXD],
+                            const double complex *wl, double complex E[MAXNL][MAXNL]) {
+    double complex B[MAXD][MAXD], Bt[MAXD][MAXD], R[MAXD][MAXNL], G[MAXD][MAXNL];
+    for (int i = 0; i < d; ++i)
+        for (int c = 0; c < d; ++c) B[i][c] = P[c + 1][i] - P[0][i];
+    double complex det = det_cplx(d, B);
+    if (creal(det) == 0.0) return 0;
+    const int nl = d + 1;
+    const double complex vol = (creal(det) < 0 ? -det : det) / factorial(d);
+    if (op == OR_STIFF) {
+        for (int i = 0; i < d; ++i)
+            for (int c = 0; c < d; ++c) Bt[i][c] = B[c][i];
+        for (int i = 0; i < d; ++i) {
+            R[i][0] = -1.0;
+            for (int a = 1; a < nl; ++a) R[i][a] = (a - 1 == i) ? 1.0 : 0.0;
+        }
+        if (!solve_cplx(d, Bt, R, G)) return 0;
+    }
+    for (int a = 0; a < nl; ++a)
+        for (int b = 0; b < nl; ++b) {
+            double complex s = 0.0;
+            if (op == OR_STIFF) {
+                for (int i = 0; i < d; ++i) s += G[i][b] * G[i][a];
+            } else if (op == OR_MASS) {
+                int ex[MAXNL] = {0, 0, 0, 0};
+                ex[a] += 1; ex[b] += 1;
+                s = magic_factor(d, ex);
+            } else {
+                for (int g = 0; g < nl; ++g) {
+                    int ex[MAXNL] = {0, 0, 0, 0};
+                    ex[a] += 1; ex[b] += 1; ex[g] += 1;
+                    s += wl[g] * magic_factor(d, ex);
+                }
+            }
+            E[a][b] = vol * s;
+        }
+    return 1;
+}
+
+static int64_t csr_find(const int64_t *rp, const int64_t *ci, int64_t r, int64_t c) {
+    int64_t lo = rp[r], hi = rp[r + 1];
+    while (lo < hi) {
+        const int64_t m = (lo + hi) / 2;
+        if (ci[m] < c) lo = m + 1; else hi = m;
+    }
+    return (lo < rp[r + 1] && ci[lo] == c) ? lo : -1;
+}
+
+int oracle_jvp(int d, int64_t nq, int64_t nme, const double *q, const int32_t *me, int op,
+               const double *w, const double *dq, const double *dw, int64_t cap,
+               int64_t *nnz_out, int64_t *row_ptr, int64_t *col_idx, double *val, double *absval) {
+    int st = oracle_validate(d, nq, nme, me);
+    if (st != OR_OK) return st;
+    if (op != OR_MASS && op != OR_MASS_W && op != OR_STIFF) return OR_ERR_ARG;
+    if (nme > 0 && (!q || !dq || (op == OR_MASS_W && (!w || !dw)))) return OR_ERR_ARG;
+    const int nl = d + 1;
+    const double h = 1e-30;
+    triplet_t *T = (triplet_t *)malloc(sizeof(triplet_t) * (nme > 0 ? nme * nl * nl : 1));
+    if (!T) return OR_ERR_NOMEM;
+    int64_t t = 0;
+    for (int64_t k = 0; k < nme; ++k) {
+        int32_t vid[MAXNL];
+        double complex P[MAXNL][MAXD], wl[MAXNL], E[MAXNL][MAXNL];
+        for (int a = 0; a < nl; ++a) {
+            vid[a] = me[(int64_t)a * nme + k];
+            for (int i = 0; i < d; ++i)
+                P[a][i] = q[(int64_t)i * nq + vid[a]] + I * h * dq[(int64_t)i * nq + vid[a]];
+            wl[a] = op == OR_MASS_W ? w[vid[a]] + I * h * dw[vid[a]] : 0.0;
+        }
+        if (!element_matrix_c(d, op, P, wl, E)) {
+            free(T);
+            return OR_ERR_DEGENERATE;
+        }
+        for (int b = 0; b < nl; ++b)
+            for (int a = 0; a < nl; ++a) {
+                T[t].row = vid[a];
+                T[t].col = vid[b];
+                T[t].seq = t;
+                T[t].val = cimag(E[a][b]) / h;
+                T[t].aval = fabs(T[t].val);
+                ++t;
+            }
+    }
+    qsort(T, (size_t)t, sizeof(triplet_t), cmp_triplet);
+    int64_t nnz = 0;
+    for (int64_t i = 0; i < t; ++i)
+        if (i == 0 || T[i].row != T[i - 1].row || T[i].col != T[i - 1].col) ++nnz;
+    if (nnz > cap) {
+        free(T);
+        return OR_ERR_OVERFLOW;
+    }
+    for (int64_t r = 0; r <= nq; ++r) row_ptr[r] = 0;
+    int64_t s = -1;
+    for (int64_t i = 0; i < t; ++i) {
+        if (i == 0 || T[i].row != T[i - 1].row || T[i].col != T[i - 1].col) {
+            ++s;
+            col_idx[s] = T[i].col;
+            val[s] = 0.0;
+            if (absval) absval[s] = 0.0;
+            row_ptr[T[i].row + 1] += 1;
+        }
+        val[s] += T[i].val;
+        if (absval) absval[s] += T[i].aval;
+    }
+    for (int64_t r = 0; r < nq; ++r) row_ptr[r + 1] += row_ptr[r];
+    *nnz_out = nnz;
+    free(T);
+    return OR_OK;
+}
+
+/* VJP.  want[v] != 0 selects the vertices whose dq / dw are computed (NULL:
+ * all); dq_out is d x nq (like q), dw_out nq; either may be NULL.  The *_abs
+ * arrays receive the sums of |element contribution| (tolerance scale). */
+int oracle_vjp(int d, int64_t nq, int64_t nme, const double *q, const int32_t *me, int op,
+               const double *w, const int64_t *rp, const int64_t *ci, const double *G,
+               const uint8_t *want, double *dq_out, double *dw_out, double *dq_abs,
+               double *dw_abs) {
+    int st = oracle_validate(d, nq, nme, me);
+    if (st != OR_OK) return st;
+    if (op != OR_MASS && op != OR_MASS_W && op != OR_STIFF) return OR_ERR_ARG;
+    if (nme > 0 && (!q || !rp || !ci || !G || (op == OR_MASS_W && !w))) return OR_ERR_ARG;
+    const int nl = d + 1;
+    const double h = 1e-30;
+    if (dq_out) memset(dq_out, 0, sizeof(double) * (size_t)(d * nq));
+    if (dw_out) memset(dw_out, 0, sizeof(double) * (size_t)nq);
+    if (dq_abs) memset(dq_abs, 0, sizeof(double) * (size_t)(d * nq));
+    if (dw_abs) memset(dw_abs, 0, sizeof(double) * (size_t)nq);
+    for (int64_t k = 0; k < nme; ++k) {
+        int32_t vid[MAXNL];
+        int need = 0;
+        for (int a = 0; a < nl; ++a) {
+            vid[a] = me[(int64_t)a * nme + k];
+            need |= !want || want[vid[a]];
+        }
+        if (!need) continue;
+        double Gk[MAXNL][MAXNL];
+        for (int a = 0; a < nl; ++a)
+            for (int b = 0; b < nl; ++b) {
+                const int64_t s = csr_find(rp, ci, vid[a], vid[b]);
+                if (s < 0) return OR_ERR_INDEX;
+                Gk[a][b] = G[s];
+            }
+        double complex P0[MAXNL][MAXD], w0[MAXNL];
+        for (int a = 0; a < nl; ++a) {
+            for (int i = 0; i < d; ++i) P0[a][i] = q[(int64_t)i * nq + vid[a]];
+            w0[a] = op == OR_MASS_W ? w[vid[a]] : 0.0;
+        }
+        for (int c = 0; c < nl; ++c) {
+            if (want && !want[vid[c]]) continue;
+            for (int i = 0; i < d + 1; ++i) {
+                if (i == d && (op != OR_MASS_W || !dw_out)) continue;
+                if (i < d && !dq_out) continue;
+                double complex P[MAXNL][MAXD], wl[MAXNL], E[MAXNL][MAXNL];
+                memcpy(P, P0, sizeof(P));
+                memcpy(wl, w0, sizeof(wl));
+                if (i < d) P[c][i] += I * h;
+                else wl[c] += I * h;
+                if (!element_matrix_c(d, op, P, wl, E)) return OR_ERR_DEGENERATE;
+                double s = 0.0, sa = 0.0;
+                for (int a = 0; a < nl; ++a)
+                    for (int b = 0; b < nl; ++b) {
+                        s += Gk[a][b] * (cimag(E[a][b]) / h);
+                        sa += fabs(Gk[a][b] * (cimag(E[a][b]) / h));
+                    }
+                if (i < d) {
+                    dq_out[(int64_t)i * nq + vid[c]] += s;
+                    if (dq_abs) dq_abs[(int64_t)i * nq + vid[c]] += sa;
+                } else {
+                    dw_out[vid[c]] += s;
+                    if (dw_abs) dw_abs[vid[c]] += sa;
+                }
+            }
+        }
+    }
     return OR_OK;
 }

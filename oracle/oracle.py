@@ -66,6 +66,8 @@ def _load():
         lib.oracle_assemble_general.argtypes = [C.c_int, i64, i64, P, P, P, i64, P, i64, P, P, P,
                                                 P, P]
         lib.oracle_boundary_mass.argtypes = [C.c_int, i64, i64, P, P, P, i64, P, P, P, P, P]
+        lib.oracle_jvp.argtypes = [C.c_int, i64, i64, P, P, C.c_int, P, P, P, i64, P, P, P, P, P]
+        lib.oracle_vjp.argtypes = [C.c_int, i64, i64, P, P, C.c_int, P, P, P, P, P, P, P, P, P]
         lib.oracle_pk_coeff.argtypes = [C.c_int, C.c_int, P]
         lib.oracle_pk_alpha.argtypes = [C.c_int, C.c_int, P]
         lib.oracle_pk_mass.argtypes = [C.c_int, C.c_int, i64, i64, P, P, i64, P, P, P, P, P]
@@ -75,7 +77,7 @@ def _load():
                   lib.oracle_grad, lib.oracle_element_matrix, lib.oracle_pk_coeff,
                   lib.oracle_pk_alpha, lib.oracle_pk_mass, lib.oracle_pk_mass_rows,
                   lib.oracle_assemble_lame, lib.oracle_assemble_general,
-                  lib.oracle_boundary_mass):
+                  lib.oracle_boundary_mass, lib.oracle_jvp, lib.oracle_vjp):
             f.restype = C.c_int
         _lib = lib
     return _lib
@@ -230,6 +232,53 @@ def boundary_mass(q, facets, w=None):
         raise OracleError(st, "boundary_mass")
     k = nnz.value
     return rp, ci[:k].copy(), v[:k].copy(), av[:k].copy()
+
+
+def jvp(q, me, op: str, dq, w=None, dw=None):
+    """Directional derivative dA of the assembled operator (MASS, MASS_W or
+    STIFF) along (dq, dw), as CSR (row_ptr, col_idx, val, absval)."""
+    d, q, me = _mesh_arrays(q, me)
+    nq, nme = q.shape[1], me.shape[1]
+    dq = np.ascontiguousarray(dq, np.float64)
+    wv = None if w is None else np.ascontiguousarray(w, np.float64)
+    dwv = None if dw is None else np.ascontiguousarray(dw, np.float64)
+    cap = max(1, nme * (d + 1) ** 2)
+    rp = np.zeros(nq + 1, np.int64)
+    ci = np.zeros(cap, np.int64)
+    v = np.zeros(cap, np.float64)
+    av = np.zeros(cap, np.float64)
+    nnz = C.c_int64(0)
+    st = _load().oracle_jvp(d, nq, nme, _ptr(q), _ptr(me), OP[op], _ptr(wv), _ptr(dq), _ptr(dwv),
+                            cap, C.byref(nnz), _ptr(rp), _ptr(ci), _ptr(v), _ptr(av))
+    if st:
+        raise OracleError(st, "jvp")
+    n = nnz.value
+    return rp, ci[:n].copy(), v[:n].copy(), av[:n].copy()
+
+
+def vjp(q, me, op: str, rp, ci, G, w=None, vertices=None, want_w=True):
+    """Gradient of L = sum_s G_s A_s (A the operator's CSR values on the
+    pattern rp, ci) with respect to q (d, nq) and w (nq,); only the listed
+    vertices when given.  Returns (dq, dw, dq_abs, dw_abs)."""
+    d, q, me = _mesh_arrays(q, me)
+    nq, nme = q.shape[1], me.shape[1]
+    rp = np.ascontiguousarray(rp, np.int64)
+    ci = np.ascontiguousarray(ci, np.int64)
+    G = np.ascontiguousarray(G, np.float64)
+    wv = None if w is None else np.ascontiguousarray(w, np.float64)
+    want = None
+    if vertices is not None:
+        want = np.zeros(nq, np.uint8)
+        want[np.asarray(vertices)] = 1
+    dq = np.zeros((d, nq))
+    dqa = np.zeros((d, nq))
+    dw = np.zeros(nq) if (op == "MASS_W" and want_w) else None
+    dwa = np.zeros(nq) if dw is not None else None
+    st = _load().oracle_vjp(d, nq, nme, _ptr(q), _ptr(me), OP[op], _ptr(wv), _ptr(rp), _ptr(ci),
+                            _ptr(G), _ptr(want), _ptr(dq), _ptr(dw), _ptr(dqa), _ptr(dwa))
+    if st:
+        raise OracleError(st, "vjp")
+    return dq, dw, dqa, dwa
 
 
 def grad(q, me, w, a, b, want_w: bool = True, want_q: bool = True, with_abs: bool = False):
