@@ -12,7 +12,8 @@ Prints one JSON line.  Besides the headline numbers it carries:
   cpu_baseline  the CPU oracle on a bounded prefix of the same element list
   extra         elasticity on the same mesh (constant and nodal Lame
                 parameters), the general second-order operator, the boundary
-                weighted mass of the cube's surface, symbolic-phase time, batched vs
+                weighted mass of the cube's surface, JVP / VJP of the stiffness,
+                symbolic-phase time, batched vs
                 per-mesh launches, the 2D 2048^2 workload (stiffness, weighted
                 mass, elasticity), adjoint time, the 3D P_k mass for k = 1..6
                 on about 1e6 nodes (skipped with --no-extra)
@@ -122,6 +123,24 @@ def extras(torch, femasm, mg, plan, q, stream, steps, mesh):
     out["general_3d"] = {"elements_per_s": plan.nme / t, "nnz_per_s": nnz_s / t, "ms": t * 1e3,
                          "alg_GBps": ab / t / 1e9, "frac": ab / t / 1e9 / PEAK_HBM_GBS}
     del vals, lam_f, mu_f, vals_s
+    # JVP and VJP of the stiffness assembly (upstream gradient on every entry)
+    _, nnz_s = plan.query("STIFF")
+    gen = torch.Generator(device=q.device).manual_seed(171)
+    G = torch.randn(nnz_s, dtype=torch.float64, device=q.device, generator=gen)
+    dq = torch.randn(q.shape, dtype=torch.float64, device=q.device, generator=gen)
+    slot = plan.slot_map()
+    dA = torch.empty(nnz_s, dtype=torch.float64, device=q.device)
+    gq = torch.empty_like(q)
+    fj = lambda: femasm.fem_assemble_jvp(plan.handle, 2, q.data_ptr(), None, dq.data_ptr(), None,
+                                        dA.data_ptr(), stream.cuda_stream)
+    fv = lambda: femasm.fem_assemble_vjp(plan.handle, 2, q.data_ptr(), None, G.data_ptr(),
+                                        slot.data_ptr(), gq.data_ptr(), None, stream.cuda_stream)
+    _, pj = time_launches(fj, stream, 10, 2)
+    _, pv = time_launches(fv, stream, 10, 2)
+    out["stiff_jvp_vjp_3d"] = {"jvp_ms": statistics.mean(pj), "vjp_ms": statistics.mean(pv),
+                               "jvp_elements_per_s": plan.nme / (statistics.mean(pj) / 1e3),
+                               "vjp_elements_per_s": plan.nme / (statistics.mean(pv) / 1e3)}
+    del G, dq, slot, dA, gq
     # boundary (Robin) weighted mass on the surface of the cube
     facets = torch.from_numpy(mg.boundary_facets(mesh)).to(q.device)
     bplan = femasm.BoundaryPlan(facets, plan.nq)

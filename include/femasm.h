@@ -188,6 +188,34 @@ fem_status fem_assemble_backward(fem_plan plan, uint32_t op_mask, const double *
                                  const double *w, const double *a, const double *b,
                                  double *dJdw, double *dJdq, hipStream_t stream);
 
+/*
+ * Derivatives of the assembly map (q, w) -> A for op = FEM_OP_MASS,
+ * FEM_OP_MASS_W or FEM_OP_STIFF (generalising the adjoint above to any
+ * direction and any upstream gradient).  With the gradient systems of
+ * Appendix C.1 (d g_a = -N g_a, N = sum_c g_c dq_c^T, d|K| = |K| tr N):
+ *
+ * fem_assemble_jvp: dvalues = dA, the derivative of the operator's CSR
+ *   values along (dq, dw):  dq device d*nq doubles (layout of q); dw device
+ *   nq doubles (FEM_OP_MASS_W only, else ignored); dvalues device nnz
+ *   doubles, fully overwritten, each entry summed in ascending element
+ *   number.
+ * fem_assemble_vjp: the gradient of L = sum_s G[s] A[s] (G device, nnz
+ *   doubles, any upstream gradient on the CSR entries):  dLdq device d*nq
+ *   doubles or NULL; dLdw device nq doubles or NULL (FEM_OP_MASS_W only);
+ *   each output is the sum of its element contributions in ascending element
+ *   number.  slot is the plan's triplet-to-slot map (fem_plan_slot_map,
+ *   (d+1)^2 * nme int32, device), computed once by the caller.
+ * Both asynchronous, no allocation.  Errors: FEM_ERR_ARG (other op, null
+ * arrays), FEM_ERR_OVERFLOW; degenerate elements as in
+ * fem_assemble_numeric.
+ */
+fem_status fem_assemble_jvp(fem_plan plan, int32_t op, const double *q, const double *w,
+                            const double *dq, const double *dw, double *dvalues,
+                            hipStream_t stream);
+fem_status fem_assemble_vjp(fem_plan plan, int32_t op, const double *q, const double *w,
+                            const double *G, const int32_t *slot, double *dLdq, double *dLdw,
+                            hipStream_t stream);
+
 /* J = a^T A b for CSR values of operator `op` produced with this plan:
  * out (device, 1 double).  Row partial sums are combined in row order, so
  * the result is bitwise reproducible.  Asynchronous. */

@@ -1,0 +1,365 @@
+// Derivatives of the assembly map (q, w) -> A for the mass, weighted mass
+// and stiffness operators: the directional derivative (JVP) and the
+// gradient of L = sum_s G_s A_s (VJP) for an arbitrary upstream gradient G
+// on the CSR entries.
+//
+// Per element, with g_c the barycentric gradients (g_c = c_c / det), |K| =
+// |det|/d! and a perturbation dq_c of its vertices, the gradient systems of
+// Appendix C.1 give d g_a = -N g_a with N = sum_c g_c dq_c^T, and
+// d|K| = |K| t with t = tr N = sum_c g_c . dq_c.  Hence
+//   stiffness  dE_ab = |K| [ t g_a.g_b - (N g_a).g_b - g_a.(N g_b) ]
+//   mass       dE_ab = E_ab t          (E proportional to |K|)
+//   weighted   dE_ab = E_ab t + |K| d!/(d+3)! (1+delta_ab) (dw^s + dw_a + dw_b)
+// and, for L_K = sum_ab G_ab E_ab(K) with G_ab the upstream gradient at the
+// entry (me[a,K], me[b,K]),
+//   stiffness  dL_K/dq_c = |K| [ s g_c - sum_a z_a g_a ],  s = sum_ab G_ab g_a.g_b,
+//              z = (G + G^T) y, y_a = g_a . g_c
+//   masses     dL_K/dq_c = (sum_ab G_ab E_ab) g_c
+//   weighted   dL_K/dw_c = |K| d!/(d+3)! [ sum G + tr G + (row_c + col_c of G) + 2 G_cc ].
+// JVP: one thread per CSR row adds the tangent element rows of its vertex
+// into an LDS tile of the workgroup's CSR range, in ascending element number
+// (the row-gather scheme of the numeric phase), then the tile is written
+// coalesced.  VJP: kLanes lanes per vertex, each lane summing its share of
+// the vertex's incidences, partial sums combined in a fixed order.
+#include "element.h"
+#include "femasm_impl.h"
+#include "rowgather.h"
+
+#pragma clang fp contract(off)
+
+namespace femasm {
+
+namespace {
+
+constexpr int kVjpLanes = 4;
+
+template <int D, int OP>
+__global__ void __launch_bounds__(256) k_jvp(MeshView mv, const double *__restrict__ dq,
+                                             const double *__restrict__ dw, int32_t *status) {
+    constexpr int NL = D + 1;
+    extern __shared__ double acc[];
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t r0 = tile * blockDim.x;
+    const int64_t r1 = min(r0 + int64_t(blockDim.x), mv.nq);
+    const int64_t base = mv.rp[r0];
+    const int nacc = int(mv.rp[r1] - base);
+    for (int s = threadIdx.x; s < nacc; s += blockDim.x) acc[s] = 0.0;
+    __syncthreads();
+    int bad = 0;
+    const int64_t i = r0 + threadIdx.x;
+    if (i < r1) {
+        double *__restrict__ my = acc + (mv.rp[i] - base);
+        const int64_t nq = mv.nq;
+        for (int t = mv.inc_ptr[i]; t < mv.inc_ptr[i + 1]; ++t) {
+            const uint32_t ea = mv.inc_elem[t];
+            const uint32_t off = mv.inc_off[t];
+            const int64_t e = ea & 0x3fffffffu;
+            const int al = int(ea >> 30);
+            int v[NL];
+            double P[NL][D], dP[NL][D];
+#pragma unroll
+            for (int b = 0; b < NL; ++b) {
+                v[b] = mv.pme[e * NL + b];
+#pragma unroll
+                for (int x = 0; x < D; ++x) {
+                    P[b][x] = mv.q[x * nq + v[b]];
+                    dP[b][x] = dq[x * nq + v[b]];
+                }
+            }
+            Elem<D> E;
+            elem_geometry(P, E);
+            if (E.det == 0.0) {
+                bad = 1;
+                continue;
+            }
+            const double rdet = 1.0 / E.det;
+            const double ad = fabs(E.det);
+            double g[NL][D];
+#pragma unroll
+            for (int b = 0; b < NL; ++b)
+#pragma unroll
+                for (int x = 0; x < D; ++x) g[b][x] = E.c[b][x] * rdet;
+            // N = sum_c g_c dq_c^T, t = tr N
+            double N[D][D];
+#pragma unroll
+            for (int x = 0; x < D; ++x)
+#pragma unroll
+                for (int y = 0; y < D; ++y) {
+                    double s = g[0][x] * dP[0][y];
+#pragma unroll
+                    for (int c = 1; c < NL; ++c) s = fma(g[c][x], dP[c][y], s);
+                    N[x][y] = s;
+                }
+            double tr = N[0][0];
+#pragma unroll
+            for (int x = 1; x < D; ++x) tr += N[x][x];
+            double ga[D];
+#pragma unroll
+            for (int x = 0; x < D; ++x) {
+                double cx[NL];
+#pragma unroll
+                for (int b = 0; b < NL; ++b) cx[b] = g[b][x];
+                ga[x] = sel<D>(cx, al);
+            }
+            if constexpr (OP == FEM_OP_STIFF) {
+                const double vol = ad / Fact<D>::dfact;
+                double Nga[D];
+#pragma unroll
+                for (int x = 0; x < D; ++x) Nga[x] = cdot<D>(N[x], ga);
+#pragma unroll
+                for (int b = 0; b < NL; ++b) {
+                    double Ngb[D];
+#pragma unroll
+                    for (int x = 0; x < D; ++x) Ngb[x] = cdot<D>(N[x], g[b]);
+                    const double de =
+                        vol * ((tr * cdot<D>(ga, g[b]) - cdot<D>(Nga, g[b])) - cdot<D>(ga, Ngb));
+                    const int pos = (off >> (8 * b)) & 255u;
+                    my[pos] += de;
+                }
+            } else if constexpr (OP == FEM_OP_MASS) {
+                const double k = ad / Fact<D>::mass_den;
+#pragma unroll
+                for (int b = 0; b < NL; ++b) {
+                    const int pos = (off >> (8 * b)) & 255u;
+                    my[pos] += ((b == al) ? 2.0 * k : k) * tr;
+                }
+            } else {
+                double wl[NL], dwl[NL];
+#pragma unroll
+                for (int b = 0; b < NL; ++b) {
+                    wl[b] = mv.w[v[b]];
+                    dwl[b] = dw[v[b]];
+                }
+                double ws = wl[0], dws = dwl[0];
+#pragma unroll
+                for (int b = 1; b < NL; ++b) {
+                    ws += wl[b];
+                    dws += dwl[b];
+                }
+                const double k = ad / Fact<D>::massw_den;
+                const double wa = sel<D>(wl, al), dwa = sel<D>(dwl, al);
+#pragma unroll
+                for (int b = 0; b < NL; ++b) {
+                    const double f = (b == al) ? 2.0 * k : k;
+                    const int pos = (off >> (8 * b)) & 255u;
+                    my[pos] += f * ((ws + (wa + wl[b])) * tr + (dws + (dwa + dwl[b])));
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int s = threadIdx.x; s < nacc; s += blockDim.x) mv.values[base + s] = acc[s];
+    const unsigned long long any = __ballot(bad != 0);
+    if (any != 0ull && (threadIdx.x & 63) == __ffsll((long long)any) - 1) atomicOr(status, bad);
+}
+
+template <int D, int OP>
+__global__ void __launch_bounds__(256)
+    k_vjp(MeshView mv, const int32_t *__restrict__ porig, const int32_t *__restrict__ slot,
+          const double *__restrict__ G, double *__restrict__ dLdq, double *__restrict__ dLdw,
+          int32_t *status) {
+    constexpr int NL = D + 1;
+    const int64_t gt = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t i = gt / kVjpLanes;
+    const int j = int(gt % kVjpLanes);
+    int bad = 0;
+    double gw = 0.0, gq[D];
+#pragma unroll
+    for (int x = 0; x < D; ++x) gq[x] = 0.0;
+    if (i < mv.nq) {
+        const int64_t nq = mv.nq;
+        for (int t = mv.inc_ptr[i] + j; t < mv.inc_ptr[i + 1]; t += kVjpLanes) {
+            const uint32_t ea = mv.inc_elem[t];
+            const int64_t e = ea & 0x3fffffffu;
+            const int al = int(ea >> 30);
+            const int64_t k = porig[e];
+            double Gk[NL][NL];
+#pragma unroll
+            for (int b = 0; b < NL; ++b)
+#pragma unroll
+                for (int a = 0; a < NL; ++a) Gk[a][b] = G[slot[k * NL * NL + b * NL + a]];
+            int v[NL];
+            double P[NL][D];
+#pragma unroll
+            for (int b = 0; b < NL; ++b) {
+                v[b] = mv.pme[e * NL + b];
+#pragma unroll
+                for (int x = 0; x < D; ++x) P[b][x] = mv.q[x * nq + v[b]];
+            }
+            Elem<D> E;
+            elem_geometry(P, E);
+            if (E.det == 0.0) {
+                bad = 1;
+                continue;
+            }
+            const double rdet = 1.0 / E.det;
+            const double ad = fabs(E.det);
+            double g[NL][D];
+#pragma unroll
+            for (int b = 0; b < NL; ++b)
+#pragma unroll
+                for (int x = 0; x < D; ++x) g[b][x] = E.c[b][x] * rdet;
+            double gc[D];
+#pragma unroll
+            for (int x = 0; x < D; ++x) {
+                double cx[NL];
+#pragma unroll
+                for (int b = 0; b < NL; ++b) cx[b] = g[b][x];
+                gc[x] = sel<D>(cx, al);
+            }
+            // sums of G used by the mass terms
+            double gsum = 0.0, gtr = 0.0, rowc = 0.0, colc = 0.0, gcc = 0.0;
+#pragma unroll
+            for (int a = 0; a < NL; ++a) {
+                gtr += Gk[a][a];
+#pragma unroll
+                for (int b = 0; b < NL; ++b) {
+                    gsum += Gk[a][b];
+                    if (a == al) rowc += Gk[a][b];
+                    if (b == al) colc += Gk[a][b];
+                }
+                if (a == al) gcc = Gk[a][a];
+            }
+            if constexpr (OP == FEM_OP_STIFF) {
+                const double vol = ad / Fact<D>::dfact;
+                double y[NL], s = 0.0;
+#pragma unroll
+                for (int a = 0; a < NL; ++a) y[a] = cdot<D>(g[a], gc);
+#pragma unroll
+                for (int a = 0; a < NL; ++a)
+#pragma unroll
+                    for (int b = 0; b < NL; ++b) s = fma(Gk[a][b], cdot<D>(g[a], g[b]), s);
+                double Uz[D];
+#pragma unroll
+                for (int x = 0; x < D; ++x) Uz[x] = 0.0;
+#pragma unroll
+                for (int a = 0; a < NL; ++a) {
+                    double z = 0.0;
+#pragma unroll
+                    for (int b = 0; b < NL; ++b) z = fma(Gk[a][b] + Gk[b][a], y[b], z);
+#pragma unroll
+                    for (int x = 0; x < D; ++x) Uz[x] = fma(z, g[a][x], Uz[x]);
+                }
+#pragma unroll
+                for (int x = 0; x < D; ++x) gq[x] += vol * (s * gc[x] - Uz[x]);
+            } else if constexpr (OP == FEM_OP_MASS) {
+                const double sk = ad / Fact<D>::mass_den * (gsum + gtr);
+#pragma unroll
+                for (int x = 0; x < D; ++x) gq[x] += sk * gc[x];
+            } else {
+                double wl[NL];
+#pragma unroll
+                for (int b = 0; b < NL; ++b) wl[b] = mv.w[v[b]];
+                double ws = wl[0];
+#pragma unroll
+                for (int b = 1; b < NL; ++b) ws += wl[b];
+                const double kk = ad / Fact<D>::massw_den;
+                // sum_ab G_ab (1+delta_ab)(w^s + w_a + w_b)
+                double s = 0.0;
+#pragma unroll
+                for (int a = 0; a < NL; ++a)
+#pragma unroll
+                    for (int b = 0; b < NL; ++b)
+                        s = fma(Gk[a][b] * (a == b ? 2.0 : 1.0), ws + (wl[a] + wl[b]), s);
+                const double sk = kk * s;
+#pragma unroll
+                for (int x = 0; x < D; ++x) gq[x] += sk * gc[x];
+                gw += kk * ((gsum + gtr) + (rowc + colc) + 2.0 * gcc);
+            }
+        }
+    }
+#pragma unroll
+    for (int sh = 1; sh < kVjpLanes; sh <<= 1) {
+        gw += __shfl_xor(gw, sh, kVjpLanes);
+#pragma unroll
+        for (int x = 0; x < D; ++x) gq[x] += __shfl_xor(gq[x], sh, kVjpLanes);
+    }
+    if (i < mv.nq && j == 0) {
+        if (dLdw) dLdw[i] = gw;
+        if (dLdq)
+#pragma unroll
+            for (int x = 0; x < D; ++x) dLdq[x * mv.nq + i] = gq[x];
+    }
+    const unsigned long long any = __ballot(bad != 0);
+    if (any != 0ull && (threadIdx.x & 63) == __ffsll((long long)any) - 1) atomicOr(status, bad);
+}
+
+MeshView deriv_view(const fem_plan_s *p, const double *q, const double *w, double *values) {
+    MeshView mv{};
+    mv.rp = p->rp;
+    mv.inc_ptr = p->inc_ptr;
+    mv.inc_elem = p->inc_elem;
+    mv.inc_off = p->inc_off;
+    mv.pme = p->pme;
+    mv.q = q;
+    mv.w = w;
+    mv.values = values;
+    mv.nq = p->nq;
+    return mv;
+}
+
+template <int D>
+hipError_t launch_jvp(const fem_plan_s *p, int op, const MeshView &mv, const double *dq,
+                      const double *dw, hipStream_t s) {
+    const RowLaunch &L = p->launch[1];
+    if (L.tiles == 0) return hipSuccess;
+    const dim3 grid(unsigned(L.tiles)), block(L.rows_per_wg);
+    if (op == FEM_OP_MASS)
+        hipLaunchKernelGGL((k_jvp<D, FEM_OP_MASS>), grid, block, L.lds_bytes, s, mv, dq, dw, p->status);
+    else if (op == FEM_OP_MASS_W)
+        hipLaunchKernelGGL((k_jvp<D, FEM_OP_MASS_W>), grid, block, L.lds_bytes, s, mv, dq, dw,
+                           p->status);
+    else
+        hipLaunchKernelGGL((k_jvp<D, FEM_OP_STIFF>), grid, block, L.lds_bytes, s, mv, dq, dw,
+                           p->status);
+    return hipGetLastError();
+}
+
+template <int D>
+hipError_t launch_vjp(const fem_plan_s *p, int op, const MeshView &mv, const int32_t *slot,
+                      const double *G, double *dLdq, double *dLdw, hipStream_t s) {
+    const unsigned grid = unsigned((p->nq * kVjpLanes + 255) / 256);
+    if (op == FEM_OP_MASS)
+        hipLaunchKernelGGL((k_vjp<D, FEM_OP_MASS>), dim3(grid), dim3(256), 0, s, mv, p->porig,
+                           slot, G, dLdq, dLdw, p->status);
+    else if (op == FEM_OP_MASS_W)
+        hipLaunchKernelGGL((k_vjp<D, FEM_OP_MASS_W>), dim3(grid), dim3(256), 0, s, mv, p->porig,
+                           slot, G, dLdq, dLdw, p->status);
+    else
+        hipLaunchKernelGGL((k_vjp<D, FEM_OP_STIFF>), dim3(grid), dim3(256), 0, s, mv, p->porig,
+                           slot, G, dLdq, dLdw, p->status);
+    return hipGetLastError();
+}
+
+bool deriv_op(int32_t op) { return op == FEM_OP_MASS || op == FEM_OP_MASS_W || op == FEM_OP_STIFF; }
+
+}  // namespace
+}  // namespace femasm
+
+using namespace femasm;
+
+extern "C" fem_status fem_assemble_jvp(fem_plan plan, int32_t op, const double *q, const double *w,
+                                       const double *dq, const double *dw, double *dvalues,
+                                       hipStream_t stream) {
+    if (!plan || !deriv_op(op)) return FEM_ERR_ARG;
+    if (plan->nnz == 0) return FEM_OK;
+    if (!q || !dq || !dvalues || (op == FEM_OP_MASS_W && (!w || !dw))) return FEM_ERR_ARG;
+    if (plan->launch[1].rows_per_wg == 0) return FEM_ERR_OVERFLOW;
+    const MeshView mv = deriv_view(plan, q, w, dvalues);
+    const hipError_t e = plan->d == 2 ? launch_jvp<2>(plan, op, mv, dq, dw, stream)
+                                      : launch_jvp<3>(plan, op, mv, dq, dw, stream);
+    return hip_status(e);
+}
+
+extern "C" fem_status fem_assemble_vjp(fem_plan plan, int32_t op, const double *q, const double *w,
+                                       const double *G, const int32_t *slot, double *dLdq,
+                                       double *dLdw, hipStream_t stream) {
+    if (!plan || !deriv_op(op)) return FEM_ERR_ARG;
+    if (plan->nq == 0) return FEM_OK;
+    if (!q || (plan->nnz > 0 && (!G || !slot)) || (op == FEM_OP_MASS_W && !w)) return FEM_ERR_ARG;
+    if (op != FEM_OP_MASS_W) dLdw = nullptr;
+    const MeshView mv = deriv_view(plan, q, w, nullptr);
+    const hipError_t e = plan->d == 2 ? launch_vjp<2>(plan, op, mv, slot, G, dLdq, dLdw, stream)
+                                      : launch_vjp<3>(plan, op, mv, slot, G, dLdq, dLdw, stream);
+    return hip_status(e);
+}

@@ -51,6 +51,8 @@ _SIGS = {
     "fem_assemble_numeric": ([P, I32, P, P, D, D, P, P], C.c_int),
     "fem_assemble_elasticity_nodal": ([P, P, P, P, P, P], C.c_int),
     "fem_assemble_general": ([P, P, P, P, P], C.c_int),
+    "fem_assemble_jvp": ([P, I32, P, P, P, P, P, P], C.c_int),
+    "fem_assemble_vjp": ([P, I32, P, P, P, P, P, P, P], C.c_int),
     "fem_assemble_backward": ([P, U32, P, P, P, P, P, P, P], C.c_int),
     "fem_csr_bilinear": ([P, I32, P, P, P, P, P], C.c_int),
     "fem_plan_sync_status": ([P, P], C.c_int),
@@ -165,6 +167,18 @@ def fem_assemble_general(plan: int, q: int, coef, values: int, stream=None):
     arr = (D * len(coef))(*[float(x) for x in coef])
     _check(load_library().fem_assemble_general(plan, q, arr, values, _stream(stream)),
            "fem_assemble_general")
+
+
+def fem_assemble_jvp(plan: int, op: int, q: int, w: int | None, dq: int, dw: int | None,
+                     dvalues: int, stream=None):
+    _check(load_library().fem_assemble_jvp(plan, op, q, w, dq, dw, dvalues, _stream(stream)),
+           "fem_assemble_jvp")
+
+
+def fem_assemble_vjp(plan: int, op: int, q: int, w: int | None, G: int, slot: int,
+                     dLdq: int | None, dLdw: int | None, stream=None):
+    _check(load_library().fem_assemble_vjp(plan, op, q, w, G, slot, dLdq, dLdw, _stream(stream)),
+           "fem_assemble_vjp")
 
 
 def fem_assemble_backward(plan: int, op_mask: int, q: int, w: int | None, a: int, b: int,
@@ -360,6 +374,28 @@ class Plan:
             out = torch.empty(max(nnz, 1), dtype=torch.float64, device=self.device)
         fem_assemble_general(self.handle, q.data_ptr(), list(coef), out.data_ptr(), stream)
         return out[:nnz]
+
+    def jvp(self, op, q, dq, w=None, dw=None, out=None, stream=None):
+        """Directional derivative of the operator's CSR values along (dq, dw)."""
+        _, nnz = self.query(op)
+        q, dq, w, dw = (_dev_f64(x, self.device) for x in (q, dq, w, dw))
+        if out is None:
+            out = torch.empty(max(nnz, 1), dtype=torch.float64, device=self.device)
+        fem_assemble_jvp(self.handle, _op(op), q.data_ptr(), _ptr(w), dq.data_ptr(), _ptr(dw),
+                         out.data_ptr(), stream)
+        return out[:nnz]
+
+    def vjp(self, op, q, G, w=None, slot=None, want_w=True, stream=None):
+        """Gradient of sum(G * A) with respect to q (d, nq) and, for MASS_W, w."""
+        if slot is None:
+            slot = self.slot_map(stream)
+        q, w, G = (_dev_f64(x, self.device) for x in (q, w, G))
+        gq = torch.empty(self.d, self.nq, dtype=torch.float64, device=self.device)
+        gw = (torch.empty(self.nq, dtype=torch.float64, device=self.device)
+              if (_op(op) == FEM_OP["MASS_W"] and want_w) else None)
+        fem_assemble_vjp(self.handle, _op(op), q.data_ptr(), _ptr(w), G.data_ptr(),
+                         slot.data_ptr(), gq.data_ptr(), _ptr(gw), stream)
+        return gq, gw
 
     def backward(self, q, w, a, b, op_mask=("STIFF", "MASS_W"), want_w=True, want_q=True,
                  stream=None):
