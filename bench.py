@@ -87,7 +87,18 @@ def cpu_baseline(mesh, nsample=3_000_000):
                       f"(all vertices), full oracle assembly incl. CSR emission, {dt:.1f} s"}
 
 
+def cpu_baseline_sample(fn, units, unit, what):
+    """The CPU oracle timed on a bounded sample (one core), for the extras."""
+    t0 = time.perf_counter()
+    fn()
+    dt = time.perf_counter() - t0
+    return {"value": units / dt, "unit": unit, "cores": 1, "kind": "oracle",
+            "sample": f"{what}, {dt:.1f} s"}
+
+
 def extras(torch, femasm, mg, plan, q, stream, steps, mesh):
+    import numpy as np
+    import oracle
     out = {}
     # elasticity on the same plan
     nrows, nnz_e = plan.query("ELAS")
@@ -108,9 +119,14 @@ def extras(torch, femasm, mg, plan, q, stream, steps, mesh):
     _, per = time_launches(fn, stream, max(3, steps // 4), 2)
     t = statistics.mean(per) / 1e3
     ab = algorithmic_bytes(3, plan.nq, plan.nme, nnz_e) + 2 * 8 * plan.nq
-    out["elas_nodal_3d"] = {"elements_per_s": plan.nme / t, "nnz_per_s": nnz_e / t,
-                            "ms": t * 1e3, "alg_GBps": ab / t / 1e9,
-                            "frac": ab / t / 1e9 / PEAK_HBM_GBS}
+    S = 100_000
+    lam_h, mu_h = lam_f.cpu().numpy(), mu_f.cpu().numpy()
+    out["elas_nodal_3d"] = {
+        "elements_per_s": plan.nme / t, "nnz_per_s": nnz_e / t, "ms": t * 1e3,
+        "alg_GBps": ab / t / 1e9, "frac": ab / t / 1e9 / PEAK_HBM_GBS,
+        "cpu_baseline": cpu_baseline_sample(
+            lambda: oracle.assemble_lame(mesh.q, np.ascontiguousarray(mesh.me[:, :S]), lam_h, mu_h),
+            S, "elements/s", f"first {S} elements, nodal-Lame elasticity")}
     # the general second-order operator (constant coefficients, non-symmetric)
     _, nnz_s = plan.query("STIFF")
     vals_s = torch.empty(nnz_s, dtype=torch.float64, device=q.device)
@@ -120,8 +136,14 @@ def extras(torch, femasm, mg, plan, q, stream, steps, mesh):
     _, per = time_launches(fn, stream, max(3, steps // 4), 2)
     t = statistics.mean(per) / 1e3
     ab = algorithmic_bytes(3, plan.nq, plan.nme, nnz_s)
-    out["general_3d"] = {"elements_per_s": plan.nme / t, "nnz_per_s": nnz_s / t, "ms": t * 1e3,
-                         "alg_GBps": ab / t / 1e9, "frac": ab / t / 1e9 / PEAK_HBM_GBS}
+    S = 500_000
+    out["general_3d"] = {
+        "elements_per_s": plan.nme / t, "nnz_per_s": nnz_s / t, "ms": t * 1e3,
+        "alg_GBps": ab / t / 1e9, "frac": ab / t / 1e9 / PEAK_HBM_GBS,
+        "cpu_baseline": cpu_baseline_sample(
+            lambda: oracle.assemble_general(mesh.q, np.ascontiguousarray(mesh.me[:, :S]),
+                                            np.array(coef)),
+            S, "elements/s", f"first {S} elements, general operator")}
     del vals, lam_f, mu_f, vals_s
     # JVP and VJP of the stiffness assembly (upstream gradient on every entry)
     _, nnz_s = plan.query("STIFF")
@@ -137,9 +159,24 @@ def extras(torch, femasm, mg, plan, q, stream, steps, mesh):
                                         slot.data_ptr(), gq.data_ptr(), None, stream.cuda_stream)
     _, pj = time_launches(fj, stream, 10, 2)
     _, pv = time_launches(fv, stream, 10, 2)
-    out["stiff_jvp_vjp_3d"] = {"jvp_ms": statistics.mean(pj), "vjp_ms": statistics.mean(pv),
-                               "jvp_elements_per_s": plan.nme / (statistics.mean(pj) / 1e3),
-                               "vjp_elements_per_s": plan.nme / (statistics.mean(pv) / 1e3)}
+    tj, tv = statistics.mean(pj) / 1e3, statistics.mean(pv) / 1e3
+    ab_j = 2 * 8 * 3 * plan.nq + 16 * plan.nme + 8 * nnz_s   # q, dq, me in; dA out
+    ab_v = 2 * 8 * 3 * plan.nq + 16 * plan.nme + 8 * nnz_s   # q, me, G in; dL/dq out
+    S = 200_000
+    me_s = np.ascontiguousarray(mesh.me[:, :S])
+    dq_h = dq.cpu().numpy()
+    rp_s, ci_s, _, _ = oracle.assemble(mesh.q, me_s, "STIFF")
+    G_s = np.random.default_rng(172).standard_normal(len(ci_s))
+    out["stiff_jvp_vjp_3d"] = {
+        "jvp_ms": tj * 1e3, "vjp_ms": tv * 1e3,
+        "jvp_elements_per_s": plan.nme / tj, "vjp_elements_per_s": plan.nme / tv,
+        "jvp_frac": ab_j / tj / 1e9 / PEAK_HBM_GBS, "vjp_frac": ab_v / tv / 1e9 / PEAK_HBM_GBS,
+        "cpu_baseline_jvp": cpu_baseline_sample(
+            lambda: oracle.jvp(mesh.q, me_s, "STIFF", dq_h), S, "elements/s",
+            f"first {S} elements, complex-step JVP"),
+        "cpu_baseline_vjp": cpu_baseline_sample(
+            lambda: oracle.vjp(mesh.q, me_s, "STIFF", rp_s, ci_s, G_s), S, "elements/s",
+            f"first {S} elements, complex-step VJP")}
     del G, dq, slot, dA, gq
     # boundary (Robin) weighted mass on the surface of the cube
     facets = torch.from_numpy(mg.boundary_facets(mesh)).to(q.device)
@@ -151,8 +188,15 @@ def extras(torch, femasm, mg, plan, q, stream, steps, mesh):
     _, per = time_launches(fn, stream, 20, 3)
     bplan.sync_status()
     t = statistics.mean(per) / 1e3
-    out["boundary_mass_w_3d"] = {"facets": bplan.nf, "nnz": bplan.nnz, "ms": t * 1e3,
-                                 "facets_per_s": bplan.nf / t}
+    fh = facets.cpu().numpy()
+    nvb = len(np.unique(fh))
+    ab = 8 * 3 * nvb + 8 * nvb + 4 * 3 * bplan.nf + 8 * bplan.nnz
+    wb_h = wb.cpu().numpy()
+    out["boundary_mass_w_3d"] = {
+        "facets": bplan.nf, "nnz": bplan.nnz, "ms": t * 1e3, "facets_per_s": bplan.nf / t,
+        "alg_GBps": ab / t / 1e9, "frac": ab / t / 1e9 / PEAK_HBM_GBS,
+        "cpu_baseline": cpu_baseline_sample(lambda: oracle.boundary_mass(mesh.q, fh, wb_h),
+                                            bplan.nf, "facets/s", "all surface triangles")}
     del bplan, vb, wb, facets
     # batched vs per-mesh launches (256 meshes, weighted mass + stiffness)
     cfg = mg.config_batch()
@@ -234,6 +278,11 @@ def extras(torch, femasm, mg, plan, q, stream, steps, mesh):
     for k in sorted(PK_CUBES):
         print(f"[bench] P{k} mass ...", file=sys.stderr, flush=True)
         out["pk_mass_3d"][f"P{k}"] = pk_run(torch, femasm, mg, k, stream, 10, 2)
+    m2 = mg.config_pk(2, 20)["mesh"]
+    me2 = np.ascontiguousarray(m2.me)
+    out["pk_mass_3d"]["cpu_baseline_P2"] = cpu_baseline_sample(
+        lambda: oracle.pk_mass(m2.q, me2, 2), m2.nme, "elements/s",
+        f"P2 mass of a 20^3-cube P2 mesh ({m2.nme} elements, {m2.nq} nodes)")
     return out
 
 
