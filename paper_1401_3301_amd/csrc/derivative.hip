@@ -16,11 +16,16 @@
 //              z = (G + G^T) y, y_a = g_a . g_c
 //   masses     dL_K/dq_c = (sum_ab G_ab E_ab) g_c
 //   weighted   dL_K/dw_c = |K| d!/(d+3)! [ sum G + tr G + (row_c + col_c of G) + 2 G_cc ].
-// JVP: one thread per CSR row adds the tangent element rows of its vertex
-// into an LDS tile of the workgroup's CSR range, in ascending element number
-// (the row-gather scheme of the numeric phase), then the tile is written
-// coalesced.  VJP: kLanes lanes per vertex, each lane summing its share of
+// JVP: by default on the vertex-pair kernel (pair.hip: the tangent of the
+// packed element matrix in the element phase, then the same ordered pair
+// sums); else one thread per CSR row adds the tangent element rows of its
+// vertex into an LDS tile of the workgroup's CSR range, in ascending element
+// number (the row-gather scheme of the numeric phase), then the tile is
+// written coalesced.  VJP: kLanes lanes per vertex, each lane summing its share of
 // the vertex's incidences, partial sums combined in a fixed order.
+#include <cstdlib>
+#include <cstring>
+
 #include "element.h"
 #include "femasm_impl.h"
 #include "rowgather.h"
@@ -344,6 +349,15 @@ extern "C" fem_status fem_assemble_jvp(fem_plan plan, int32_t op, const double *
     if (!plan || !deriv_op(op)) return FEM_ERR_ARG;
     if (plan->nnz == 0) return FEM_OK;
     if (!q || !dq || !dvalues || (op == FEM_OP_MASS_W && (!w || !dw))) return FEM_ERR_ARG;
+    // the vertex-pair kernel (FEMASM_KERNEL=rowgather forces the row-gather one)
+    const char *sel = getenv("FEMASM_KERNEL");
+    if (!sel || strcmp(sel, "rowgather") != 0) {
+        const int jop = op == FEM_OP_MASS ? kOpJvpMass : op == FEM_OP_MASS_W ? kOpJvpMassW
+                                                                            : kOpJvpStiff;
+        hipError_t e = hipSuccess;
+        if (launch_pair(plan, jop, q, w, 0.0, 0.0, dvalues, stream, &e, dw, nullptr, dq))
+            return hip_status(e);
+    }
     if (plan->launch[1].rows_per_wg == 0) return FEM_ERR_OVERFLOW;
     const MeshView mv = deriv_view(plan, q, w, dvalues);
     const hipError_t e = plan->d == 2 ? launch_jvp<2>(plan, op, mv, dq, dw, stream)

@@ -78,6 +78,11 @@ constexpr int kOpElasNodal = 4;
 // (fem_assemble_general); the vertex-pair kernel only.
 constexpr int kOpGeneral = 5;
 constexpr int kGeneralCoef = 16;   // A (d*d), b (d), c (d), a0, padded
+// Internal operator codes of the directional derivatives (fem_assemble_jvp)
+// of the mass, weighted mass and stiffness on the vertex-pair kernel.
+constexpr int kOpJvpMass = 6;
+constexpr int kOpJvpMassW = 7;
+constexpr int kOpJvpStiff = 8;
 
 struct fem_plan_data {
     int d = 0;
@@ -120,15 +125,17 @@ fem_status upload_pairs(PairPlan &P, int R, int slots, bool tri, int d, int64_t 
 // has no pair layout for this operator.
 // w2: the mu field of kOpElasNodal (w is then the lambda field).
 // gco: host coefficients of kOpGeneral (kGeneralCoef doubles).
+// dq: the tangent coordinates of the JVP operators (d*nq, layout of q).
 bool launch_pair(const fem_plan_data *p, int op, const double *q, const double *w, double lam,
                  double mu, double *values, hipStream_t s, hipError_t *err,
-                 const double *w2 = nullptr, const double *gco = nullptr);
+                 const double *w2 = nullptr, const double *gco = nullptr,
+                 const double *dq = nullptr);
 // Launches the pair kernel over a layout of dimension d (hipErrorNotSupported:
 // its LDS need exceeds the workgroup limit, nothing launched).
 hipError_t launch_pair_layout(const PairPlan &P, int d, int op, const double *q, const double *w,
                               double lam, double mu, double *values, int32_t *status,
                               hipStream_t s, const double *w2 = nullptr,
-                              const double *gco = nullptr);
+                              const double *gco = nullptr, const double *dq = nullptr);
 // Concatenates per-mesh pair layouts into one (block descriptors carry each
 // mesh's coordinate / weight / value offsets and vertex count).  out.ok is
 // false when some part has no layout or the slot counts differ.

@@ -57,6 +57,7 @@ struct PairView {
     const double *w;
     const double *w2;     // mu field (nodal Lame elasticity; w is the lambda field)
     double gco[kGeneralCoef];   // general operator: A (d x d, row-major), b, c, a0
+    const double *dq;     // JVP operators: tangent coordinates (layout of q); w2 is then dw
     double *values;
     int32_t nb, max_nodes;
     uint32_t off_w, off_row, off_rowof, off_ev, off_ent;
@@ -68,6 +69,7 @@ struct PairView {
 // operators: the packed upper triangle of the element matrix, entry (a, b),
 // a <= b, at a*(d+1) - a*(a-1)/2 + (b-a) (the pair entries carry that index).
 constexpr bool is_elas(int op) { return op == FEM_OP_ELAS || op == kOpElasNodal; }
+constexpr bool is_jvp(int op) { return op == kOpJvpMass || op == kOpJvpMassW || op == kOpJvpStiff; }
 
 template <int D, int OP>
 struct PairOp {
@@ -144,10 +146,75 @@ __device__ __forceinline__ int wave_task(uint64_t wp, int w) {
 
 template <int D, int OP>
 __device__ __forceinline__ void element_values(const double (&P)[D + 1][D], const double *wl,
-                                               const double *wl2, const double *gco, double *out,
+                                               const double *wl2, const double *gco,
+                                               const double (&dP)[D + 1][D], double *out,
                                                int &bad) {
     constexpr int NL = D + 1;
-    if constexpr (OP == FEM_OP_MASS || OP == FEM_OP_MASS_W) {
+    if constexpr (is_jvp(OP)) {
+        // directional derivative of the packed element matrix along dP (and
+        // dw = wl2): with g = c/det, N = sum_c g_c dP_c^T and t = tr N,
+        //   stiffness  vol [ t g_a.g_b - (N g_a).g_b - g_a.(N g_b) ]
+        //   mass       E_ab t;   weighted  E_ab t + f (dw^s + dw_a + dw_b)
+        Elem<D> E;
+        elem_geometry(P, E);
+        const bool deg = E.det == 0.0;
+        if (deg) bad = 1;
+        const double rdet = deg ? 0.0 : 1.0 / E.det;
+        const double ad = fabs(E.det);
+        double g[NL][D];
+#pragma unroll
+        for (int b = 0; b < NL; ++b)
+#pragma unroll
+            for (int x = 0; x < D; ++x) g[b][x] = E.c[b][x] * rdet;
+        double N[D][D];
+#pragma unroll
+        for (int x = 0; x < D; ++x)
+#pragma unroll
+            for (int y = 0; y < D; ++y) {
+                double s = g[0][x] * dP[0][y];
+#pragma unroll
+                for (int c = 1; c < NL; ++c) s = fma(g[c][x], dP[c][y], s);
+                N[x][y] = s;
+            }
+        double t = N[0][0];
+#pragma unroll
+        for (int x = 1; x < D; ++x) t += N[x][x];
+        if constexpr (OP == kOpJvpStiff) {
+            const double vol = ad / Fact<D>::dfact;
+            double Ng[NL][D];
+#pragma unroll
+            for (int b = 0; b < NL; ++b)
+#pragma unroll
+                for (int x = 0; x < D; ++x) Ng[b][x] = cdot<D>(N[x], g[b]);
+#pragma unroll
+            for (int a = 0; a < NL; ++a)
+#pragma unroll
+                for (int b = a; b < NL; ++b)
+                    out[tri_index<NL>(a, b)] =
+                        vol * ((t * cdot<D>(g[a], g[b]) - cdot<D>(Ng[a], g[b])) - cdot<D>(g[a], Ng[b]));
+        } else if constexpr (OP == kOpJvpMass) {
+            const double k = deg ? 0.0 : ad / Fact<D>::mass_den;
+#pragma unroll
+            for (int a = 0; a < NL; ++a)
+#pragma unroll
+                for (int b = a; b < NL; ++b) out[tri_index<NL>(a, b)] = (a == b ? 2.0 * k : k) * t;
+        } else {
+            double ws = wl[0], dws = wl2[0];
+#pragma unroll
+            for (int b = 1; b < NL; ++b) {
+                ws += wl[b];
+                dws += wl2[b];
+            }
+            const double k = deg ? 0.0 : ad / Fact<D>::massw_den;
+#pragma unroll
+            for (int a = 0; a < NL; ++a)
+#pragma unroll
+                for (int b = a; b < NL; ++b) {
+                    const double f = a == b ? 2.0 * k : k;
+                    out[tri_index<NL>(a, b)] = f * ((ws + (wl[a] + wl[b])) * t + (dws + (wl2[a] + wl2[b])));
+                }
+        }
+    } else if constexpr (OP == FEM_OP_MASS || OP == FEM_OP_MASS_W) {
         // the same operations as the row-gather kernel: (1+delta) k, and
         // f (w^s + (w_a + w_b)) with f = (1+delta) k
         const double det = elem_det(P);
@@ -255,8 +322,10 @@ __global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, doubl
     constexpr int M = O::M;
     constexpr int M2 = M * M;
     constexpr int NX = O::NX;
-    constexpr bool kW = OP == FEM_OP_MASS_W || OP == kOpElasNodal;
-    constexpr bool kW2 = OP == kOpElasNodal;
+    constexpr bool kW = OP == FEM_OP_MASS_W || OP == kOpElasNodal || OP == kOpJvpMassW;
+    constexpr bool kW2 = OP == kOpElasNodal || OP == kOpJvpMassW;
+    constexpr bool kDQ = is_jvp(OP);
+    constexpr int kDqOff = (kW ? 1 : 0) + (kW2 ? 1 : 0);   // tangents after w and w2
     extern __shared__ __align__(16) unsigned char smem[];
     double *crd = reinterpret_cast<double *>(smem);
     double *wv = reinterpret_cast<double *>(smem + pv.off_w);
@@ -286,6 +355,7 @@ __global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, doubl
     int rcntv = 0, reoffv = 0, rns = 0;   // task entry counts / offsets, lane s = slot s
     double rq[kNodeSlots][D];
     double rw[kNodeSlots], rw2[kNodeSlots];
+    double rdq[kNodeSlots][D];
     int nid[kNodeSlots];
 
     auto load_nodes = [&](const Desc &d) {
@@ -303,6 +373,9 @@ __global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, doubl
                 for (int x = 0; x < D; ++x) rq[u][x] = pv.q[d.qo + x * d.nq + nid[u]];
                 if constexpr (kW) rw[u] = pv.w[d.wo + nid[u]];
                 if constexpr (kW2) rw2[u] = pv.w2[d.wo + nid[u]];
+                if constexpr (kDQ)
+#pragma unroll
+                    for (int x = 0; x < D; ++x) rdq[u][x] = pv.dq[d.qo + x * d.nq + nid[u]];
             }
         }
     };
@@ -356,6 +429,9 @@ __global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, doubl
                 for (int x = 0; x < D; ++x) crd[x * MN + n] = rq[u][x];
                 if constexpr (kW) wv[n] = rw[u];
                 if constexpr (kW2) wv[MN + n] = rw2[u];
+                if constexpr (kDQ)
+#pragma unroll
+                    for (int x = 0; x < D; ++x) wv[kDqOff * MN + x * MN + n] = rdq[u][x];
             }
         }
         // L2: coordinates of the next block in flight
@@ -411,7 +487,7 @@ __global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, doubl
                 const uint32_t vv = el[u];
                 const int v[4] = {int(vv & 255u), int((vv >> 8) & 255u), int((vv >> 16) & 255u),
                                   int(vv >> 24)};
-                double P[NL][D];
+                double P[NL][D], dP[NL][D];
                 double wl[NL], wl2[NL];
 #pragma unroll
                 for (int a = 0; a < NL; ++a) {
@@ -419,8 +495,11 @@ __global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, doubl
                     for (int x = 0; x < D; ++x) P[a][x] = crd[x * MN + v[a]];
                     if constexpr (kW) wl[a] = wv[v[a]];
                     if constexpr (kW2) wl2[a] = wv[MN + v[a]];
+                    if constexpr (kDQ)
+#pragma unroll
+                        for (int x = 0; x < D; ++x) dP[a][x] = wv[kDqOff * MN + x * MN + v[a]];
                 }
-                element_values<D, OP>(P, wl, wl2, pv.gco, ev + e * NV, bad);
+                element_values<D, OP>(P, wl, wl2, pv.gco, dP, ev + e * NV, bad);
             } else if (e == dc.ne) {
 #pragma unroll
                 for (int t = 0; t < NV; ++t) ev[e * NV + t] = 0.0;
@@ -575,8 +654,14 @@ PairLds pair_lds(const PairPlan &P) {
     PairView pv{};
     size_t o = size_t(D) * P.max_nodes * sizeof(double);
     pv.off_w = align16(o);
-    if (OP == FEM_OP_MASS_W) o = pv.off_w + size_t(P.max_nodes) * sizeof(double);
-    if (OP == kOpElasNodal) o = pv.off_w + 2 * size_t(P.max_nodes) * sizeof(double);
+    {
+        // per-node fields after the coordinates: w, the second field, the
+        // tangent coordinates (see k_pair)
+        constexpr bool kW = OP == FEM_OP_MASS_W || OP == kOpElasNodal || OP == kOpJvpMassW;
+        constexpr bool kW2 = OP == kOpElasNodal || OP == kOpJvpMassW;
+        const int nf = (kW ? 1 : 0) + (kW2 ? 1 : 0) + (is_jvp(OP) ? D : 0);
+        o = pv.off_w + size_t(nf) * P.max_nodes * sizeof(double);
+    }
     pv.off_row = align16(o);
     o = pv.off_row + size_t(P.max_rows) * sizeof(int4);
     pv.off_rowof = align16(o);
@@ -591,8 +676,8 @@ PairLds pair_lds(const PairPlan &P) {
 
 template <int D, int OP, int S>
 hipError_t launch_pair_t(const PairPlan &P, const double *q, const double *w, const double *w2,
-                         const double *gco, double lam, double mu, double *values,
-                         int32_t *status, hipStream_t s) {
+                         const double *gco, const double *dq, double lam, double mu,
+                         double *values, int32_t *status, hipStream_t s) {
     PairLds L = pair_lds<D, OP>(P);
     if (L.bytes > 160 * 1024) return hipErrorNotSupported;   // caller falls back
     PairView pv = L.pv;
@@ -608,14 +693,15 @@ hipError_t launch_pair_t(const PairPlan &P, const double *q, const double *w, co
     pv.q = q;
     pv.w = w;
     pv.w2 = w2;
+    pv.dq = dq;
     for (int i = 0; i < kGeneralCoef; ++i) pv.gco[i] = gco ? gco[i] : 0.0;
     pv.values = values;
     pv.nb = P.nb;
     pv.max_nodes = P.max_nodes;
     const void *fn = reinterpret_cast<const void *>(&k_pair<D, OP, S>);
     // persistent grid: resident workgroups per CU x CUs, a multiple of the 8 XCDs
-    static thread_local int cached[2][6][3] = {};
-    static thread_local size_t cached_lds[2][6][3] = {};
+    static thread_local int cached[2][9][3] = {};
+    static thread_local size_t cached_lds[2][9][3] = {};
     const int si = S == 1 ? 0 : (S == 2 ? 1 : 2);
     int &occ = cached[D - 2][OP][si];
     if (occ == 0 || cached_lds[D - 2][OP][si] != L.bytes) {
@@ -641,31 +727,33 @@ hipError_t launch_pair_t(const PairPlan &P, const double *q, const double *w, co
 
 template <int D, int OP>
 hipError_t launch_pair_s(const PairPlan &P, const double *q, const double *w, const double *w2,
-                         const double *gco, double lam, double mu, double *values,
-                         int32_t *status, hipStream_t s) {
-    if (P.slots == 4) return launch_pair_t<D, OP, 4>(P, q, w, w2, gco, lam, mu, values, status, s);
-    if (P.slots == 1) return launch_pair_t<D, OP, 1>(P, q, w, w2, gco, lam, mu, values, status, s);
-    return launch_pair_t<D, OP, 2>(P, q, w, w2, gco, lam, mu, values, status, s);
+                         const double *gco, const double *dq, double lam, double mu,
+                         double *values, int32_t *status, hipStream_t s) {
+    if (P.slots == 4)
+        return launch_pair_t<D, OP, 4>(P, q, w, w2, gco, dq, lam, mu, values, status, s);
+    if (P.slots == 1)
+        return launch_pair_t<D, OP, 1>(P, q, w, w2, gco, dq, lam, mu, values, status, s);
+    return launch_pair_t<D, OP, 2>(P, q, w, w2, gco, dq, lam, mu, values, status, s);
 }
 
 template <int D>
 hipError_t launch_pair_d(const PairPlan &P, int op, const double *q, const double *w,
-                         const double *w2, const double *gco, double lam, double mu,
-                         double *values, int32_t *status, hipStream_t s) {
+                         const double *w2, const double *gco, const double *dq, double lam,
+                         double mu, double *values, int32_t *status, hipStream_t s) {
+#define FEMASM_PAIR_CASE(OPC) \
+    case OPC: return launch_pair_s<D, OPC>(P, q, w, w2, gco, dq, lam, mu, values, status, s);
     switch (op) {
-        case FEM_OP_MASS:
-            return launch_pair_s<D, FEM_OP_MASS>(P, q, w, w2, gco, lam, mu, values, status, s);
-        case FEM_OP_MASS_W:
-            return launch_pair_s<D, FEM_OP_MASS_W>(P, q, w, w2, gco, lam, mu, values, status, s);
-        case FEM_OP_STIFF:
-            return launch_pair_s<D, FEM_OP_STIFF>(P, q, w, w2, gco, lam, mu, values, status, s);
-        case kOpElasNodal:
-            return launch_pair_s<D, kOpElasNodal>(P, q, w, w2, gco, lam, mu, values, status, s);
-        case kOpGeneral:
-            return launch_pair_s<D, kOpGeneral>(P, q, w, w2, gco, lam, mu, values, status, s);
-        default:
-            return launch_pair_s<D, FEM_OP_ELAS>(P, q, w, w2, gco, lam, mu, values, status, s);
+        FEMASM_PAIR_CASE(FEM_OP_MASS)
+        FEMASM_PAIR_CASE(FEM_OP_MASS_W)
+        FEMASM_PAIR_CASE(FEM_OP_STIFF)
+        FEMASM_PAIR_CASE(kOpElasNodal)
+        FEMASM_PAIR_CASE(kOpGeneral)
+        FEMASM_PAIR_CASE(kOpJvpMass)
+        FEMASM_PAIR_CASE(kOpJvpMassW)
+        FEMASM_PAIR_CASE(kOpJvpStiff)
+        default: return launch_pair_s<D, FEM_OP_ELAS>(P, q, w, w2, gco, dq, lam, mu, values, status, s);
     }
+#undef FEMASM_PAIR_CASE
 }
 
 }  // namespace
@@ -767,19 +855,20 @@ fem_status upload_pairs(PairPlan &P, int R, int slots, bool tri, int d, int64_t 
 
 hipError_t launch_pair_layout(const PairPlan &P, int d, int op, const double *q, const double *w,
                               double lam, double mu, double *values, int32_t *status,
-                              hipStream_t s, const double *w2, const double *gco) {
-    return d == 2 ? launch_pair_d<2>(P, op, q, w, w2, gco, lam, mu, values, status, s)
-                  : launch_pair_d<3>(P, op, q, w, w2, gco, lam, mu, values, status, s);
+                              hipStream_t s, const double *w2, const double *gco,
+                              const double *dq) {
+    return d == 2 ? launch_pair_d<2>(P, op, q, w, w2, gco, dq, lam, mu, values, status, s)
+                  : launch_pair_d<3>(P, op, q, w, w2, gco, dq, lam, mu, values, status, s);
 }
 
 bool launch_pair(const fem_plan_data *p, int op, const double *q, const double *w, double lam,
                  double mu, double *values, hipStream_t s, hipError_t *err, const double *w2,
-                 const double *gco) {
+                 const double *gco, const double *dq) {
     // the (a, b)-coded layout serves elasticity and the non-symmetric operator
     const PairPlan &P = is_elas(op) || op == kOpGeneral ? p->pvec : p->pscal;
     if (!P.ok) return false;
     const hipError_t e =
-        launch_pair_layout(P, p->d, op, q, w, lam, mu, values, p->status, s, w2, gco);
+        launch_pair_layout(P, p->d, op, q, w, lam, mu, values, p->status, s, w2, gco, dq);
     if (e == hipErrorNotSupported) return false;
     *err = e;
     return true;

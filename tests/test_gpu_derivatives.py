@@ -97,3 +97,20 @@ def test_full_size_3d(op):
     oq, ow, oqa, owa = oracle.vjp(mesh.q, mesh.me, op, rp, ci, G, w=wt, vertices=verts)
     assert_parity(gq[:, verts].ravel(), oq[:, verts].ravel(), oqa[:, verts].ravel(),
                   what=f"full-size VJP {op}")
+
+
+@pytest.mark.parametrize("op", OPS)
+def test_jvp_rowgather_fallback(op, monkeypatch):
+    """The row-gather JVP (the fallback when a mesh has no vertex-pair
+    layout) against the oracle too."""
+    mesh = MESHES["cube9_perm"]()
+    rng, w, dq, dw, plan = _setup(mesh, 180)
+    wt, dwt = (w, dw) if op == "MASS_W" else (None, None)
+    monkeypatch.setenv("FEMASM_KERNEL", "rowgather")
+    v = plan.jvp(op, mesh.q, dq, wt, dwt).cpu().numpy()
+    monkeypatch.delenv("FEMASM_KERNEL")
+    vp = plan.jvp(op, mesh.q, dq, wt, dwt).cpu().numpy()
+    plan.sync_status()
+    _, _, ov, oav = oracle.jvp(mesh.q, mesh.me, op, dq, wt, dwt)
+    assert_parity(v, ov, oav, what=f"row-gather JVP {op}")
+    assert_parity(vp, ov, oav, what=f"pair JVP {op}")
