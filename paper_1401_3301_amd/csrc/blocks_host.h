@@ -1,7 +1,8 @@
 // Host construction of the vertex-block layout used by the block kernels.
 //
 // Vertices (CSR rows) are grouped into compact blocks by breadth-first
-// growth over the mesh graph, seeded at the lowest unassigned vertex.  For
+// growth over the mesh graph, seeded at the lowest unassigned vertex (within
+// contiguous id chunks grown in parallel for large meshes).  For
 // each block the plan stores
 //   - its rows (ascending vertex id) and its touched vertices: the rows first,
 //     then every other vertex of an element around a row (ascending id);
@@ -51,95 +52,133 @@ constexpr int kMaxRowLen = 32;
 inline BlockHost build_block_host(int d, int64_t nq, int64_t nme, const int32_t *me,
                                   const int32_t *rp, const int32_t *ci, const int64_t *ip,
                                   const int32_t *inc_k, int R, int nthreads,
-                                  int64_t max_pairs = 0, int max_nodes = 0) {
+                                  int64_t max_pairs = 0, int max_nodes = 0,
+                                  int64_t chunk_min = 8192) {
     BlockHost H;
     const int NL = d + 1;
     for (int64_t i = 0; i < nq; ++i)
         if (rp[i + 1] - rp[i] > kMaxRowLen) return H;
 
-    // ---- breadth-first blocks over used vertices, capped in rows and elements
-    std::vector<int32_t> blk_of(nq, -1);
-    std::vector<int32_t> queue;
-    std::vector<int32_t> estamp(nme, -1);   // block that last counted the element
-    std::vector<int32_t> nstamp(max_nodes > 0 ? nq : 0, -1);   // ... the touched vertex
-    queue.reserve(R);
+    // ---- breadth-first blocks over used vertices, capped in rows and elements.
+    // The vertex ids are cut into contiguous chunks grown independently (one
+    // thread each, with its own stamps; growth never leaves a chunk), and the
+    // chunks' blocks are concatenated in chunk order, so the layout does not
+    // depend on thread timing.
+    // (at most 8 chunks: the blocks cut at chunk borders cost a little list
+    // traffic in the numeric phase)
+    const int nchunk = int(std::max<int64_t>(
+        1, std::min<int64_t>(std::min(nthreads, 8), nq / std::max<int64_t>(1, chunk_min))));
+    std::vector<int32_t> blk_of(nq, -1);   // chunk-local block of each taken vertex
+    std::vector<std::vector<int32_t>> crow(nchunk), cptr(nchunk);
+    std::vector<int> cfail(nchunk, 0);
+    auto grow = [&](int c) {
+        const int64_t v0 = nq * c / nchunk, v1 = nq * (c + 1) / nchunk;
+        std::vector<int32_t> queue;
+        std::vector<int32_t> estamp(nme, -1);   // block that last counted the element
+        std::vector<int32_t> nstamp(max_nodes > 0 ? nq : 0, -1);   // ... the touched vertex
+        std::vector<int32_t> &rows = crow[c], &rptr = cptr[c];
+        queue.reserve(R);
+        rptr.push_back(0);
+        int nbc = 0;
+        auto new_elems = [&](int32_t v, int b) {
+            int n = 0;
+            for (int64_t t = ip[v]; t < ip[v + 1]; ++t) n += estamp[inc_k[t]] != b;
+            return n;
+        };
+        // touched vertices the elements of v would add (only when capped)
+        auto new_nodes = [&](int32_t v, int b) {
+            const int32_t prov = -2 - b;   // provisional mark, undone below
+            int n = 0;
+            for (int64_t t = ip[v]; t < ip[v + 1]; ++t) {
+                const int32_t k = inc_k[t];
+                if (estamp[k] == b) continue;
+                for (int a = 0; a < d + 1; ++a) {
+                    const int32_t u = me[int64_t(a) * nme + k];
+                    if (nstamp[u] != b && nstamp[u] != prov) {
+                        nstamp[u] = prov;
+                        ++n;
+                    }
+                }
+            }
+            for (int64_t t = ip[v]; t < ip[v + 1]; ++t) {
+                const int32_t k = inc_k[t];
+                if (estamp[k] == b) continue;
+                for (int a = 0; a < d + 1; ++a) {
+                    const int32_t u = me[int64_t(a) * nme + k];
+                    if (nstamp[u] == prov) nstamp[u] = -1;
+                }
+            }
+            return n;
+        };
+        auto take = [&](int32_t v, int b) {
+            blk_of[v] = b;
+            for (int64_t t = ip[v]; t < ip[v + 1]; ++t) {
+                const int32_t k = inc_k[t];
+                if (max_nodes > 0 && estamp[k] != b)
+                    for (int a = 0; a < d + 1; ++a) nstamp[me[int64_t(a) * nme + k]] = b;
+                estamp[k] = b;
+            }
+        };
+        for (int64_t seed = v0; seed < v1; ++seed) {
+            if (blk_of[seed] != -1 || rp[seed + 1] == rp[seed]) continue;
+            const int b = nbc;
+            if (ip[seed + 1] - ip[seed] > kMaxBlockElems) {
+                cfail[c] = 1;
+                return;
+            }
+            queue.clear();
+            queue.push_back(int32_t(seed));
+            int nel = new_elems(int32_t(seed), b);
+            int64_t npairs = rp[seed + 1] - rp[seed];
+            int nnodes = max_nodes > 0 ? new_nodes(int32_t(seed), b) : 0;
+            if (max_nodes > 0 && nnodes > max_nodes) {
+                cfail[c] = 1;
+                return;
+            }
+            take(int32_t(seed), b);
+            size_t head = 0;
+            bool full = false;
+            while (head < queue.size() && int(queue.size()) < R && !full) {
+                const int32_t v = queue[head++];
+                for (int32_t s = rp[v]; s < rp[v + 1] && int(queue.size()) < R; ++s) {
+                    const int32_t j = ci[s];
+                    if (j < v0 || j >= v1 || blk_of[j] != -1 || rp[j + 1] == rp[j]) continue;
+                    const int add = new_elems(j, b);
+                    const int64_t addp = rp[j + 1] - rp[j];
+                    const int addn = max_nodes > 0 ? new_nodes(j, b) : 0;
+                    if (nel + add > kMaxBlockElems || (max_pairs > 0 && npairs + addp > max_pairs) ||
+                        (max_nodes > 0 && nnodes + addn > max_nodes)) {
+                        full = true;
+                        break;
+                    }
+                    nel += add;
+                    npairs += addp;
+                    nnodes += addn;
+                    take(j, b);
+                    queue.push_back(j);
+                }
+            }
+            std::sort(queue.begin(), queue.end());
+            rows.insert(rows.end(), queue.begin(), queue.end());
+            rptr.push_back(int32_t(rows.size()));
+            nbc += 1;
+        }
+    };
+    if (nchunk == 1) {
+        grow(0);
+    } else {
+        std::vector<std::thread> th;
+        for (int c = 0; c < nchunk; ++c) th.emplace_back(grow, c);
+        for (auto &x : th) x.join();
+    }
     H.row_ptr.push_back(0);
-    auto new_elems = [&](int32_t v, int b) {
-        int n = 0;
-        for (int64_t t = ip[v]; t < ip[v + 1]; ++t) n += estamp[inc_k[t]] != b;
-        return n;
-    };
-    // touched vertices the elements of v would add (only when capped)
-    auto new_nodes = [&](int32_t v, int b) {
-        const int32_t prov = -2 - b;   // provisional mark, undone below
-        int n = 0;
-        for (int64_t t = ip[v]; t < ip[v + 1]; ++t) {
-            const int32_t k = inc_k[t];
-            if (estamp[k] == b) continue;
-            for (int a = 0; a < d + 1; ++a) {
-                const int32_t u = me[int64_t(a) * nme + k];
-                if (nstamp[u] != b && nstamp[u] != prov) {
-                    nstamp[u] = prov;
-                    ++n;
-                }
-            }
+    for (int c = 0; c < nchunk; ++c) {
+        if (cfail[c]) return BlockHost();
+        for (size_t b = 1; b < cptr[c].size(); ++b) {
+            H.rows.insert(H.rows.end(), crow[c].begin() + cptr[c][b - 1], crow[c].begin() + cptr[c][b]);
+            H.row_ptr.push_back(int32_t(H.rows.size()));
+            H.nb += 1;
         }
-        for (int64_t t = ip[v]; t < ip[v + 1]; ++t) {
-            const int32_t k = inc_k[t];
-            if (estamp[k] == b) continue;
-            for (int a = 0; a < d + 1; ++a) {
-                const int32_t u = me[int64_t(a) * nme + k];
-                if (nstamp[u] == prov) nstamp[u] = -1;
-            }
-        }
-        return n;
-    };
-    auto take = [&](int32_t v, int b) {
-        blk_of[v] = b;
-        for (int64_t t = ip[v]; t < ip[v + 1]; ++t) {
-            const int32_t k = inc_k[t];
-            if (max_nodes > 0 && estamp[k] != b)
-                for (int a = 0; a < d + 1; ++a) nstamp[me[int64_t(a) * nme + k]] = b;
-            estamp[k] = b;
-        }
-    };
-    for (int64_t seed = 0; seed < nq; ++seed) {
-        if (blk_of[seed] != -1 || rp[seed + 1] == rp[seed]) continue;
-        const int b = H.nb;
-        if (ip[seed + 1] - ip[seed] > kMaxBlockElems) return H;
-        queue.clear();
-        queue.push_back(int32_t(seed));
-        int nel = new_elems(int32_t(seed), b);
-        int64_t npairs = rp[seed + 1] - rp[seed];
-        int nnodes = max_nodes > 0 ? new_nodes(int32_t(seed), b) : 0;
-        if (max_nodes > 0 && nnodes > max_nodes) return H;
-        take(int32_t(seed), b);
-        size_t head = 0;
-        bool full = false;
-        while (head < queue.size() && int(queue.size()) < R && !full) {
-            const int32_t v = queue[head++];
-            for (int32_t s = rp[v]; s < rp[v + 1] && int(queue.size()) < R; ++s) {
-                const int32_t j = ci[s];
-                if (blk_of[j] != -1 || rp[j + 1] == rp[j]) continue;
-                const int add = new_elems(j, b);
-                const int64_t addp = rp[j + 1] - rp[j];
-                const int addn = max_nodes > 0 ? new_nodes(j, b) : 0;
-                if (nel + add > kMaxBlockElems || (max_pairs > 0 && npairs + addp > max_pairs) ||
-                    (max_nodes > 0 && nnodes + addn > max_nodes)) {
-                    full = true;
-                    break;
-                }
-                nel += add;
-                npairs += addp;
-                nnodes += addn;
-                take(j, b);
-                queue.push_back(j);
-            }
-        }
-        std::sort(queue.begin(), queue.end());
-        H.rows.insert(H.rows.end(), queue.begin(), queue.end());
-        H.row_ptr.push_back(int32_t(H.rows.size()));
-        H.nb += 1;
     }
     const int nb = H.nb;
 

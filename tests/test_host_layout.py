@@ -52,12 +52,13 @@ def _pattern(mesh):
     return me, rp, ci, ip, inc_k
 
 
-def _build(shim, mesh, R, max_pairs=0, max_nodes=0, waves=8, slots=2, tri=False, dedup=True):
+def _build(shim, mesh, R, max_pairs=0, max_nodes=0, waves=8, slots=2, tri=False, dedup=True,
+           chunk_min=8192):
     me, rp, ci, ip, inc_k = _pattern(mesh)
     sizes = np.zeros(8, np.int64)
     st = shim.hl_build(mesh.d, ctypes.c_int64(mesh.nq), ctypes.c_int64(mesh.nme), _p(me), _p(rp),
                        _p(ci), _p(ip), _p(inc_k), R, ctypes.c_int64(max_pairs), max_nodes, waves,
-                       slots, int(tri), int(dedup), _p(sizes))
+                       slots, int(tri), int(dedup), ctypes.c_int64(chunk_min), _p(sizes))
     assert st == 0, f"builder refused the mesh (status {st})"
     nb, nrows, nnodes, nelem, nrec, ntask, nent, _ = (int(x) for x in sizes)
     B = dict(rows=np.zeros(nrows, np.int32), row_ptr=np.zeros(nb + 1, np.int32),
@@ -165,8 +166,10 @@ def _check(mesh, built, R, max_pairs, max_nodes, waves, slots, tri, dedup):
 
 
 CASES = [
-    # (mesh, R, max_pairs, max_nodes, waves, slots, tri, dedup)
+    # (mesh, R, max_pairs, max_nodes, waves, slots, tri, dedup[, chunk_min])
     ("square12", 16, 0, 0, 8, 2, False, True),
+    ("square12", 16, 512, 64, 8, 2, True, True, 40),      # four id chunks grown in parallel
+    ("cube5_perm", 56, 1024, 256, 8, 2, True, True, 50),
     ("square12", 40, 512, 60, 4, 4, True, True),
     ("cube5_perm", 56, 1024, 256, 8, 2, True, True),
     ("cube5_perm", 20, 512, 0, 8, 1, False, False),
@@ -182,11 +185,13 @@ MESHES = {
 
 @pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}-R{c[1]}-p{c[2]}-n{c[3]}-w{c[4]}s{c[5]}"
                                               f"-{'tri' if c[6] else 'ab'}-{'dd' if c[7] else 'nodd'}"
+                                              f"{'-chunks' if len(c) > 8 else ''}"
                                               for c in CASES])
 def test_layout_against_brute_force(shim, case):
-    name, R, max_pairs, max_nodes, waves, slots, tri, dedup = case
+    name, R, max_pairs, max_nodes, waves, slots, tri, dedup = case[:8]
+    chunk_min = case[8] if len(case) > 8 else 8192
     mesh = MESHES[name]()
-    built = _build(shim, mesh, R, max_pairs, max_nodes, waves, slots, tri, dedup)
+    built = _build(shim, mesh, R, max_pairs, max_nodes, waves, slots, tri, dedup, chunk_min)
     _check(mesh, built, R, max_pairs, max_nodes, waves, slots, tri, dedup)
 
 
@@ -206,5 +211,6 @@ def test_unused_vertices_and_refusals(shim):
     me, rp, ci, ip, inc_k = _pattern(mg.Mesh(2, qf, mef))
     sizes = np.zeros(8, np.int64)
     st = shim.hl_build(2, ctypes.c_int64(n + 1), ctypes.c_int64(n), _p(me), _p(rp), _p(ci),
-                       _p(ip), _p(inc_k), 16, ctypes.c_int64(0), 0, 8, 2, 0, 1, _p(sizes))
+                       _p(ip), _p(inc_k), 16, ctypes.c_int64(0), 0, 8, 2, 0, 1, ctypes.c_int64(8192),
+                       _p(sizes))
     assert st == 1
