@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <string>
+#include <thread>
 
 #include "blocks_host.h"
 #include "element.h"
@@ -327,13 +328,6 @@ fem_status upload_blocks(fem_plan_data *p, int d, int64_t nq, int64_t nme, const
     // per block when set, else 64
     int R = 64;
     if (const char *env = getenv("FEMASM_BLOCK_ROWS")) R = std::max(16, std::min(kMaxWG, atoi(env)));
-    {
-        BlockHost H = build_block_host(d, nq, nme, me, rp, ci, ip, inc_k, R, 16);
-        if (H.ok && H.nb > 0) {
-            fem_status st = upload_layout(p->blk, H, rp, true);
-            if (st != FEM_OK) return st;
-        }
-    }
     // pair layouts: FEMASM_PAIR_ROWS / FEMASM_ELAS_ROWS rows per block when
     // set (16..128), else 56 (scalar operators) and 48 in 3D / 64 in 2D
     // (elasticity); FEMASM_PAIR_SLOTS / FEMASM_ELAS_SLOTS (1, 2 or 4) tasks
@@ -348,8 +342,24 @@ fem_status upload_blocks(fem_plan_data *p, int d, int64_t nq, int64_t nme, const
     const int Ss = slots_of(env_int("FEMASM_PAIR_SLOTS", 2, 1, 4));
     const int Re = env_int("FEMASM_ELAS_ROWS", d == 3 ? 48 : 64, 16, 128);
     const int Se = slots_of(env_int("FEMASM_ELAS_SLOTS", 2, 1, 4));
-    fem_status st = upload_pairs(p->pscal, Rs, Ss, true, d, nq, nme, me, rp, ci, ip, inc_k);
-    if (st == FEM_OK) st = upload_pairs(p->pvec, Re, Se, false, d, nq, nme, me, rp, ci, ip, inc_k);
+    // the three layouts are independent: built concurrently, each thread on
+    // the plan's device
+    fem_status sb = FEM_OK, ss = FEM_OK, sv = FEM_OK;
+    const int dev = p->device;
+    std::thread tb([&] {
+        (void)hipSetDevice(dev);
+        BlockHost H = build_block_host(d, nq, nme, me, rp, ci, ip, inc_k, R, 16);
+        if (H.ok && H.nb > 0) sb = upload_layout(p->blk, H, rp, true);
+    });
+    std::thread ts([&] {
+        (void)hipSetDevice(dev);
+        ss = upload_pairs(p->pscal, Rs, Ss, true, d, nq, nme, me, rp, ci, ip, inc_k);
+    });
+    (void)hipSetDevice(dev);
+    sv = upload_pairs(p->pvec, Re, Se, false, d, nq, nme, me, rp, ci, ip, inc_k);
+    tb.join();
+    ts.join();
+    fem_status st = sb != FEM_OK ? sb : (ss != FEM_OK ? ss : sv);
     if (st != FEM_OK) {
         free_blocks(&p->blk);
         free_pairs(&p->pscal);

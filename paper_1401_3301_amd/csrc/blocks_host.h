@@ -16,7 +16,7 @@
 //     each from bit 12).  Records are interleaved across the rows of the
 //     block (record t of row r at t*nrows + r) and padded with ~0u.
 // Blocks grow until they hold R rows or the next vertex would bring the
-// element count above kMaxBlockElems (or, when max_pairs > 0, the number of
+// element count above max_elems (at most kMaxBlockElems; or, when max_pairs > 0, the number of
 // CSR entries of the block's rows above max_pairs; when max_nodes > 0, the
 // number of touched vertices above max_nodes).  A mesh with a row longer than 32
 // entries, or a vertex whose own star exceeds the element cap, does not fit
@@ -53,7 +53,8 @@ inline BlockHost build_block_host(int d, int64_t nq, int64_t nme, const int32_t 
                                   const int32_t *rp, const int32_t *ci, const int64_t *ip,
                                   const int32_t *inc_k, int R, int nthreads,
                                   int64_t max_pairs = 0, int max_nodes = 0,
-                                  int64_t chunk_min = 8192) {
+                                  int64_t chunk_min = 8192, int max_elems = kMaxBlockElems) {
+    const int ecap = std::min(max_elems, kMaxBlockElems);   // growth stops above it
     BlockHost H;
     const int NL = d + 1;
     for (int64_t i = 0; i < nq; ++i)
@@ -146,7 +147,7 @@ inline BlockHost build_block_host(int d, int64_t nq, int64_t nme, const int32_t 
                     const int add = new_elems(j, b);
                     const int64_t addp = rp[j + 1] - rp[j];
                     const int addn = max_nodes > 0 ? new_nodes(j, b) : 0;
-                    if (nel + add > kMaxBlockElems || (max_pairs > 0 && npairs + addp > max_pairs) ||
+                    if (nel + add > ecap || (max_pairs > 0 && npairs + addp > max_pairs) ||
                         (max_nodes > 0 && nnodes + addn > max_nodes)) {
                         full = true;
                         break;

@@ -774,8 +774,15 @@ fem_status upload_pairs(PairPlan &P, int R, int slots, bool tri, int d, int64_t 
     if (const char *e = getenv("FEMASM_PAIR_DEDUP")) dedup = atoi(e) != 0;
     P = PairPlan();
     const int64_t max_pairs = int64_t(64) * kPairWaves * slots;
+    // Element cap of a 3D block: the kernel keeps every block element's values
+    // in LDS (11 doubles per element for the scalar operators, 13 for
+    // elasticity) and its LDS size follows the largest block, so 700 / 600
+    // elements keep it within the 80 KB that two workgroups per compute unit
+    // allow (blocks grown against a chunk border would otherwise grow flat and
+    // large).
+    const int ecap = d == 3 ? (tri ? 700 : 600) : kMaxBlockElems;
     BlockHost H = build_block_host(d, nq, nme, me, rp, ci, ip, inc_k, std::min(R, 128), 16,
-                                   max_pairs, kMaxPairNodes);
+                                   max_pairs, kMaxPairNodes, 8192, ecap);
     if (!H.ok || H.nb == 0) return FEM_OK;   // row-gather kernel only
     PairHost PH = build_pair_host(H, d, rp, ci, kPairWaves, slots, 16, tri, dedup);
     if (!PH.ok || PH.max_ent > int64_t(kEntSlots) * kPairWG * 8 ||
