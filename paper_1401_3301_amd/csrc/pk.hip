@@ -97,7 +97,7 @@ __global__ __launch_bounds__(256) void k_pk_vol(const int32_t *__restrict__ gme,
 // thread adds the products of its entries (contiguous, ascending element) in
 // order.  The first chunk and the entry offsets of the next tile are loaded
 // into registers while the current tile is summed.
-constexpr int kPkMaxChunk = 3072;
+constexpr int kPkMaxChunk = 2048;
 constexpr int kPkRegs = kPkMaxChunk / kPkThreads;
 
 // Boundary facets ((D-1)-simplices in R^D): the packed element matrix of
