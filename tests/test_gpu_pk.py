@@ -36,7 +36,7 @@ def _run(m, k):
 
 
 SMALL = [(2, 1, 22), (2, 2, 12), (2, 3, 8), (2, 4, 6), (2, 5, 5), (2, 6, 4),
-         (3, 1, 7), (3, 2, 4), (3, 3, 3), (3, 4, 2), (3, 5, 2), (3, 6, 1)]
+         (3, 1, 7), (3, 2, 4), (3, 3, 3), (3, 4, 2), (3, 5, 2), (3, 6, 1), (3, 6, 2)]
 
 
 @pytest.mark.parametrize("d,k,n", SMALL, ids=[f"d{d}-P{k}-n{n}" for d, k, n in SMALL])
