@@ -1,0 +1,75 @@
+"""GPU checks of the fallback routes: a vertex with more than 32 neighbours
+has no vertex-pair layout, so the scalar operators, elasticity and the JVP
+run on the record-block / row-gather kernels (still against the oracle),
+while the pair-only operators report FEM_ERR_OVERFLOW; a row beyond 255
+entries is refused by the symbolic phase."""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import assert_parity
+from paper_1401_3301_amd import meshgen as mg
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1401_3301_amd import femasm  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def _fan(n, seed=0):
+    """n triangles around vertex 0 of a jittered disk, plus a ring of outer
+    triangles so that every row but 0 stays short."""
+    rng = np.random.default_rng(seed)
+    ang = np.linspace(0, 2 * np.pi, n, endpoint=False) + rng.uniform(-0.01, 0.01, n)
+    r2 = 2.0
+    q = np.hstack([[[0.0], [0.0]], np.vstack([np.cos(ang), np.sin(ang)]),
+                   r2 * np.vstack([np.cos(ang + np.pi / n), np.sin(ang + np.pi / n)])])
+    inner = [[0, 1 + i, 1 + (i + 1) % n] for i in range(n)]
+    outer = []
+    for i in range(n):
+        a, b, c = 1 + i, 1 + (i + 1) % n, 1 + n + i
+        outer += [[a, c, b]]
+    me = np.ascontiguousarray(np.array(inner + outer, np.int32).T)
+    return mg.Mesh(2, np.ascontiguousarray(q), me)
+
+
+def test_long_row_uses_fallback_kernels():
+    mesh = _fan(40)
+    me = torch.from_numpy(mesh.me).to(DEV)
+    q = torch.from_numpy(mesh.q).to(DEV)
+    w = mg.lognormal_field(mesh.nq, 3)
+    plan = femasm.Plan(me, mesh.nq)
+    assert plan.max_row == 41
+    for op in ("MASS", "MASS_W", "STIFF", "ELAS"):
+        wt = w if op == "MASS_W" else None
+        v = plan.numeric(op, q, wt).cpu().numpy()
+        plan.sync_status()
+        _, _, ov, oav = oracle.assemble(mesh.q, mesh.me, op, w=wt)
+        assert_parity(v, ov, oav, what=f"fan40 {op}")
+    # pair-only operators refuse the mesh
+    with pytest.raises(femasm.FemError) as e:
+        plan.elasticity_nodal(q, np.ones(mesh.nq), np.ones(mesh.nq))
+    assert e.value.name == "FEM_ERR_OVERFLOW"
+    with pytest.raises(femasm.FemError) as e:
+        plan.general(q, oracle.general_coef(2, np.eye(2)))
+    assert e.value.name == "FEM_ERR_OVERFLOW"
+    # the JVP falls back to the row-gather kernel
+    dq = np.random.default_rng(4).standard_normal(mesh.q.shape) * 0.01
+    v = plan.jvp("STIFF", q, dq).cpu().numpy()
+    _, _, ov, oav = oracle.jvp(mesh.q, mesh.me, "STIFF", dq)
+    assert_parity(v, ov, oav, what="fan40 JVP")
+
+
+def test_row_beyond_255_entries_is_refused():
+    mesh = _fan(300)
+    with pytest.raises(femasm.FemError) as e:
+        femasm.Plan(torch.from_numpy(mesh.me).to(DEV), mesh.nq)
+    assert e.value.name == "FEM_ERR_OVERFLOW"
+    # the oracle has no such limit
+    rp, ci, v, av = oracle.assemble(mesh.q, mesh.me, "STIFF")
+    assert rp[1] - rp[0] == 301
