@@ -416,6 +416,9 @@ def main():
                      "kernel": kernel, "kernel_ms": kern_ms,
                      "algorithmic_bytes": ab},
         "symbolic_s": t_sym,
+        # symbolic + one numeric assembly: the paper's full assembly builds the
+        # pattern every time (its timings include `sparse`)
+        "full_assembly_elements_per_s": mesh.nme / (t_sym + ms_per_step / 1e3),
     }
     if not args.no_cpu and args.op == "STIFF":
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
