@@ -329,6 +329,19 @@ struct PairHost {
 
 constexpr uint16_t kPairPad = 0xffffu;
 
+// The task starts of wavefronts 1..waves of one block, relative to the
+// block's first task (wt[0]), packed kWaveStartBits bits each, wavefront 1 in
+// the low bits.  A block holds at most waves * slots <= 8 * 4 = 32 tasks, so
+// a start is at most 32 and fits the 6-bit field.
+constexpr int kWaveStartBits = 6;
+
+inline uint64_t pack_wave_starts(const int32_t *wt, int waves) {
+    uint64_t wp = 0;
+    for (int w = 1; w <= waves; ++w)
+        wp |= uint64_t(uint32_t(wt[w] - wt[0])) << (kWaveStartBits * (w - 1));
+    return wp;
+}
+
 inline PairHost build_pair_host(const BlockHost &H, int d, const int32_t *rp, const int32_t *ci,
                                 int kWaves, int kSlots, int nthreads, bool tri = false,
                                 bool dedup = false) {

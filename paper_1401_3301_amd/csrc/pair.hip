@@ -42,6 +42,8 @@ constexpr int kNodeSlots = 512 / kPairWG;       // touched vertices per thread
 constexpr int kMaxPairNodes = 256;              // touched vertices per block: 8-bit local ids
 constexpr int kElemSlots = 1024 / kPairWG;      // elements per thread: <= 1023 (+ dummy)
 static_assert(kEntSlots == 2 && kNodeSlots == 1 && kElemSlots == 2, "512-thread workgroups");
+static_assert(kPairWaves * 4 < (1 << kWaveStartBits) && kPairWaves * kWaveStartBits <= 64,
+              "task starts of up to 4 tasks per wavefront fit the descriptor");
 
 struct PairView {
     const int32_t *desc;
@@ -94,7 +96,7 @@ __device__ __forceinline__ constexpr int tri_index(int a, int b) {
 // [2] first touched vertex, [3] touched vertices, [4] first element,
 // [5] elements, [6] CSR entries of the rows, [7] first task, [8] entry
 // count / 8, [9],[12] task starts of wavefronts 1..8 relative to the first
-// task (5 bits each, low word first), [10..11] first entry, and the block's
+// task (6 bits each, low word first), [10..11] first entry, and the block's
 // mesh within the coordinate, weight and value arrays (several meshes share
 // one launch in the batched assembly): [14..15] coordinate offset, [16..17]
 // weight offset, [18..19] value offset, [20..21] its vertex count n_q; 64-bit
@@ -141,7 +143,7 @@ __device__ __forceinline__ Desc desc_from(int dv) {
 
 // First task of wavefront w (0..kPairWaves) of a block, relative to its t0.
 __device__ __forceinline__ int wave_task(uint64_t wp, int w) {
-    return w == 0 ? 0 : int((wp >> (5 * (w - 1))) & 31u);
+    return w == 0 ? 0 : int((wp >> (kWaveStartBits * (w - 1))) & ((1u << kWaveStartBits) - 1u));
 }
 
 template <int D, int OP>
@@ -816,9 +818,7 @@ fem_status upload_pairs(PairPlan &P, int R, int slots, bool tri, int d, int64_t 
         x[5] = H.elem_ptr[b + 1] - H.elem_ptr[b];
         x[6] = o;
         x[7] = t0;
-        uint64_t wp = 0;
-        for (int w = 1; w <= kPairWaves; ++w)
-            wp |= uint64_t(PH.wt[size_t(b) * (kPairWaves + 1) + w] - t0) << (5 * (w - 1));
+        const uint64_t wp = pack_wave_starts(&PH.wt[size_t(b) * (kPairWaves + 1)], kPairWaves);
         x[8] = int32_t((PH.ent_ptr[b + 1] - PH.ent_ptr[b]) / 8);
         x[9] = int32_t(uint32_t(wp & 0xffffffffu));
         x[12] = int32_t(uint32_t(wp >> 32));

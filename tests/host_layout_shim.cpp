@@ -62,3 +62,7 @@ extern "C" void hl_pairs(int32_t *wt, int32_t *task_cnt, int64_t *task_ent, uint
     put(ent, g_p.ent);
     put(ent_ptr, g_p.ent_ptr);
 }
+
+extern "C" uint64_t hl_pack_wave_starts(const int32_t *wt, int waves) {
+    return pack_wave_starts(wt, waves);
+}

@@ -214,3 +214,32 @@ def test_unused_vertices_and_refusals(shim):
                        _p(ip), _p(inc_k), 16, ctypes.c_int64(0), 0, 8, 2, 0, 1, ctypes.c_int64(8192),
                        _p(sizes))
     assert st == 1
+
+
+def _unpack_wave_starts(wp, waves):
+    return [0] + [(wp >> (6 * (w - 1))) & 63 for w in range(1, waves + 1)]
+
+
+def test_wave_start_packing(shim):
+    # the descriptor's wavefront task starts: a full block of 8 wavefronts x
+    # 4 tasks ends at task 32, which must survive the packing, as must every
+    # monotone start sequence within that bound and any first task
+    shim.hl_pack_wave_starts.restype = ctypes.c_uint64
+    rng = np.random.default_rng(11)
+    seqs = [np.arange(0, 33, 4), np.zeros(9, int), np.full(9, 7)]
+    for _ in range(200):
+        inc = rng.integers(0, 5, 8)
+        seqs.append(np.concatenate([[0], np.cumsum(inc)]))
+    for s in seqs:
+        t0 = int(rng.integers(0, 1 << 20))
+        wt = np.ascontiguousarray(np.asarray(s) + t0, np.int32)
+        wp = shim.hl_pack_wave_starts(_p(wt), 8)
+        assert _unpack_wave_starts(wp, 8) == list(np.asarray(s) - s[0]), s
+        assert wp < (1 << 48)
+    # the starts of a layout the builder made, with 4 tasks per wavefront
+    mesh = MESHES["cube5_perm"]()
+    built = _build(shim, mesh, 64, 2048, 256, 8, 4, True, True)
+    wt = built[3]["wt"].reshape(-1, 9)
+    for row in wt:
+        wp = shim.hl_pack_wave_starts(_p(np.ascontiguousarray(row)), 8)
+        assert _unpack_wave_starts(wp, 8) == list(row - row[0])
