@@ -181,8 +181,11 @@ fem_status fem_assemble_general(fem_plan plan, const double *q, const double *co
  *   q, w, a, b  device; w is read when MASS_W is in the mask; a, b have nq doubles
  *   dJdw     device nq doubles or NULL
  *   dJdq     device d*nq doubles (laid out like q) or NULL
- * Each output entry is the sum of its element contributions in ascending
- * element number (bitwise reproducible).  Asynchronous, no allocation.
+ * Each output entry is the sum of its element contributions in a fixed
+ * order: four partial sums, partial j over the vertex's incident elements
+ * j, j+4, j+8, ... in ascending element number, combined as
+ * ((p0 + p1) + (p2 + p3)); bitwise reproducible from run to run.
+ * Asynchronous, no allocation.
  */
 fem_status fem_assemble_backward(fem_plan plan, uint32_t op_mask, const double *q,
                                  const double *w, const double *a, const double *b,
@@ -202,8 +205,10 @@ fem_status fem_assemble_backward(fem_plan plan, uint32_t op_mask, const double *
  * fem_assemble_vjp: the gradient of L = sum_s G[s] A[s] (G device, nnz
  *   doubles, any upstream gradient on the CSR entries):  dLdq device d*nq
  *   doubles or NULL; dLdw device nq doubles or NULL (FEM_OP_MASS_W only);
- *   each output is the sum of its element contributions in ascending element
- *   number.  slot is the plan's triplet-to-slot map (fem_plan_slot_map,
+ *   each output is the sum of its element contributions in a fixed order
+ *   (eight partial sums, partial j over the vertex's incident elements j,
+ *   j+8, ... in ascending element number, combined pairwise in a fixed
+ *   tree), so bitwise reproducible.  slot is the plan's triplet-to-slot map (fem_plan_slot_map,
  *   (d+1)^2 * nme int32, device), computed once by the caller.
  * Both asynchronous, no allocation.  Errors: FEM_ERR_ARG (other op, null
  * arrays), FEM_ERR_OVERFLOW; degenerate elements as in
