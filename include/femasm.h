@@ -223,7 +223,9 @@ fem_status fem_assemble_vjp(fem_plan plan, int32_t op, const double *q, const do
 
 /* J = a^T A b for CSR values of operator `op` produced with this plan:
  * out (device, 1 double).  Row partial sums are combined in row order, so
- * the result is bitwise reproducible.  Asynchronous. */
+ * the result is bitwise reproducible.  Asynchronous.  The partial sums live
+ * in a plan-owned work array: concurrent calls with one plan on different
+ * streams race on it. */
 fem_status fem_csr_bilinear(fem_plan plan, int32_t op, const double *values, const double *a,
                             const double *b, double *out, hipStream_t stream);
 
@@ -378,7 +380,8 @@ fem_status fem_boundary_symbolic(int32_t d, int64_t nq, int64_t nf, const int32_
  * matrices into a plan-owned work array, then the entry sums); no host
  * synchronisation, no allocation.  A facet of zero measure sets the plan's
  * status word.  FEM_ERR_ARG for a plan not made by fem_boundary_symbolic
- * (and fem_pk_mass refuses boundary plans). */
+ * (and fem_pk_mass refuses boundary plans).  Concurrent calls with one plan
+ * race on its work array. */
 fem_status fem_boundary_mass(fem_pk_plan plan, const double *q, const double *w, double *values,
                              hipStream_t stream);
 
