@@ -346,23 +346,24 @@ fem_status upload_blocks(fem_plan_data *p, int d, int64_t nq, int64_t nme, const
     const int Ss = slots_of(env_int("FEMASM_PAIR_SLOTS", 2, 1, 4));
     const int Re = env_int("FEMASM_ELAS_ROWS", d == 3 ? 48 : 128, 16, 128);
     const int Se = slots_of(env_int("FEMASM_ELAS_SLOTS", 2, 1, 4));
-    // the three layouts are independent: built concurrently, each thread on
-    // the plan's device
+    // the two pair layouts are independent: built concurrently, each thread
+    // on the plan's device.  The record-block layout serves the scalar
+    // operators only when the scalar pair layout cannot be built (or when
+    // FEMASM_BLOCK_LAYOUT=1 asks for it, for comparisons of the kernel
+    // families), so it is built only then.
     fem_status sb = FEM_OK, ss = FEM_OK, sv = FEM_OK;
     const int dev = p->device;
-    std::thread tb([&] {
-        (void)hipSetDevice(dev);
-        BlockHost H = build_block_host(d, nq, nme, me, rp, ci, ip, inc_k, R, 16);
-        if (H.ok && H.nb > 0) sb = upload_layout(p->blk, H, rp, true);
-    });
     std::thread ts([&] {
         (void)hipSetDevice(dev);
         ss = upload_pairs(p->pscal, Rs, Ss, true, d, nq, nme, me, rp, ci, ip, inc_k);
     });
     (void)hipSetDevice(dev);
     sv = upload_pairs(p->pvec, Re, Se, false, d, nq, nme, me, rp, ci, ip, inc_k);
-    tb.join();
     ts.join();
+    if (ss == FEM_OK && (!p->pscal.ok || env_int("FEMASM_BLOCK_LAYOUT", 0, 0, 1) == 1)) {
+        BlockHost H = build_block_host(d, nq, nme, me, rp, ci, ip, inc_k, R, 16);
+        if (H.ok && H.nb > 0) sb = upload_layout(p->blk, H, rp, true);
+    }
     fem_status st = sb != FEM_OK ? sb : (ss != FEM_OK ? ss : sv);
     if (st != FEM_OK) {
         free_blocks(&p->blk);

@@ -15,6 +15,7 @@
 #include <thread>
 
 #include "femasm_impl.h"
+#include "symbolic_host.h"
 
 namespace femasm {
 
@@ -157,23 +158,19 @@ extern "C" fem_status fem_assemble_symbolic(int32_t d, int64_t nq, int64_t nme, 
     if (bad) return FEM_ERR_INDEX;
 
     // ---- incidences: vertex -> (element, local vertex), ascending element
-    std::vector<int64_t> ip(nq + 1, 0);
-    for (int64_t k = 0; k < nme; ++k)
-        for (int a = 0; a < NL; ++a) ip[hme[size_t(a) * nme + k] + 1] += 1;
-    for (int64_t i = 0; i < nq; ++i) ip[i + 1] += ip[i];
-    const int64_t ninc = ip[nq];
+    // (element slots k*(d+1)+a sorted stably by their vertex)
+    const int64_t ninc = int64_t(NL) * nme;
+    std::vector<int64_t> ip;
     std::vector<int32_t> inc_k(ninc);
     std::vector<uint8_t> inc_a(ninc);
-    {
-        std::vector<int64_t> fill(ip.begin(), ip.end() - 1);
-        for (int64_t k = 0; k < nme; ++k)
-            for (int a = 0; a < NL; ++a) {
-                int32_t v = hme[size_t(a) * nme + k];
-                int64_t pos = fill[v]++;
-                inc_k[pos] = int32_t(k);
-                inc_a[pos] = uint8_t(a);
-            }
-    }
+    stable_key_sort(
+        ninc, nq, worker_count(),
+        [&](int64_t r) { return int64_t(hme[size_t(r % NL) * nme + r / NL]); },
+        [&](int64_t pos, int64_t r) {
+            inc_k[pos] = int32_t(r / NL);
+            inc_a[pos] = uint8_t(r % NL);
+        },
+        ip);
 
     // ---- pattern: row i = sorted unique vertices of the elements around i
     std::vector<int32_t> rowlen(nq, 0);
@@ -230,20 +227,19 @@ extern "C" fem_status fem_assemble_symbolic(int32_t d, int64_t nq, int64_t nme, 
     // stable in caller element number)
     std::vector<int32_t> porig(nme), pinv(nme);
     {
-        std::vector<int64_t> cnt(nq + 1, 0);
-        std::vector<int32_t> key(nme);
-        for (int64_t k = 0; k < nme; ++k) {
-            int32_t m0 = hme[k];
-            for (int a = 1; a < NL; ++a) m0 = std::min(m0, hme[size_t(a) * nme + k]);
-            key[k] = m0;
-            cnt[m0 + 1] += 1;
-        }
-        for (int64_t i = 0; i < nq; ++i) cnt[i + 1] += cnt[i];
-        for (int64_t k = 0; k < nme; ++k) {
-            int64_t p = cnt[key[k]]++;
-            porig[p] = int32_t(k);
-            pinv[k] = int32_t(p);
-        }
+        std::vector<int64_t> kptr;
+        stable_key_sort(
+            nme, nq, worker_count(),
+            [&](int64_t k) {
+                int32_t m0 = hme[size_t(k)];
+                for (int a = 1; a < NL; ++a) m0 = std::min(m0, hme[size_t(a) * nme + k]);
+                return int64_t(m0);
+            },
+            [&](int64_t p, int64_t k) {
+                porig[p] = int32_t(k);
+                pinv[k] = int32_t(p);
+            },
+            kptr);
     }
     std::vector<int32_t> pme(size_t(NL) * nme);
     parallel_ranges(nme, [&](int64_t b, int64_t e) {

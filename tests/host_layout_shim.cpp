@@ -66,3 +66,14 @@ extern "C" void hl_pairs(int32_t *wt, int32_t *task_cnt, int64_t *task_ent, uint
 extern "C" uint64_t hl_pack_wave_starts(const int32_t *wt, int waves) {
     return pack_wave_starts(wt, waves);
 }
+
+#include "../paper_1401_3301_amd/csrc/symbolic_host.h"
+
+extern "C" void hl_key_sort(int64_t n, int64_t nkeys, const int64_t *keys, int nthreads,
+                            int64_t *order, int64_t *ptr) {
+    std::vector<int64_t> p;
+    stable_key_sort(
+        n, nkeys, nthreads, [&](int64_t r) { return keys[r]; },
+        [&](int64_t pos, int64_t r) { order[pos] = r; }, p);
+    std::memcpy(ptr, p.data(), sizeof(int64_t) * p.size());
+}

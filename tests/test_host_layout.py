@@ -243,3 +243,37 @@ def test_wave_start_packing(shim):
     for row in wt:
         wp = shim.hl_pack_wave_starts(_p(np.ascontiguousarray(row)), 8)
         assert _unpack_wave_starts(wp, 8) == list(row - row[0])
+
+
+@pytest.mark.parametrize("n,nkeys,threads", [(0, 5, 4), (7, 1, 4), (1000, 37, 1), (200_000, 50, 8),
+                                             (300_000, 2_000_000, 8), (150_000, 150_001, 3)])
+def test_stable_key_sort(shim, n, nkeys, threads):
+    # the symbolic phase's parallel counting sort against a stable argsort
+    rng = np.random.default_rng(n + nkeys)
+    keys = np.ascontiguousarray(rng.integers(0, nkeys, n), np.int64)
+    if n > 10:
+        keys[: n // 10] = nkeys - 1          # a heavy key and an empty key range
+    order = np.zeros(n, np.int64)
+    ptr = np.zeros(nkeys + 1, np.int64)
+    shim.hl_key_sort(ctypes.c_int64(n), ctypes.c_int64(nkeys), _p(keys), threads, _p(order),
+                     _p(ptr))
+    assert np.array_equal(order, np.argsort(keys, kind="stable"))
+    ref = np.zeros(nkeys + 1, np.int64)
+    ref[1:] = np.cumsum(np.bincount(keys, minlength=nkeys))
+    assert np.array_equal(ptr, ref)
+
+
+def test_incidence_order_of_a_mesh(shim):
+    # element slots k*(d+1)+a keyed by their vertex: each vertex's incidences
+    # in ascending element number, the order the numeric phase sums in
+    mesh = mg.kuhn_cube(6, 0.1, seed=3, perm_seed=4)
+    nl = mesh.d + 1
+    keys = np.ascontiguousarray(mesh.me.T.ravel(), np.int64)    # r = k*nl + a
+    order = np.zeros(len(keys), np.int64)
+    ptr = np.zeros(mesh.nq + 1, np.int64)
+    shim.hl_key_sort(ctypes.c_int64(len(keys)), ctypes.c_int64(mesh.nq), _p(keys), 8, _p(order),
+                     _p(ptr))
+    for v in range(0, mesh.nq, 7):
+        ks = order[ptr[v]:ptr[v + 1]] // nl
+        assert np.all(np.diff(ks) > 0)
+        assert set(ks.tolist()) == set(np.nonzero((mesh.me == v).any(axis=0))[0].tolist())

@@ -1,6 +1,7 @@
-"""The library's host-side plan builders (blocks_host.h, pk_host.h) under
-ThreadSanitizer (the parallel block growth over vertex-id chunks and the
-per-block list builders) and AddressSanitizer + UBSan, on the CPU.  The
+"""The library's host-side plan builders (blocks_host.h, pk_host.h,
+symbolic_host.h) under ThreadSanitizer (the parallel block growth over
+vertex-id chunks, the per-block list builders and the parallel key sort)
+and AddressSanitizer + UBSan, on the CPU.  The
 shims are compiled with g++ for the host only; each sanitized build runs a
 small driver over meshes that exercise several chunks."""
 import os
@@ -20,6 +21,7 @@ DRIVER = textwrap.dedent(r"""
     #include <algorithm>
     #include "blocks_host.h"
     #include "pk_host.h"
+    #include "symbolic_host.h"
     using namespace femasm;
     // Kuhn cube of n^3 cubes: connectivity, CSR pattern and incidences
     static void kuhn(int n, std::vector<int32_t> &me, int64_t &nq, int64_t &nme) {
@@ -65,6 +67,26 @@ DRIVER = textwrap.dedent(r"""
             PairHost P = build_pair_host(H, 3, rp.data(), ci.data(), 8, 2, 8, true, true);
             if (!H.ok || !P.ok) bad = 1;
             std::printf("blocks %d (chunk_min %d) tasks %zu\n", H.nb, chunk_min, P.task_cnt.size());
+        }
+        // the parallel stable key sort: incidences as the symbolic phase
+        // builds them (against the serial ones above), then a large random
+        // key set over several threads and buckets
+        {
+            std::vector<int64_t> ptr;
+            std::vector<int32_t> inc2(4 * nme);
+            stable_key_sort(4 * nme, nq, 8, [&](int64_t r) { return int64_t(me[(r % 4) * nme + r / 4]); },
+                            [&](int64_t pos, int64_t r) { inc2[pos] = int32_t(r / 4); }, ptr);
+            if (inc2 != inc || ptr != ip) bad = 1;
+            const int64_t n = 400000, nk = 1500000;
+            std::vector<int64_t> keys(n), order(n, -1);
+            uint64_t x = 88172645463325252ull;
+            for (auto &k : keys) { x ^= x << 13; x ^= x >> 7; x ^= x << 17; k = int64_t(x % nk); }
+            stable_key_sort(n, nk, 8, [&](int64_t r) { return keys[r]; },
+                            [&](int64_t pos, int64_t r) { order[pos] = r; }, ptr);
+            for (int64_t i = 1; i < n; ++i)
+                if (keys[order[i - 1]] > keys[order[i]] ||
+                    (keys[order[i - 1]] == keys[order[i]] && order[i - 1] > order[i])) { bad = 1; break; }
+            std::printf("key sort ok %d\n", bad == 0);
         }
         // P_k plan on the same connectivity read as P1 (k = 1)
         PkHost K = build_pk_host(3, 1, nq, nme, me.data(), 8);
