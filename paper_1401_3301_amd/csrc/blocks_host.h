@@ -196,6 +196,12 @@ inline BlockHost build_block_host(int d, int64_t nq, int64_t nme, const int32_t 
     auto work = [&](int b0, int b1) {
         std::vector<int32_t> loc(nq, -1);
         std::vector<int32_t> elems, halo;
+        // per block: element id -> position (open addressing, stamped by
+        // block so nothing is cleared); per row: local vertex -> column position
+        constexpr int kHash = 2048;   // > 2 * kMaxBlockElems
+        std::vector<int32_t> hkey(kHash), hval(kHash), hgen(kHash, -1);
+        std::vector<uint8_t> colpos;
+        auto hslot = [](int32_t k) { return int((uint32_t(k) * 2654435761u) >> 21); };
         for (int b = b0; b < b1; ++b) {
             Blk &B = blks[b];
             const int32_t *rw = H.rows.data() + H.row_ptr[b];
@@ -237,20 +243,33 @@ inline BlockHost build_block_host(int d, int64_t nq, int64_t nme, const int32_t 
                     maxdeg = std::max<int>(maxdeg, int(ip[rw[r] + 1] - ip[rw[r]]));
                 B.maxdeg = maxdeg;
                 B.rec.assign(size_t(maxdeg) * nr, kRecPad);
+                for (size_t e = 0; e < elems.size(); ++e) {
+                    int h = hslot(elems[e]);
+                    while (hgen[h] == b) h = (h + 1) & (kHash - 1);
+                    hgen[h] = b;
+                    hkey[h] = elems[e];
+                    hval[h] = int32_t(e);
+                }
+                colpos.resize(B.nodes.size());
                 for (int r = 0; r < nr; ++r) {
                     const int32_t row = rw[r];
                     const int32_t *c0 = ci + rp[row], *c1 = ci + rp[row + 1];
                     B.nacc += c1 - c0;
+                    // every column of a block row is a touched vertex of the block
+                    for (const int32_t *c = c0; c < c1; ++c) colpos[loc[*c]] = uint8_t(c - c0);
                     int t = 0;
                     for (int64_t s = ip[row]; s < ip[row + 1]; ++s, ++t) {
                         const int32_t k = inc_k[s];
-                        const uint32_t epos =
-                            uint32_t(std::lower_bound(elems.begin(), elems.end(), k) - elems.begin());
-                        uint32_t recv = epos;
+                        int h = hslot(k);
+                        while (hgen[h] == b && hkey[h] != k) h = (h + 1) & (kHash - 1);
+                        if (hgen[h] != b) {   // cannot happen: k is a block element
+                            B.ok = false;
+                            break;
+                        }
+                        uint32_t recv = uint32_t(hval[h]);
                         for (int a = 0; a < NL; ++a) {
                             const int32_t v = me[int64_t(a) * nme + k];
-                            const uint32_t pos = uint32_t(std::lower_bound(c0, c1, v) - c0);
-                            recv |= pos << (12 + 5 * a);
+                            recv |= uint32_t(colpos[loc[v]]) << (12 + 5 * a);
                             if (v == row) recv |= uint32_t(a) << 10;
                         }
                         B.rec[size_t(t) * nr + r] = recv;

@@ -172,26 +172,51 @@ extern "C" fem_status fem_assemble_symbolic(int32_t d, int64_t nq, int64_t nme, 
         },
         ip);
 
-    // ---- pattern: row i = sorted unique vertices of the elements around i
+    // ---- pattern: row i = sorted unique vertices of the elements around i,
+    // and for every incidence the positions of its element's vertices in the
+    // row.  One sort per row: each thread keeps the columns of its contiguous
+    // row range until the row offsets are known, then copies them into place.
     std::vector<int32_t> rowlen(nq, 0);
+    std::vector<uint32_t> ioff(ninc);
     std::atomic<int> too_long{0};
-    auto row_cols = [&](int64_t i, std::vector<int32_t> &buf) {
-        buf.clear();
-        for (int64_t t = ip[i]; t < ip[i + 1]; ++t) {
-            int64_t k = inc_k[t];
-            for (int b = 0; b < NL; ++b) buf.push_back(hme[size_t(b) * nme + k]);
-        }
-        std::sort(buf.begin(), buf.end());
-        buf.erase(std::unique(buf.begin(), buf.end()), buf.end());
-    };
-    parallel_ranges(nq, [&](int64_t b, int64_t e) {
-        std::vector<int32_t> buf;
-        for (int64_t i = b; i < e; ++i) {
-            row_cols(i, buf);
-            rowlen[i] = int32_t(buf.size());
-            if (buf.size() > 255) too_long = 1;
-        }
-    });
+    const int nrt = nq < 4096 ? 1 : worker_count();
+    const int64_t rchunk = (nq + nrt - 1) / nrt;
+    std::vector<std::vector<int32_t>> tcols(nrt);
+    {
+        auto rows_of = [&](int t) {
+            std::vector<int32_t> buf;
+            std::vector<int32_t> &out = tcols[t];
+            for (int64_t i = t * rchunk, e = std::min(nq, (t + 1) * rchunk); i < e; ++i) {
+                buf.clear();
+                for (int64_t s = ip[i]; s < ip[i + 1]; ++s) {
+                    const int64_t k = inc_k[s];
+                    for (int b = 0; b < NL; ++b) buf.push_back(hme[size_t(b) * nme + k]);
+                }
+                std::sort(buf.begin(), buf.end());
+                buf.erase(std::unique(buf.begin(), buf.end()), buf.end());
+                rowlen[i] = int32_t(buf.size());
+                if (buf.size() > 255) {
+                    too_long = 1;
+                    return;
+                }
+                out.insert(out.end(), buf.begin(), buf.end());
+                for (int64_t s = ip[i]; s < ip[i + 1]; ++s) {
+                    const int64_t k = inc_k[s];
+                    uint32_t packed = 0;
+                    for (int b = 0; b < NL; ++b) {
+                        const int32_t v = hme[size_t(b) * nme + k];
+                        packed |= uint32_t(std::lower_bound(buf.begin(), buf.end(), v) - buf.begin())
+                                  << (8 * b);
+                    }
+                    ioff[s] = packed;
+                }
+            }
+        };
+        std::vector<std::thread> th;
+        for (int t = 1; t < nrt; ++t) th.emplace_back(rows_of, t);
+        rows_of(0);
+        for (auto &x : th) x.join();
+    }
     if (too_long) return FEM_ERR_OVERFLOW;
     std::vector<int32_t> rp(nq + 1, 0);
     int64_t nnz = 0;
@@ -204,24 +229,18 @@ extern "C" fem_status fem_assemble_symbolic(int32_t d, int64_t nq, int64_t nme, 
     }
     rp[nq] = int32_t(nnz);
     std::vector<int32_t> ci(nnz);
-    std::vector<uint32_t> ioff(ninc);
-    parallel_ranges(nq, [&](int64_t b, int64_t e) {
-        std::vector<int32_t> buf;
-        for (int64_t i = b; i < e; ++i) {
-            row_cols(i, buf);
-            std::copy(buf.begin(), buf.end(), ci.begin() + rp[i]);
-            for (int64_t t = ip[i]; t < ip[i + 1]; ++t) {
-                int64_t k = inc_k[t];
-                uint32_t packed = 0;
-                for (int b2 = 0; b2 < NL; ++b2) {
-                    int32_t v = hme[size_t(b2) * nme + k];
-                    uint32_t pos = uint32_t(std::lower_bound(buf.begin(), buf.end(), v) - buf.begin());
-                    packed |= pos << (8 * b2);
-                }
-                ioff[t] = packed;
-            }
+    {
+        std::vector<std::thread> th;
+        for (int t = 0; t < nrt; ++t) {
+            const int64_t r0 = std::min(nq, t * rchunk);
+            if (tcols[t].empty()) continue;
+            th.emplace_back([&, t, r0] {
+                std::copy(tcols[t].begin(), tcols[t].end(), ci.begin() + rp[r0]);
+                std::vector<int32_t>().swap(tcols[t]);
+            });
         }
-    });
+        for (auto &x : th) x.join();
+    }
 
     // ---- locality order of elements: by smallest vertex id (counting sort,
     // stable in caller element number)
