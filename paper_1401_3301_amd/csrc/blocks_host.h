@@ -290,23 +290,45 @@ inline BlockHost build_block_host(int d, int64_t nq, int64_t nme, const int32_t 
         }
         for (auto &x : th) x.join();
     }
-    H.node_ptr.push_back(0);
-    H.elem_ptr.push_back(0);
-    H.rec_ptr.push_back(0);
+    // offsets of every block's lists, then the lists copied into place in
+    // parallel (block order, so the result does not depend on the threads)
+    H.node_ptr.assign(size_t(nb) + 1, 0);
+    H.elem_ptr.assign(size_t(nb) + 1, 0);
+    H.rec_ptr.assign(size_t(nb) + 1, 0);
+    H.maxdeg.resize(nb);
     for (int b = 0; b < nb; ++b) {
         const Blk &B = blks[b];
         if (!B.ok) return BlockHost();
-        H.nodes.insert(H.nodes.end(), B.nodes.begin(), B.nodes.end());
-        H.elem.insert(H.elem.end(), B.elem.begin(), B.elem.end());
-        H.rec.insert(H.rec.end(), B.rec.begin(), B.rec.end());
-        H.node_ptr.push_back(int32_t(H.nodes.size()));
-        H.elem_ptr.push_back(int32_t(H.elem.size() / 4));
-        H.rec_ptr.push_back(int64_t(H.rec.size()));
-        H.maxdeg.push_back(B.maxdeg);
+        H.node_ptr[b + 1] = H.node_ptr[b] + int32_t(B.nodes.size());
+        H.elem_ptr[b + 1] = H.elem_ptr[b] + int32_t(B.elem.size() / 4);
+        H.rec_ptr[b + 1] = H.rec_ptr[b] + int64_t(B.rec.size());
+        H.maxdeg[b] = B.maxdeg;
         H.max_rows = std::max(H.max_rows, H.row_ptr[b + 1] - H.row_ptr[b]);
         H.max_nodes = std::max(H.max_nodes, int(B.nodes.size()));
         H.max_elems = std::max(H.max_elems, int(B.elem.size() / 4));
         H.max_nacc = std::max(H.max_nacc, B.nacc);
+    }
+    H.nodes.resize(size_t(H.node_ptr[nb]));
+    H.elem.resize(size_t(H.elem_ptr[nb]) * 4);
+    H.rec.resize(size_t(H.rec_ptr[nb]));
+    {
+        const int nt = std::max(1, std::min(nthreads, nb / 64 + 1));
+        std::vector<std::thread> th;
+        const int chunk = (nb + nt - 1) / nt;
+        for (int t = 0; t < nt; ++t) {
+            const int b0 = t * chunk, b1 = std::min(nb, b0 + chunk);
+            if (b0 >= b1) break;
+            th.emplace_back([&, b0, b1] {
+                for (int b = b0; b < b1; ++b) {
+                    Blk &B = blks[b];
+                    std::copy(B.nodes.begin(), B.nodes.end(), H.nodes.begin() + H.node_ptr[b]);
+                    std::copy(B.elem.begin(), B.elem.end(), H.elem.begin() + size_t(H.elem_ptr[b]) * 4);
+                    std::copy(B.rec.begin(), B.rec.end(), H.rec.begin() + H.rec_ptr[b]);
+                    B = Blk();
+                }
+            });
+        }
+        for (auto &x : th) x.join();
     }
     H.total_elems = H.elem_ptr.back();
     H.ok = true;
@@ -495,22 +517,50 @@ inline PairHost build_pair_host(const BlockHost &H, int d, const int32_t *rp, co
         }
         for (auto &x : th) x.join();
     }
-    P.ent_ptr.push_back(0);
+    // task and entry offsets of every block, then the lists copied into
+    // place in parallel (block order)
+    std::vector<int64_t> tptr(size_t(nb) + 1, 0);
+    P.ent_ptr.assign(size_t(nb) + 1, 0);
     for (int b = 0; b < nb; ++b) {
         const Blk &B = blks[b];
         if (!B.ok) return PairHost();
-        const int32_t t0 = int32_t(P.task_cnt.size());
-        const int64_t e0 = int64_t(P.ent.size());
-        for (int w = 0; w <= kWaves; ++w) P.wt.push_back(t0 + B.wfirst[w]);
-        for (size_t t = 0; t < B.cnt.size(); ++t) {
-            P.task_cnt.push_back(B.cnt[t]);
-            P.task_ent.push_back(e0 + B.eoff[t]);
-        }
-        P.hdr.insert(P.hdr.end(), B.hdr.begin(), B.hdr.end());
-        P.hdr2.insert(P.hdr2.end(), B.hdr2.begin(), B.hdr2.end());
-        P.ent.insert(P.ent.end(), B.ent.begin(), B.ent.end());
-        P.ent_ptr.push_back(int64_t(P.ent.size()));
+        tptr[b + 1] = tptr[b] + int64_t(B.cnt.size());
+        P.ent_ptr[b + 1] = P.ent_ptr[b] + int64_t(B.ent.size());
         P.max_ent = std::max<int64_t>(P.max_ent, int64_t(B.ent.size()));
+    }
+    if (tptr[nb] >= (int64_t(1) << 31)) return PairHost();
+    P.wt.resize(size_t(nb) * (kWaves + 1));
+    P.task_cnt.resize(size_t(tptr[nb]));
+    P.task_ent.resize(size_t(tptr[nb]));
+    P.hdr.resize(size_t(tptr[nb]) * 64);
+    P.hdr2.resize(size_t(tptr[nb]) * 64);
+    P.ent.resize(size_t(P.ent_ptr[nb]));
+    {
+        const int nt = std::max(1, std::min(nthreads, nb / 64 + 1));
+        std::vector<std::thread> th;
+        const int chunk = (nb + nt - 1) / nt;
+        for (int t = 0; t < nt; ++t) {
+            const int b0 = t * chunk, b1 = std::min(nb, b0 + chunk);
+            if (b0 >= b1) break;
+            th.emplace_back([&, b0, b1] {
+                for (int b = b0; b < b1; ++b) {
+                    Blk &B = blks[b];
+                    const int32_t t0 = int32_t(tptr[b]);
+                    const int64_t e0 = P.ent_ptr[b];
+                    for (int w = 0; w <= kWaves; ++w)
+                        P.wt[size_t(b) * (kWaves + 1) + w] = t0 + B.wfirst[w];
+                    for (size_t t = 0; t < B.cnt.size(); ++t) {
+                        P.task_cnt[size_t(t0) + t] = B.cnt[t];
+                        P.task_ent[size_t(t0) + t] = e0 + B.eoff[t];
+                    }
+                    std::copy(B.hdr.begin(), B.hdr.end(), P.hdr.begin() + size_t(t0) * 64);
+                    std::copy(B.hdr2.begin(), B.hdr2.end(), P.hdr2.begin() + size_t(t0) * 64);
+                    std::copy(B.ent.begin(), B.ent.end(), P.ent.begin() + e0);
+                    B = Blk();
+                }
+            });
+        }
+        for (auto &x : th) x.join();
     }
     P.ok = true;
     return P;
