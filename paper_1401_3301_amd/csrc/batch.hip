@@ -193,7 +193,7 @@ static fem_status build_items(fem_batch_s *B) {
     return FEM_OK;
 }
 
-extern "C" fem_status fem_batch_create(int32_t nmesh, const int32_t *d, const int64_t *nq,
+static fem_status fem_batch_create_impl(int32_t nmesh, const int32_t *d, const int64_t *nq,
                                        const int64_t *nme, const int32_t *const *me,
                                        hipStream_t stream, fem_batch *out) {
     if (!out || nmesh < 1 || !d || !nq || !nme || !me) return FEM_ERR_ARG;
@@ -254,6 +254,18 @@ extern "C" fem_status fem_batch_create(int32_t nmesh, const int32_t *d, const in
     }
     *out = B.release();
     return FEM_OK;
+}
+
+extern "C" fem_status fem_batch_create(int32_t nmesh, const int32_t *d, const int64_t *nq,
+                                       const int64_t *nme, const int32_t *const *me,
+                                       hipStream_t stream, fem_batch *out) {
+    // host allocations (or threads) can fail for very large batches: report
+    // it, never throw across the ABI
+    try {
+        return fem_batch_create_impl(nmesh, d, nq, nme, me, stream, out);
+    } catch (...) {
+        return FEM_ERR_NOMEM;
+    }
 }
 
 extern "C" fem_status fem_batch_set_kernel(fem_batch batch, int32_t kernel) {

@@ -357,7 +357,7 @@ fem_status pk_sum(fem_pk_plan plan, double *values, hipStream_t stream) {
 
 }  // namespace
 
-extern "C" fem_status fem_pk_symbolic(int32_t d, int32_t k, int64_t nq, int64_t nme,
+static fem_status fem_pk_symbolic_impl(int32_t d, int32_t k, int64_t nq, int64_t nme,
                                       const int32_t *me, hipStream_t stream, fem_pk_plan *out) {
     if (!out || (d != 2 && d != 3) || k < 1 || k > kPkMaxK || nq < 0 || nme < 0 ||
         (nme > 0 && !me))
@@ -365,11 +365,34 @@ extern "C" fem_status fem_pk_symbolic(int32_t d, int32_t k, int64_t nq, int64_t 
     return pk_build(d, d, k, false, nq, nme, me, stream, out);
 }
 
-extern "C" fem_status fem_boundary_symbolic(int32_t d, int64_t nq, int64_t nf,
+extern "C" fem_status fem_pk_symbolic(int32_t d, int32_t k, int64_t nq, int64_t nme,
+                                      const int32_t *me, hipStream_t stream, fem_pk_plan *out) {
+    // host allocations (or threads) can fail for very large meshes: report
+    // it, never throw across the ABI
+    try {
+        return fem_pk_symbolic_impl(d, k, nq, nme, me, stream, out);
+    } catch (...) {
+        return FEM_ERR_NOMEM;
+    }
+}
+
+static fem_status fem_boundary_symbolic_impl(int32_t d, int64_t nq, int64_t nf,
                                             const int32_t *facets, hipStream_t stream,
                                             fem_pk_plan *out) {
     if (!out || (d != 2 && d != 3) || nq < 0 || nf < 0 || (nf > 0 && !facets)) return FEM_ERR_ARG;
     return pk_build(d - 1, d, 1, true, nq, nf, facets, stream, out);
+}
+
+extern "C" fem_status fem_boundary_symbolic(int32_t d, int64_t nq, int64_t nf,
+                                            const int32_t *facets, hipStream_t stream,
+                                            fem_pk_plan *out) {
+    // host allocations (or threads) can fail for very large meshes: report
+    // it, never throw across the ABI
+    try {
+        return fem_boundary_symbolic_impl(d, nq, nf, facets, stream, out);
+    } catch (...) {
+        return FEM_ERR_NOMEM;
+    }
 }
 
 extern "C" fem_status fem_boundary_mass(fem_pk_plan plan, const double *q, const double *w,

@@ -77,6 +77,7 @@ void free_plan_arrays(fem_plan_data *p) {
     p->status = nullptr;
     p->part = nullptr;
     free_blocks(&p->blk);
+    free_pairs(&p->pscal);
     free_pairs(&p->pvec);
 }
 
@@ -125,7 +126,7 @@ extern "C" const char *fem_status_str(fem_status s) {
     return "FEM_ERR_UNKNOWN";
 }
 
-extern "C" fem_status fem_assemble_symbolic(int32_t d, int64_t nq, int64_t nme, const int32_t *me,
+static fem_status fem_assemble_symbolic_impl(int32_t d, int64_t nq, int64_t nme, const int32_t *me,
                                             hipStream_t stream, fem_plan *out) {
     if (!out || (d != 2 && d != 3) || nq < 0 || nme < 0 || (nme > 0 && !me))
         return FEM_ERR_ARG;
@@ -242,6 +243,35 @@ extern "C" fem_status fem_assemble_symbolic(int32_t d, int64_t nq, int64_t nme, 
         for (auto &x : th) x.join();
     }
 
+    // ---- device plan.  The block layouts need only the pattern and the
+    // incidences: they are built on another thread while this one orders the
+    // elements and uploads the plan arrays (no return before the join).
+    std::unique_ptr<fem_plan_s> p(new fem_plan_s());
+    p->d = d;
+    p->nq = nq;
+    p->nme = nme;
+    p->nnz = nnz;
+    p->max_row = max_row;
+    (void)hipGetDevice(&p->device);
+    fem_status sb = FEM_OK;
+    std::thread layouts;
+    struct Joiner {
+        std::thread &t;
+        ~Joiner() {
+            if (t.joinable()) t.join();
+        }
+    } join_layouts{layouts};   // also on an exception below
+    if (nme > 0)
+        layouts = std::thread([&] {
+            (void)hipSetDevice(p->device);
+            try {
+                sb = upload_blocks(p.get(), d, nq, nme, hme.data(), rp.data(), ci.data(),
+                                   ip.data(), inc_k.data());
+            } catch (...) {
+                sb = FEM_ERR_NOMEM;
+            }
+        });
+
     // ---- locality order of elements: by smallest vertex id (counting sort,
     // stable in caller element number)
     std::vector<int32_t> porig(nme), pinv(nme);
@@ -254,17 +284,17 @@ extern "C" fem_status fem_assemble_symbolic(int32_t d, int64_t nq, int64_t nme, 
                 for (int a = 1; a < NL; ++a) m0 = std::min(m0, hme[size_t(a) * nme + k]);
                 return int64_t(m0);
             },
-            [&](int64_t p, int64_t k) {
-                porig[p] = int32_t(k);
-                pinv[k] = int32_t(p);
+            [&](int64_t q, int64_t k) {
+                porig[q] = int32_t(k);
+                pinv[k] = int32_t(q);
             },
             kptr);
     }
     std::vector<int32_t> pme(size_t(NL) * nme);
     parallel_ranges(nme, [&](int64_t b, int64_t e) {
-        for (int64_t p = b; p < e; ++p) {
-            int64_t k = porig[p];
-            for (int a = 0; a < NL; ++a) pme[size_t(p) * NL + a] = hme[size_t(a) * nme + k];
+        for (int64_t q = b; q < e; ++q) {
+            int64_t k = porig[q];
+            for (int a = 0; a < NL; ++a) pme[size_t(q) * NL + a] = hme[size_t(a) * nme + k];
         }
     });
     std::vector<uint32_t> ielem(ninc);
@@ -274,14 +304,6 @@ extern "C" fem_status fem_assemble_symbolic(int32_t d, int64_t nq, int64_t nme, 
     });
     for (int64_t i = 0; i <= nq; ++i) ip32[i] = int32_t(ip[i]);
 
-    // ---- device plan
-    std::unique_ptr<fem_plan_s> p(new fem_plan_s());
-    p->d = d;
-    p->nq = nq;
-    p->nme = nme;
-    p->nnz = nnz;
-    p->max_row = max_row;
-    (void)hipGetDevice(&p->device);
     fem_status st = FEM_OK;
     if (st == FEM_OK) st = upload(&p->rp, rp);
     if (st == FEM_OK) st = upload(&p->ci, ci);
@@ -292,13 +314,8 @@ extern "C" fem_status fem_assemble_symbolic(int32_t d, int64_t nq, int64_t nme, 
     if (st == FEM_OK) st = upload(&p->inc_off, ioff);
     if (st == FEM_OK) st = upload(&p->status, std::vector<int32_t>(1, 0));
     if (st == FEM_OK) st = upload(&p->part, std::vector<double>(size_t((int64_t(d) * nq + 255) / 256 + 1), 0.0));
-    if (st != FEM_OK) {
-        free_plan_arrays(p.get());
-        return st;
-    }
-    if (st == FEM_OK && nme > 0)
-        st = upload_blocks(p.get(), d, nq, nme, hme.data(), rp.data(), ci.data(), ip.data(),
-                           inc_k.data());
+    if (layouts.joinable()) layouts.join();
+    if (st == FEM_OK) st = sb;
     if (st != FEM_OK) {
         free_plan_arrays(p.get());
         return st;
@@ -307,6 +324,17 @@ extern "C" fem_status fem_assemble_symbolic(int32_t d, int64_t nq, int64_t nme, 
     for (int M : {1, d}) p->launch[M] = row_launch_for(p->h_rp, nq, M, kLdsCap);
     *out = p.release();
     return FEM_OK;
+}
+
+extern "C" fem_status fem_assemble_symbolic(int32_t d, int64_t nq, int64_t nme, const int32_t *me,
+                                            hipStream_t stream, fem_plan *out) {
+    // host allocations (or threads) can fail for very large meshes: report
+    // it, never throw across the ABI
+    try {
+        return fem_assemble_symbolic_impl(d, nq, nme, me, stream, out);
+    } catch (...) {
+        return FEM_ERR_NOMEM;
+    }
 }
 
 extern "C" fem_status fem_plan_query(fem_plan plan, int32_t op, int64_t *nrows, int64_t *nnz) {
