@@ -31,6 +31,8 @@
 #include <thread>
 #include <vector>
 
+#include "symbolic_host.h"
+
 namespace femasm {
 
 constexpr int kPkMaxK = 6;
@@ -199,39 +201,52 @@ inline PkHost build_pk_host(int d, int k, int64_t nq, int64_t nme, const int32_t
         return H;
     }
 
-    // incidences node -> (element, local node), ascending element
-    std::vector<int64_t> ip(nq + 1, 0);
-    for (int64_t e = 0; e < nme; ++e)
-        for (int a = 0; a < n; ++a) ip[node(a, e) + 1] += 1;
-    for (int64_t i = 0; i < nq; ++i) ip[i + 1] += ip[i];
-    std::vector<int32_t> inc_e(ip[nq]);
-    std::vector<uint8_t> inc_a(ip[nq]);
-    {
-        std::vector<int64_t> fill(ip.begin(), ip.end() - 1);
-        for (int64_t e = 0; e < nme; ++e)
-            for (int a = 0; a < n; ++a) {
-                const int64_t p = fill[node(a, e)]++;
-                inc_e[p] = int32_t(e);
-                inc_a[p] = uint8_t(a);
-            }
-    }
+    // incidences node -> (element, local node), ascending element: the
+    // element slots e*n+a sorted stably by their node
+    std::vector<int64_t> ip;
+    std::vector<int32_t> inc_e(size_t(n) * nme);
+    std::vector<uint8_t> inc_a(size_t(n) * nme);
+    stable_key_sort(
+        int64_t(n) * nme, nq, nthreads, [&](int64_t r) { return int64_t(node(int(r % n), r / n)); },
+        [&](int64_t pos, int64_t r) {
+            inc_e[pos] = int32_t(r / n);
+            inc_a[pos] = uint8_t(r % n);
+        },
+        ip);
 
-    // pattern: row i = sorted distinct nodes of the elements around i
+    // pattern: row i = sorted distinct nodes of the elements around i, and
+    // the number of contributions of every entry.  One sort per row: each
+    // thread keeps the columns and counts of its contiguous row range until
+    // the row offsets are known, then copies them into place.
     std::vector<int32_t> rowlen(nq, 0);
-    auto row_cols = [&](int64_t i, std::vector<int32_t> &buf) {
-        buf.clear();
-        for (int64_t t = ip[i]; t < ip[i + 1]; ++t)
-            for (int b = 0; b < n; ++b) buf.push_back(node(b, inc_e[t]));
-        std::sort(buf.begin(), buf.end());
-        buf.erase(std::unique(buf.begin(), buf.end()), buf.end());
-    };
-    pk_parallel(nq, nthreads, [&](int64_t b, int64_t e) {
-        std::vector<int32_t> buf;
-        for (int64_t i = b; i < e; ++i) {
-            row_cols(i, buf);
-            rowlen[i] = int32_t(buf.size());
-        }
-    });
+    const int nrt = nq < 4096 ? 1 : std::max(1, nthreads);
+    const int64_t rchunk = (nq + nrt - 1) / nrt;
+    std::vector<std::vector<int32_t>> tcols(nrt), tcnt(nrt);
+    {
+        auto rows_of = [&](int t) {
+            std::vector<int32_t> buf;
+            for (int64_t i = t * rchunk, e = std::min(nq, (t + 1) * rchunk); i < e; ++i) {
+                buf.clear();
+                for (int64_t u = ip[i]; u < ip[i + 1]; ++u)
+                    for (int b = 0; b < n; ++b) buf.push_back(node(b, inc_e[u]));
+                std::sort(buf.begin(), buf.end());
+                buf.erase(std::unique(buf.begin(), buf.end()), buf.end());
+                rowlen[i] = int32_t(buf.size());
+                const size_t base = tcols[t].size();
+                tcols[t].insert(tcols[t].end(), buf.begin(), buf.end());
+                tcnt[t].resize(base + buf.size(), 0);
+                for (int64_t u = ip[i]; u < ip[i + 1]; ++u)
+                    for (int bb = 0; bb < n; ++bb) {
+                        const int32_t j = node(bb, inc_e[u]);
+                        tcnt[t][base + (std::lower_bound(buf.begin(), buf.end(), j) - buf.begin())] += 1;
+                    }
+            }
+        };
+        std::vector<std::thread> th;
+        for (int t = 1; t < nrt; ++t) th.emplace_back(rows_of, t);
+        rows_of(0);
+        for (auto &x : th) x.join();
+    }
     H.rp.assign(nq + 1, 0);
     int64_t nnz = 0;
     for (int64_t i = 0; i < nq; ++i) {
@@ -248,19 +263,20 @@ inline PkHost build_pk_host(int d, int k, int64_t nq, int64_t nme, const int32_t
     // contributions of every entry, ascending element: (element, tri code)
     H.ci.assign(nnz, 0);
     std::vector<int64_t> cptr(nnz + 1, 0);
-    pk_parallel(nq, nthreads, [&](int64_t b, int64_t e) {
-        std::vector<int32_t> buf;
-        for (int64_t i = b; i < e; ++i) {
-            row_cols(i, buf);
-            std::copy(buf.begin(), buf.end(), H.ci.begin() + H.rp[i]);
-            for (int64_t t = ip[i]; t < ip[i + 1]; ++t)
-                for (int bb = 0; bb < n; ++bb) {
-                    const int32_t j = node(bb, inc_e[t]);
-                    const int64_t pos = std::lower_bound(buf.begin(), buf.end(), j) - buf.begin();
-                    cptr[H.rp[i] + pos + 1] += 1;
-                }
+    {
+        std::vector<std::thread> th;
+        for (int t = 0; t < nrt; ++t) {
+            if (tcols[t].empty()) continue;
+            th.emplace_back([&, t] {
+                const int64_t o = H.rp[std::min(nq, t * rchunk)];
+                std::copy(tcols[t].begin(), tcols[t].end(), H.ci.begin() + o);
+                for (size_t x = 0; x < tcnt[t].size(); ++x) cptr[o + int64_t(x) + 1] = tcnt[t][x];
+                std::vector<int32_t>().swap(tcols[t]);
+                std::vector<int32_t>().swap(tcnt[t]);
+            });
         }
-    });
+        for (auto &x : th) x.join();
+    }
     for (int64_t s = 0; s < nnz; ++s) cptr[s + 1] += cptr[s];
     const int64_t ncontrib = cptr[nnz];
     std::vector<int32_t> celem(ncontrib);

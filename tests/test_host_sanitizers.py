@@ -92,6 +92,10 @@ DRIVER = textwrap.dedent(r"""
         PkHost K = build_pk_host(3, 1, nq, nme, me.data(), 8);
         if (K.status) bad = 1;
         std::printf("pk nnz %ld\n", long(K.nnz));
+        // more than 4096 nodes: the multi-threaded row passes of the P_k builder
+        kuhn(16, me, nq, nme);
+        PkHost K2 = build_pk_host(3, 1, nq, nme, me.data(), 8);
+        if (K2.status || K2.nnz != K2.rp.back()) bad = 1;
         return bad;
     }
 """)

@@ -63,7 +63,9 @@ def _entry_items(L, s, nnz):
     return it & ((1 << eb) - 1), it >> eb
 
 
-CASES = [(2, 2, 3), (2, 3, 2), (2, 5, 1), (3, 2, 2), (3, 3, 1), (3, 1, 2)]
+CASES = [(2, 2, 3), (2, 3, 2), (2, 5, 1), (3, 2, 2), (3, 3, 1), (3, 1, 2),
+         # more than 4096 nodes: the builder's multi-threaded row passes
+         (2, 2, 33), (3, 1, 16)]
 
 
 @pytest.mark.parametrize("d,k,n", CASES)
