@@ -157,9 +157,16 @@ def extras(torch, femasm, mg, plan, q, stream, steps, mesh):
                                         dA.data_ptr(), stream.cuda_stream)
     fv = lambda: femasm.fem_assemble_vjp(plan.handle, 2, q.data_ptr(), None, G.data_ptr(),
                                         slot.data_ptr(), gq.data_ptr(), None, stream.cuda_stream)
+    wbytes = femasm.fem_vjp_work_bytes(plan.handle, 2)
+    work = torch.empty(wbytes // 8, dtype=torch.float64, device=q.device)
+    fvw = lambda: femasm.fem_assemble_vjp_ws(plan.handle, 2, q.data_ptr(), None, G.data_ptr(),
+                                             slot.data_ptr(), work.data_ptr(), wbytes,
+                                             gq.data_ptr(), None, stream.cuda_stream)
     _, pj = time_launches(fj, stream, 10, 2)
     _, pv = time_launches(fv, stream, 10, 2)
+    _, pvw = time_launches(fvw, stream, 10, 2)
     tj, tv = statistics.mean(pj) / 1e3, statistics.mean(pv) / 1e3
+    tvw = statistics.mean(pvw) / 1e3
     ab_j = 2 * 8 * 3 * plan.nq + 16 * plan.nme + 8 * nnz_s   # q, dq, me in; dA out
     ab_v = 2 * 8 * 3 * plan.nq + 16 * plan.nme + 8 * nnz_s   # q, me, G in; dL/dq out
     S = 200_000
@@ -171,13 +178,15 @@ def extras(torch, femasm, mg, plan, q, stream, steps, mesh):
         "jvp_ms": tj * 1e3, "vjp_ms": tv * 1e3,
         "jvp_elements_per_s": plan.nme / tj, "vjp_elements_per_s": plan.nme / tv,
         "jvp_frac": ab_j / tj / 1e9 / PEAK_HBM_GBS, "vjp_frac": ab_v / tv / 1e9 / PEAK_HBM_GBS,
+        "vjp_ws_ms": tvw * 1e3, "vjp_ws_elements_per_s": plan.nme / tvw,
+        "vjp_ws_frac": ab_v / tvw / 1e9 / PEAK_HBM_GBS, "vjp_ws_work_bytes": wbytes,
         "cpu_baseline_jvp": cpu_baseline_sample(
             lambda: oracle.jvp(mesh.q, me_s, "STIFF", dq_h), S, "elements/s",
             f"first {S} elements, complex-step JVP"),
         "cpu_baseline_vjp": cpu_baseline_sample(
             lambda: oracle.vjp(mesh.q, me_s, "STIFF", rp_s, ci_s, G_s), S, "elements/s",
             f"first {S} elements, complex-step VJP")}
-    del G, dq, slot, dA, gq
+    del G, dq, slot, dA, gq, work
     # boundary (Robin) weighted mass on the surface of the cube
     facets = torch.from_numpy(mg.boundary_facets(mesh)).to(q.device)
     bplan = femasm.BoundaryPlan(facets, plan.nq)

@@ -221,6 +221,28 @@ fem_status fem_assemble_vjp(fem_plan plan, int32_t op, const double *q, const do
                             const double *G, const int32_t *slot, double *dLdq, double *dLdw,
                             hipStream_t stream);
 
+/*
+ * Workspace form of fem_assemble_vjp, for callers that can lend scratch
+ * memory: the same outputs, bit for bit, computed with every element's
+ * derivative terms evaluated once (fem_assemble_vjp evaluates them once per
+ * vertex of the element).  Two kernels on `stream`: one thread per element
+ * writes the terms of its d+1 vertices into `work`, then the vertex pass
+ * sums each vertex's terms in the order of fem_assemble_vjp.
+ *   fem_vjp_work_bytes: bytes `work` must hold for operator `op`,
+ *     8 (d+1) nw nme with nw = d (d+1 for FEM_OP_MASS_W); host out-pointer.
+ *   work        device, >= that many bytes, 8-byte aligned; overwritten
+ *               (its contents are scratch; the caller owns the buffer)
+ *   work_bytes  its size in bytes
+ * Other arguments, outputs and errors as fem_assemble_vjp, plus FEM_ERR_ARG
+ * for a missing, short or misaligned work buffer.  Asynchronous, no
+ * allocation.  Concurrent calls must not share `work`.
+ */
+fem_status fem_vjp_work_bytes(fem_plan plan, int32_t op, int64_t *bytes);
+fem_status fem_assemble_vjp_ws(fem_plan plan, int32_t op, const double *q, const double *w,
+                               const double *G, const int32_t *slot, double *work,
+                               int64_t work_bytes, double *dLdq, double *dLdw,
+                               hipStream_t stream);
+
 /* J = a^T A b for CSR values of operator `op` produced with this plan:
  * out (device, 1 double).  Row partial sums are combined in row order, so
  * the result is bitwise reproducible.  Asynchronous.  The partial sums live

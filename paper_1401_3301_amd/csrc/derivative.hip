@@ -164,6 +164,147 @@ __global__ void __launch_bounds__(256) k_jvp(MeshView mv, const double *__restri
     if (any != 0ull && (threadIdx.x & 63) == __ffsll((long long)any) - 1) atomicOr(status, bad);
 }
 
+// Geometry of one element for the VJP terms: barycentric gradients and
+// |det B_K|.  False for a degenerate element (no contribution).
+template <int D>
+struct VjpGeom {
+    double g[D + 1][D];
+    double ad;
+};
+
+template <int D>
+__device__ __forceinline__ bool vjp_geometry(const double (&P)[D + 1][D], VjpGeom<D> &V) {
+    Elem<D> E;
+    elem_geometry(P, E);
+    if (E.det == 0.0) return false;
+    const double rdet = 1.0 / E.det;
+    V.ad = fabs(E.det);
+#pragma unroll
+    for (int b = 0; b < D + 1; ++b)
+#pragma unroll
+        for (int x = 0; x < D; ++x) V.g[b][x] = E.c[b][x] * rdet;
+    return true;
+}
+
+// The VJP term of one element at its local vertex al: tq (d values, the
+// contribution to dL/dq at that vertex) and, for the weighted mass, tw (to
+// dL/dw).  Gk[a][b] is the upstream gradient at the element's entry (a, b);
+// wl the element's nodal weights (weighted mass only).
+template <int D, int OP>
+__device__ __forceinline__ void vjp_term(const VjpGeom<D> &V, const double (&Gk)[D + 1][D + 1],
+                                         const double (&wl)[D + 1], int al, double (&tq)[D],
+                                         double &tw) {
+    constexpr int NL = D + 1;
+    double gc[D];
+#pragma unroll
+    for (int x = 0; x < D; ++x) {
+        double cx[NL];
+#pragma unroll
+        for (int b = 0; b < NL; ++b) cx[b] = V.g[b][x];
+        gc[x] = sel<D>(cx, al);
+    }
+    // sums of G used by the mass terms
+    double gsum = 0.0, gtr = 0.0, rowc = 0.0, colc = 0.0, gcc = 0.0;
+#pragma unroll
+    for (int a = 0; a < NL; ++a) {
+        gtr += Gk[a][a];
+#pragma unroll
+        for (int b = 0; b < NL; ++b) {
+            gsum += Gk[a][b];
+            if (a == al) rowc += Gk[a][b];
+            if (b == al) colc += Gk[a][b];
+        }
+        if (a == al) gcc = Gk[a][a];
+    }
+    tw = 0.0;
+    if constexpr (OP == FEM_OP_STIFF) {
+        const double vol = V.ad / Fact<D>::dfact;
+        double y[NL], s = 0.0;
+#pragma unroll
+        for (int a = 0; a < NL; ++a) y[a] = cdot<D>(V.g[a], gc);
+#pragma unroll
+        for (int a = 0; a < NL; ++a)
+#pragma unroll
+            for (int b = 0; b < NL; ++b) s = fma(Gk[a][b], cdot<D>(V.g[a], V.g[b]), s);
+        double Uz[D];
+#pragma unroll
+        for (int x = 0; x < D; ++x) Uz[x] = 0.0;
+#pragma unroll
+        for (int a = 0; a < NL; ++a) {
+            double z = 0.0;
+#pragma unroll
+            for (int b = 0; b < NL; ++b) z = fma(Gk[a][b] + Gk[b][a], y[b], z);
+#pragma unroll
+            for (int x = 0; x < D; ++x) Uz[x] = fma(z, V.g[a][x], Uz[x]);
+        }
+#pragma unroll
+        for (int x = 0; x < D; ++x) tq[x] = vol * (s * gc[x] - Uz[x]);
+    } else if constexpr (OP == FEM_OP_MASS) {
+        const double sk = V.ad / Fact<D>::mass_den * (gsum + gtr);
+#pragma unroll
+        for (int x = 0; x < D; ++x) tq[x] = sk * gc[x];
+    } else {
+        double ws = wl[0];
+#pragma unroll
+        for (int b = 1; b < NL; ++b) ws += wl[b];
+        const double kk = V.ad / Fact<D>::massw_den;
+        // sum_ab G_ab (1+delta_ab)(w^s + w_a + w_b)
+        double s = 0.0;
+#pragma unroll
+        for (int a = 0; a < NL; ++a)
+#pragma unroll
+            for (int b = 0; b < NL; ++b)
+                s = fma(Gk[a][b] * (a == b ? 2.0 : 1.0), ws + (wl[a] + wl[b]), s);
+        const double sk = kk * s;
+#pragma unroll
+        for (int x = 0; x < D; ++x) tq[x] = sk * gc[x];
+        tw = kk * ((gsum + gtr) + (rowc + colc) + 2.0 * gcc);
+    }
+}
+
+// Loads of one element (internal number e) for the VJP: coordinates, the
+// upstream gradient block through the caller's slot map, nodal weights.
+template <int D, int OP>
+__device__ __forceinline__ void vjp_load(const MeshView &mv, const int32_t *__restrict__ porig,
+                                         const int32_t *__restrict__ slot,
+                                         const double *__restrict__ G, int64_t e,
+                                         double (&P)[D + 1][D], double (&Gk)[D + 1][D + 1],
+                                         double (&wl)[D + 1]) {
+    constexpr int NL = D + 1;
+    const int64_t k = porig[e];
+#pragma unroll
+    for (int b = 0; b < NL; ++b)
+#pragma unroll
+        for (int a = 0; a < NL; ++a) Gk[a][b] = G[slot[k * NL * NL + b * NL + a]];
+#pragma unroll
+    for (int b = 0; b < NL; ++b) {
+        const int v = mv.pme[e * NL + b];
+#pragma unroll
+        for (int x = 0; x < D; ++x) P[b][x] = mv.q[x * mv.nq + v];
+        wl[b] = OP == FEM_OP_MASS_W ? mv.w[v] : 0.0;
+    }
+}
+
+// Lane-strided sums of one vertex's incidence terms, combined by shuffles in
+// a fixed tree; lane 0 of each group writes the vertex's outputs.
+template <int D>
+__device__ __forceinline__ void vjp_store(const MeshView &mv, int64_t i, int j, double (&gq)[D],
+                                          double gw, double *__restrict__ dLdq,
+                                          double *__restrict__ dLdw) {
+#pragma unroll
+    for (int sh = 1; sh < kVjpLanes; sh <<= 1) {
+        gw += __shfl_xor(gw, sh, kVjpLanes);
+#pragma unroll
+        for (int x = 0; x < D; ++x) gq[x] += __shfl_xor(gq[x], sh, kVjpLanes);
+    }
+    if (i < mv.nq && j == 0) {
+        if (dLdw) dLdw[i] = gw;
+        if (dLdq)
+#pragma unroll
+            for (int x = 0; x < D; ++x) dLdq[x * mv.nq + i] = gq[x];
+    }
+}
+
 template <int D, int OP>
 __global__ void __launch_bounds__(256)
     k_vjp(MeshView mv, const int32_t *__restrict__ porig, const int32_t *__restrict__ slot,
@@ -295,6 +436,69 @@ __global__ void __launch_bounds__(256)
     if (any != 0ull && (threadIdx.x & 63) == __ffsll((long long)any) - 1) atomicOr(status, bad);
 }
 
+// Workspace VJP, element pass: one thread per element (plan order e) writes
+// the terms of its d+1 vertices to work[(e*(d+1) + a)*NW + ...], NW = d
+// (+1 for the weighted mass); zeros for a degenerate element.
+template <int D, int OP>
+__global__ void __launch_bounds__(256)
+    k_vjp_elem(MeshView mv, int64_t nme, const int32_t *__restrict__ porig,
+               const int32_t *__restrict__ slot, const double *__restrict__ G,
+               double *__restrict__ work, int32_t *status) {
+    constexpr int NL = D + 1;
+    constexpr int NW = D + (OP == FEM_OP_MASS_W ? 1 : 0);
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    int bad = 0;
+    if (e < nme) {
+        double P[NL][D], Gk[NL][NL], wl[NL];
+        vjp_load<D, OP>(mv, porig, slot, G, e, P, Gk, wl);
+        VjpGeom<D> V;
+        double *out = work + e * NL * NW;
+        if (!vjp_geometry<D>(P, V)) {
+            bad = 1;
+#pragma unroll
+            for (int u = 0; u < NL * NW; ++u) out[u] = 0.0;
+        } else {
+#pragma unroll
+            for (int al = 0; al < NL; ++al) {
+                double tq[D], tw;
+                vjp_term<D, OP>(V, Gk, wl, al, tq, tw);
+#pragma unroll
+                for (int x = 0; x < D; ++x) out[al * NW + x] = tq[x];
+                if constexpr (OP == FEM_OP_MASS_W) out[al * NW + D] = tw;
+            }
+        }
+    }
+    const unsigned long long any = __ballot(bad != 0);
+    if (any != 0ull && (threadIdx.x & 63) == __ffsll((long long)any) - 1) atomicOr(status, bad);
+}
+
+// Workspace VJP, vertex pass: the terms of each vertex's incidences summed in
+// the order of k_vjp (same lanes, same tree), so the outputs are identical.
+template <int D, int OP>
+__global__ void __launch_bounds__(256)
+    k_vjp_gather(MeshView mv, const double *__restrict__ work, double *__restrict__ dLdq,
+                 double *__restrict__ dLdw) {
+    constexpr int NL = D + 1;
+    constexpr int NW = D + (OP == FEM_OP_MASS_W ? 1 : 0);
+    const int64_t gt = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t i = gt / kVjpLanes;
+    const int j = int(gt % kVjpLanes);
+    double gw = 0.0, gq[D];
+#pragma unroll
+    for (int x = 0; x < D; ++x) gq[x] = 0.0;
+    if (i < mv.nq) {
+        for (int t = mv.inc_ptr[i] + j; t < mv.inc_ptr[i + 1]; t += kVjpLanes) {
+            const uint32_t ea = mv.inc_elem[t];
+            const int64_t e = ea & 0x3fffffffu;
+            const double *in = work + (e * NL + int(ea >> 30)) * NW;
+#pragma unroll
+            for (int x = 0; x < D; ++x) gq[x] += in[x];
+            if constexpr (OP == FEM_OP_MASS_W) gw += in[D];
+        }
+    }
+    vjp_store<D>(mv, i, j, gq, gw, dLdq, dLdw);
+}
+
 MeshView deriv_view(const fem_plan_s *p, const double *q, const double *w, double *values) {
     MeshView mv{};
     mv.rp = p->rp;
@@ -342,7 +546,38 @@ hipError_t launch_vjp(const fem_plan_s *p, int op, const MeshView &mv, const int
     return hipGetLastError();
 }
 
+template <int D, int OP>
+hipError_t launch_vjp_ws_t(const fem_plan_s *p, const MeshView &mv, const int32_t *slot,
+                           const double *G, double *work, double *dLdq, double *dLdw,
+                           hipStream_t s) {
+    if (p->nme > 0) {
+        const unsigned ge = unsigned((p->nme + 255) / 256);
+        hipLaunchKernelGGL((k_vjp_elem<D, OP>), dim3(ge), dim3(256), 0, s, mv, p->nme, p->porig,
+                           slot, G, work, p->status);
+    }
+    const unsigned gv = unsigned((p->nq * kVjpLanes + 255) / 256);
+    hipLaunchKernelGGL((k_vjp_gather<D, OP>), dim3(gv), dim3(256), 0, s, mv, work, dLdq, dLdw);
+    return hipGetLastError();
+}
+
+template <int D>
+hipError_t launch_vjp_ws(const fem_plan_s *p, int op, const MeshView &mv, const int32_t *slot,
+                         const double *G, double *work, double *dLdq, double *dLdw,
+                         hipStream_t s) {
+    if (op == FEM_OP_MASS)
+        return launch_vjp_ws_t<D, FEM_OP_MASS>(p, mv, slot, G, work, dLdq, dLdw, s);
+    if (op == FEM_OP_MASS_W)
+        return launch_vjp_ws_t<D, FEM_OP_MASS_W>(p, mv, slot, G, work, dLdq, dLdw, s);
+    return launch_vjp_ws_t<D, FEM_OP_STIFF>(p, mv, slot, G, work, dLdq, dLdw, s);
+}
+
 bool deriv_op(int32_t op) { return op == FEM_OP_MASS || op == FEM_OP_MASS_W || op == FEM_OP_STIFF; }
+
+// bytes of the element-term work array of the workspace VJP
+int64_t vjp_work_bytes(const fem_plan_s *p, int32_t op) {
+    const int64_t nw = p->d + (op == FEM_OP_MASS_W ? 1 : 0);
+    return int64_t(sizeof(double)) * (p->d + 1) * nw * p->nme;
+}
 
 }  // namespace
 }  // namespace femasm
@@ -381,5 +616,29 @@ extern "C" fem_status fem_assemble_vjp(fem_plan plan, int32_t op, const double *
     const MeshView mv = deriv_view(plan, q, w, nullptr);
     const hipError_t e = plan->d == 2 ? launch_vjp<2>(plan, op, mv, slot, G, dLdq, dLdw, stream)
                                       : launch_vjp<3>(plan, op, mv, slot, G, dLdq, dLdw, stream);
+    return hip_status(e);
+}
+
+extern "C" fem_status fem_vjp_work_bytes(fem_plan plan, int32_t op, int64_t *bytes) {
+    if (!plan || !deriv_op(op) || !bytes) return FEM_ERR_ARG;
+    *bytes = vjp_work_bytes(plan, op);
+    return FEM_OK;
+}
+
+extern "C" fem_status fem_assemble_vjp_ws(fem_plan plan, int32_t op, const double *q,
+                                          const double *w, const double *G, const int32_t *slot,
+                                          double *work, int64_t work_bytes, double *dLdq,
+                                          double *dLdw, hipStream_t stream) {
+    if (!plan || !deriv_op(op)) return FEM_ERR_ARG;
+    if (plan->nq == 0) return FEM_OK;
+    if (!q || (plan->nnz > 0 && (!G || !slot)) || (op == FEM_OP_MASS_W && !w)) return FEM_ERR_ARG;
+    if (plan->nme > 0 && (!work || work_bytes < vjp_work_bytes(plan, op) ||
+                          (reinterpret_cast<uintptr_t>(work) & 7u) != 0))
+        return FEM_ERR_ARG;
+    if (op != FEM_OP_MASS_W) dLdw = nullptr;
+    const MeshView mv = deriv_view(plan, q, w, nullptr);
+    const hipError_t e =
+        plan->d == 2 ? launch_vjp_ws<2>(plan, op, mv, slot, G, work, dLdq, dLdw, stream)
+                     : launch_vjp_ws<3>(plan, op, mv, slot, G, work, dLdq, dLdw, stream);
     return hip_status(e);
 }

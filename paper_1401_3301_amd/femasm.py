@@ -53,6 +53,8 @@ _SIGS = {
     "fem_assemble_general": ([P, P, P, P, P], C.c_int),
     "fem_assemble_jvp": ([P, I32, P, P, P, P, P, P], C.c_int),
     "fem_assemble_vjp": ([P, I32, P, P, P, P, P, P, P], C.c_int),
+    "fem_vjp_work_bytes": ([P, I32, C.POINTER(I64)], C.c_int),
+    "fem_assemble_vjp_ws": ([P, I32, P, P, P, P, P, I64, P, P, P], C.c_int),
     "fem_assemble_backward": ([P, U32, P, P, P, P, P, P, P], C.c_int),
     "fem_csr_bilinear": ([P, I32, P, P, P, P, P], C.c_int),
     "fem_plan_sync_status": ([P, P], C.c_int),
@@ -179,6 +181,18 @@ def fem_assemble_vjp(plan: int, op: int, q: int, w: int | None, G: int, slot: in
                      dLdq: int | None, dLdw: int | None, stream=None):
     _check(load_library().fem_assemble_vjp(plan, op, q, w, G, slot, dLdq, dLdw, _stream(stream)),
            "fem_assemble_vjp")
+
+
+def fem_vjp_work_bytes(plan: int, op: int) -> int:
+    n = I64(0)
+    _check(load_library().fem_vjp_work_bytes(plan, op, C.byref(n)), "fem_vjp_work_bytes")
+    return int(n.value)
+
+
+def fem_assemble_vjp_ws(plan: int, op: int, q: int, w: int | None, G: int, slot: int, work: int,
+                        work_bytes: int, dLdq: int | None, dLdw: int | None, stream=None):
+    _check(load_library().fem_assemble_vjp_ws(plan, op, q, w, G, slot, work, work_bytes, dLdq,
+                                              dLdw, _stream(stream)), "fem_assemble_vjp_ws")
 
 
 def fem_assemble_backward(plan: int, op_mask: int, q: int, w: int | None, a: int, b: int,
@@ -385,16 +399,30 @@ class Plan:
                          out.data_ptr(), stream)
         return out[:nnz]
 
-    def vjp(self, op, q, G, w=None, slot=None, want_w=True, stream=None):
-        """Gradient of sum(G * A) with respect to q (d, nq) and, for MASS_W, w."""
+    def vjp_work_bytes(self, op):
+        """Bytes of the work buffer of the workspace VJP for operator `op`."""
+        return fem_vjp_work_bytes(self.handle, _op(op))
+
+    def vjp(self, op, q, G, w=None, slot=None, want_w=True, stream=None, work=None):
+        """Gradient of sum(G * A) with respect to q (d, nq) and, for MASS_W, w.
+        With `work` (a device tensor of at least vjp_work_bytes(op) bytes) the
+        workspace form runs: the same values, each element evaluated once."""
         if slot is None:
             slot = self.slot_map(stream)
         q, w, G = (_dev_f64(x, self.device) for x in (q, w, G))
         gq = torch.empty(self.d, self.nq, dtype=torch.float64, device=self.device)
         gw = (torch.empty(self.nq, dtype=torch.float64, device=self.device)
               if (_op(op) == FEM_OP["MASS_W"] and want_w) else None)
-        fem_assemble_vjp(self.handle, _op(op), q.data_ptr(), _ptr(w), G.data_ptr(),
-                         slot.data_ptr(), gq.data_ptr(), _ptr(gw), stream)
+        if work is None:
+            fem_assemble_vjp(self.handle, _op(op), q.data_ptr(), _ptr(w), G.data_ptr(),
+                             slot.data_ptr(), gq.data_ptr(), _ptr(gw), stream)
+        else:
+            if not work.is_cuda:
+                raise ValueError("work must be a device tensor")
+            fem_assemble_vjp_ws(self.handle, _op(op), q.data_ptr(), _ptr(w), G.data_ptr(),
+                                slot.data_ptr(), work.data_ptr(),
+                                work.numel() * work.element_size(), gq.data_ptr(), _ptr(gw),
+                                stream)
         return gq, gw
 
     def backward(self, q, w, a, b, op_mask=("STIFF", "MASS_W"), want_w=True, want_q=True,
