@@ -549,9 +549,9 @@ inline PairHost build_pair_host(const BlockHost &H, int d, const int32_t *rp, co
                     const int64_t e0 = P.ent_ptr[b];
                     for (int w = 0; w <= kWaves; ++w)
                         P.wt[size_t(b) * (kWaves + 1) + w] = t0 + B.wfirst[w];
-                    for (size_t t = 0; t < B.cnt.size(); ++t) {
-                        P.task_cnt[size_t(t0) + t] = B.cnt[t];
-                        P.task_ent[size_t(t0) + t] = e0 + B.eoff[t];
+                    for (size_t u = 0; u < B.cnt.size(); ++u) {
+                        P.task_cnt[size_t(t0) + u] = B.cnt[u];
+                        P.task_ent[size_t(t0) + u] = e0 + B.eoff[u];
                     }
                     std::copy(B.hdr.begin(), B.hdr.end(), P.hdr.begin() + size_t(t0) * 64);
                     std::copy(B.hdr2.begin(), B.hdr2.end(), P.hdr2.begin() + size_t(t0) * 64);

@@ -99,7 +99,7 @@ __global__ void k_bilinear_rows(const int32_t *__restrict__ rp, const int32_t *_
     }
     red[threadIdx.x] = s;
     __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    for (unsigned w = blockDim.x / 2; w > 0; w >>= 1) {
         if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
@@ -115,7 +115,7 @@ __global__ void k_sum_parts(const double *__restrict__ part, int64_t n, double *
     for (int64_t k = b0; k < b1; ++k) s += part[k];
     red[threadIdx.x] = s;
     __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    for (unsigned w = blockDim.x / 2; w > 0; w >>= 1) {
         if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
