@@ -353,13 +353,13 @@ fem_status upload_blocks(fem_plan_data *p, int d, int64_t nq, int64_t nme, const
     // families), so it is built only then.
     fem_status sb = FEM_OK, ss = FEM_OK, sv = FEM_OK;
     const int dev = p->device;
-    std::thread ts([&] {
+    run_threads(2, [&](int t) {
         (void)hipSetDevice(dev);
-        ss = upload_pairs(p->pscal, Rs, Ss, true, d, nq, nme, me, rp, ci, ip, inc_k);
+        if (t == 0)
+            sv = upload_pairs(p->pvec, Re, Se, false, d, nq, nme, me, rp, ci, ip, inc_k);
+        else
+            ss = upload_pairs(p->pscal, Rs, Ss, true, d, nq, nme, me, rp, ci, ip, inc_k);
     });
-    (void)hipSetDevice(dev);
-    sv = upload_pairs(p->pvec, Re, Se, false, d, nq, nme, me, rp, ci, ip, inc_k);
-    ts.join();
     if (ss == FEM_OK && (!p->pscal.ok || env_int("FEMASM_BLOCK_LAYOUT", 0, 0, 1) == 1)) {
         BlockHost H = build_block_host(d, nq, nme, me, rp, ci, ip, inc_k, R, 16);
         if (H.ok && H.nb > 0) sb = upload_layout(p->blk, H, rp, true);

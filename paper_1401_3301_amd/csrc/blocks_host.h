@@ -28,6 +28,8 @@
 #include <thread>
 #include <vector>
 
+#include "host_threads.h"
+
 namespace femasm {
 
 struct BlockHost {
@@ -165,13 +167,7 @@ inline BlockHost build_block_host(int d, int64_t nq, int64_t nme, const int32_t 
             nbc += 1;
         }
     };
-    if (nchunk == 1) {
-        grow(0);
-    } else {
-        std::vector<std::thread> th;
-        for (int c = 0; c < nchunk; ++c) th.emplace_back(grow, c);
-        for (auto &x : th) x.join();
-    }
+    run_threads(nchunk, grow);
     H.row_ptr.push_back(0);
     for (int c = 0; c < nchunk; ++c) {
         if (cfail[c]) return BlockHost();
@@ -279,17 +275,8 @@ inline BlockHost build_block_host(int d, int64_t nq, int64_t nme, const int32_t 
             for (int32_t v : B.nodes) loc[v] = -1;
         }
     };
-    {
-        const int nt = std::max(1, std::min(nthreads, nb / 64 + 1));
-        std::vector<std::thread> th;
-        const int chunk = (nb + nt - 1) / nt;
-        for (int t = 0; t < nt; ++t) {
-            const int b0 = t * chunk, b1 = std::min(nb, b0 + chunk);
-            if (b0 >= b1) break;
-            th.emplace_back(work, b0, b1);
-        }
-        for (auto &x : th) x.join();
-    }
+    run_chunks(std::min(nthreads, nb / 64 + 1), nb,
+               [&](int64_t b0, int64_t b1) { work(int(b0), int(b1)); });
     // offsets of every block's lists, then the lists copied into place in
     // parallel (block order, so the result does not depend on the threads)
     H.node_ptr.assign(size_t(nb) + 1, 0);
@@ -311,25 +298,15 @@ inline BlockHost build_block_host(int d, int64_t nq, int64_t nme, const int32_t 
     H.nodes.resize(size_t(H.node_ptr[nb]));
     H.elem.resize(size_t(H.elem_ptr[nb]) * 4);
     H.rec.resize(size_t(H.rec_ptr[nb]));
-    {
-        const int nt = std::max(1, std::min(nthreads, nb / 64 + 1));
-        std::vector<std::thread> th;
-        const int chunk = (nb + nt - 1) / nt;
-        for (int t = 0; t < nt; ++t) {
-            const int b0 = t * chunk, b1 = std::min(nb, b0 + chunk);
-            if (b0 >= b1) break;
-            th.emplace_back([&, b0, b1] {
-                for (int b = b0; b < b1; ++b) {
-                    Blk &B = blks[b];
-                    std::copy(B.nodes.begin(), B.nodes.end(), H.nodes.begin() + H.node_ptr[b]);
-                    std::copy(B.elem.begin(), B.elem.end(), H.elem.begin() + size_t(H.elem_ptr[b]) * 4);
-                    std::copy(B.rec.begin(), B.rec.end(), H.rec.begin() + H.rec_ptr[b]);
-                    B = Blk();
-                }
-            });
+    run_chunks(std::min(nthreads, nb / 64 + 1), nb, [&](int64_t b0, int64_t b1) {
+        for (int64_t b = b0; b < b1; ++b) {
+            Blk &B = blks[b];
+            std::copy(B.nodes.begin(), B.nodes.end(), H.nodes.begin() + H.node_ptr[b]);
+            std::copy(B.elem.begin(), B.elem.end(), H.elem.begin() + size_t(H.elem_ptr[b]) * 4);
+            std::copy(B.rec.begin(), B.rec.end(), H.rec.begin() + H.rec_ptr[b]);
+            B = Blk();
         }
-        for (auto &x : th) x.join();
-    }
+    });
     H.total_elems = H.elem_ptr.back();
     H.ok = true;
     return H;
@@ -506,17 +483,8 @@ inline PairHost build_pair_host(const BlockHost &H, int d, const int32_t *rp, co
             }
         }
     };
-    {
-        const int nt = std::max(1, std::min(nthreads, nb / 64 + 1));
-        std::vector<std::thread> th;
-        const int chunk = (nb + nt - 1) / nt;
-        for (int t = 0; t < nt; ++t) {
-            const int b0 = t * chunk, b1 = std::min(nb, b0 + chunk);
-            if (b0 >= b1) break;
-            th.emplace_back(work, b0, b1);
-        }
-        for (auto &x : th) x.join();
-    }
+    run_chunks(std::min(nthreads, nb / 64 + 1), nb,
+               [&](int64_t b0, int64_t b1) { work(int(b0), int(b1)); });
     // task and entry offsets of every block, then the lists copied into
     // place in parallel (block order)
     std::vector<int64_t> tptr(size_t(nb) + 1, 0);
@@ -535,33 +503,22 @@ inline PairHost build_pair_host(const BlockHost &H, int d, const int32_t *rp, co
     P.hdr.resize(size_t(tptr[nb]) * 64);
     P.hdr2.resize(size_t(tptr[nb]) * 64);
     P.ent.resize(size_t(P.ent_ptr[nb]));
-    {
-        const int nt = std::max(1, std::min(nthreads, nb / 64 + 1));
-        std::vector<std::thread> th;
-        const int chunk = (nb + nt - 1) / nt;
-        for (int t = 0; t < nt; ++t) {
-            const int b0 = t * chunk, b1 = std::min(nb, b0 + chunk);
-            if (b0 >= b1) break;
-            th.emplace_back([&, b0, b1] {
-                for (int b = b0; b < b1; ++b) {
-                    Blk &B = blks[b];
-                    const int32_t t0 = int32_t(tptr[b]);
-                    const int64_t e0 = P.ent_ptr[b];
-                    for (int w = 0; w <= kWaves; ++w)
-                        P.wt[size_t(b) * (kWaves + 1) + w] = t0 + B.wfirst[w];
-                    for (size_t u = 0; u < B.cnt.size(); ++u) {
-                        P.task_cnt[size_t(t0) + u] = B.cnt[u];
-                        P.task_ent[size_t(t0) + u] = e0 + B.eoff[u];
-                    }
-                    std::copy(B.hdr.begin(), B.hdr.end(), P.hdr.begin() + size_t(t0) * 64);
-                    std::copy(B.hdr2.begin(), B.hdr2.end(), P.hdr2.begin() + size_t(t0) * 64);
-                    std::copy(B.ent.begin(), B.ent.end(), P.ent.begin() + e0);
-                    B = Blk();
-                }
-            });
+    run_chunks(std::min(nthreads, nb / 64 + 1), nb, [&](int64_t b0, int64_t b1) {
+        for (int64_t b = b0; b < b1; ++b) {
+            Blk &B = blks[b];
+            const int32_t t0 = int32_t(tptr[b]);
+            const int64_t e0 = P.ent_ptr[b];
+            for (int w = 0; w <= kWaves; ++w) P.wt[size_t(b) * (kWaves + 1) + w] = t0 + B.wfirst[w];
+            for (size_t u = 0; u < B.cnt.size(); ++u) {
+                P.task_cnt[size_t(t0) + u] = B.cnt[u];
+                P.task_ent[size_t(t0) + u] = e0 + B.eoff[u];
+            }
+            std::copy(B.hdr.begin(), B.hdr.end(), P.hdr.begin() + size_t(t0) * 64);
+            std::copy(B.hdr2.begin(), B.hdr2.end(), P.hdr2.begin() + size_t(t0) * 64);
+            std::copy(B.ent.begin(), B.ent.end(), P.ent.begin() + e0);
+            B = Blk();
         }
-        for (auto &x : th) x.join();
-    }
+    });
     P.ok = true;
     return P;
 }

@@ -31,6 +31,7 @@
 #include <thread>
 #include <vector>
 
+#include "host_threads.h"
 #include "symbolic_host.h"
 
 namespace femasm {
@@ -138,14 +139,7 @@ void pk_parallel(int64_t n, int nthreads, F fn) {
         fn(int64_t(0), n);
         return;
     }
-    std::vector<std::thread> th;
-    const int64_t chunk = (n + nt - 1) / nt;
-    for (int t = 0; t < nt; ++t) {
-        const int64_t b = t * chunk, e = std::min(n, b + chunk);
-        if (b >= e) break;
-        th.emplace_back([=] { fn(b, e); });
-    }
-    for (auto &x : th) x.join();
+    run_chunks(nt, n, fn);
 }
 
 // Bits of an item that hold the element number, for n local nodes.
@@ -242,10 +236,7 @@ inline PkHost build_pk_host(int d, int k, int64_t nq, int64_t nme, const int32_t
                     }
             }
         };
-        std::vector<std::thread> th;
-        for (int t = 1; t < nrt; ++t) th.emplace_back(rows_of, t);
-        rows_of(0);
-        for (auto &x : th) x.join();
+        run_threads(nrt, rows_of);
     }
     H.rp.assign(nq + 1, 0);
     int64_t nnz = 0;
@@ -263,20 +254,14 @@ inline PkHost build_pk_host(int d, int k, int64_t nq, int64_t nme, const int32_t
     // contributions of every entry, ascending element: (element, tri code)
     H.ci.assign(nnz, 0);
     std::vector<int64_t> cptr(nnz + 1, 0);
-    {
-        std::vector<std::thread> th;
-        for (int t = 0; t < nrt; ++t) {
-            if (tcols[t].empty()) continue;
-            th.emplace_back([&, t] {
-                const int64_t o = H.rp[std::min(nq, t * rchunk)];
-                std::copy(tcols[t].begin(), tcols[t].end(), H.ci.begin() + o);
-                for (size_t x = 0; x < tcnt[t].size(); ++x) cptr[o + int64_t(x) + 1] = tcnt[t][x];
-                std::vector<int32_t>().swap(tcols[t]);
-                std::vector<int32_t>().swap(tcnt[t]);
-            });
-        }
-        for (auto &x : th) x.join();
-    }
+    run_threads(nrt, [&](int t) {
+        if (tcols[t].empty()) return;
+        const int64_t o = H.rp[std::min(nq, t * rchunk)];
+        std::copy(tcols[t].begin(), tcols[t].end(), H.ci.begin() + o);
+        for (size_t x = 0; x < tcnt[t].size(); ++x) cptr[o + int64_t(x) + 1] = tcnt[t][x];
+        std::vector<int32_t>().swap(tcols[t]);
+        std::vector<int32_t>().swap(tcnt[t]);
+    });
     for (int64_t s = 0; s < nnz; ++s) cptr[s + 1] += cptr[s];
     const int64_t ncontrib = cptr[nnz];
     std::vector<int32_t> celem(ncontrib);

@@ -15,6 +15,7 @@
 #include <thread>
 
 #include "femasm_impl.h"
+#include "host_threads.h"
 #include "symbolic_host.h"
 
 namespace femasm {
@@ -41,14 +42,7 @@ void parallel_ranges(int64_t n, F fn) {
         fn(int64_t(0), n);
         return;
     }
-    std::vector<std::thread> th;
-    int64_t chunk = (n + nt - 1) / nt;
-    for (int t = 0; t < nt; ++t) {
-        int64_t b = t * chunk, e = std::min(n, b + chunk);
-        if (b >= e) break;
-        th.emplace_back([=] { fn(b, e); });
-    }
-    for (auto &x : th) x.join();
+    run_chunks(nt, n, fn);
 }
 
 template <class T>
@@ -213,10 +207,7 @@ static fem_status fem_assemble_symbolic_impl(int32_t d, int64_t nq, int64_t nme,
                 }
             }
         };
-        std::vector<std::thread> th;
-        for (int t = 1; t < nrt; ++t) th.emplace_back(rows_of, t);
-        rows_of(0);
-        for (auto &x : th) x.join();
+        run_threads(nrt, rows_of);
     }
     if (too_long) return FEM_ERR_OVERFLOW;
     std::vector<int32_t> rp(nq + 1, 0);
@@ -230,18 +221,11 @@ static fem_status fem_assemble_symbolic_impl(int32_t d, int64_t nq, int64_t nme,
     }
     rp[nq] = int32_t(nnz);
     std::vector<int32_t> ci(nnz);
-    {
-        std::vector<std::thread> th;
-        for (int t = 0; t < nrt; ++t) {
-            const int64_t r0 = std::min(nq, t * rchunk);
-            if (tcols[t].empty()) continue;
-            th.emplace_back([&, t, r0] {
-                std::copy(tcols[t].begin(), tcols[t].end(), ci.begin() + rp[r0]);
-                std::vector<int32_t>().swap(tcols[t]);
-            });
-        }
-        for (auto &x : th) x.join();
-    }
+    run_threads(nrt, [&](int t) {
+        if (tcols[t].empty()) return;
+        std::copy(tcols[t].begin(), tcols[t].end(), ci.begin() + rp[std::min(nq, t * rchunk)]);
+        std::vector<int32_t>().swap(tcols[t]);
+    });
 
     // ---- device plan.  The block layouts need only the pattern and the
     // incidences: they are built on another thread while this one orders the

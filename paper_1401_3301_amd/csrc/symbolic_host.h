@@ -10,8 +10,9 @@
 #include <algorithm>
 #include <atomic>
 #include <cstdint>
-#include <thread>
 #include <vector>
+
+#include "host_threads.h"
 
 namespace femasm {
 
@@ -35,16 +36,7 @@ void stable_key_sort(int64_t n, int64_t nkeys, int nthreads, KeyF key, EmitF emi
     const int T = int(std::max<int64_t>(1, std::min<int64_t>(nthreads, n / 65536 + 1)));
     const int64_t chunk = (n + T - 1) / T;
     std::vector<int64_t> cnt(size_t(T) * nbk, 0);   // [thread][bucket]
-    auto run = [&](int nt, auto fn) {
-        if (nt == 1) {
-            fn(0);
-            return;
-        }
-        std::vector<std::thread> th;
-        for (int t = 0; t < nt; ++t) th.emplace_back([&, t] { fn(t); });
-        for (auto &x : th) x.join();
-    };
-    run(T, [&](int t) {
+    run_threads(T, [&](int t) {
         int64_t *c = cnt.data() + size_t(t) * nbk;
         for (int64_t r = t * chunk, e = std::min(n, r + chunk); r < e; ++r) c[key(r) >> S] += 1;
     });
@@ -63,7 +55,7 @@ void stable_key_sort(int64_t n, int64_t nkeys, int nthreads, KeyF key, EmitF emi
         bstart[nbk] = o;
     }
     std::vector<uint32_t> tmp(static_cast<size_t>(n));
-    run(T, [&](int t) {
+    run_threads(T, [&](int t) {
         int64_t *c = cnt.data() + size_t(t) * nbk;
         for (int64_t r = t * chunk, e = std::min(n, r + chunk); r < e; ++r)
             tmp[c[key(r) >> S]++] = uint32_t(r);
@@ -71,7 +63,7 @@ void stable_key_sort(int64_t n, int64_t nkeys, int nthreads, KeyF key, EmitF emi
     // buckets: counting sort by the low key bits, handed out dynamically
     std::atomic<int64_t> next{0};
     const int TB = int(std::max<int64_t>(1, std::min<int64_t>(nthreads, nbk)));
-    run(TB, [&](int) {
+    run_threads(TB, [&](int) {
         std::vector<int64_t> h(size_t(1) << S);
         for (int64_t b; (b = next.fetch_add(1)) < nbk;) {
             const int64_t k0 = b << S, k1 = std::min(nkeys, k0 + (int64_t(1) << S));

@@ -77,3 +77,21 @@ extern "C" void hl_key_sort(int64_t n, int64_t nkeys, const int64_t *keys, int n
         [&](int64_t pos, int64_t r) { order[pos] = r; }, p);
     std::memcpy(ptr, p.data(), sizeof(int64_t) * p.size());
 }
+
+#include <new>
+
+#include "../paper_1401_3301_amd/csrc/host_threads.h"
+
+// run_threads: every index runs; an exception thrown on one of them reaches
+// the caller after all have been joined (returns 1 then).
+extern "C" int hl_run_threads(int nt, int throw_at, int *ran) {
+    try {
+        run_threads(nt, [&](int t) {
+            ran[t] = 1;
+            if (t == throw_at) throw std::bad_alloc();
+        });
+    } catch (const std::bad_alloc &) {
+        return 1;
+    }
+    return 0;
+}

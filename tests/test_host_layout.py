@@ -277,3 +277,14 @@ def test_incidence_order_of_a_mesh(shim):
         ks = order[ptr[v]:ptr[v + 1]] // nl
         assert np.all(np.diff(ks) > 0)
         assert set(ks.tolist()) == set(np.nonzero((mesh.me == v).any(axis=0))[0].tolist())
+
+
+@pytest.mark.parametrize("nt,throw_at", [(1, -1), (8, -1), (8, 0), (8, 5), (3, 2)])
+def test_run_threads_joins_and_rethrows(shim, nt, throw_at):
+    # the builders' thread helper: all indices run and are joined; a worker's
+    # exception is rethrown on the calling thread (the entry points turn it
+    # into FEM_ERR_NOMEM instead of terminating the process)
+    ran = np.zeros(nt, np.int32)
+    st = shim.hl_run_threads(nt, throw_at, _p(ran))
+    assert st == (1 if throw_at >= 0 else 0)
+    assert ran.tolist() == [1] * nt
