@@ -96,6 +96,71 @@ def cpu_baseline_sample(fn, units, unit, what):
             "sample": f"{what}, {dt:.1f} s"}
 
 
+NEXT_OPS = ("nodal", "general", "jvp", "vjp", "vjp_ws", "boundary")
+
+
+def next_run(torch, femasm, mg, name, stream, steps, warmup):
+    """Times one operator beyond the four P1 ones alone on the 128^3 cube
+    (inputs as in the extras), for kernel traces of that operator."""
+    mesh = mg.config_large_3d()["mesh"]
+    dev = torch.device("cuda:0")
+    q = torch.from_numpy(mesh.q).to(dev)
+    plan = femasm.Plan(torch.from_numpy(mesh.me).to(dev), mesh.nq)
+    s = stream.cuda_stream
+    keep = []
+    if name == "nodal":
+        _, nnz = plan.query("ELAS")
+        lam = torch.from_numpy(mg.lognormal_field(plan.nq, 82)).to(dev)
+        mu = torch.from_numpy(0.5 * mg.lognormal_field(plan.nq, 83)).to(dev)
+        out = torch.empty(nnz, dtype=torch.float64, device=dev)
+        keep += [lam, mu, out]
+        fn = lambda: femasm.fem_assemble_elasticity_nodal(plan.handle, q.data_ptr(), lam.data_ptr(),
+                                                         mu.data_ptr(), out.data_ptr(), s)
+        units = plan.nme
+    elif name == "general":
+        _, nnz = plan.query("STIFF")
+        out = torch.empty(nnz, dtype=torch.float64, device=dev)
+        keep.append(out)
+        coef = [2.0, 0.3, -0.1, 0.2, 1.5, 0.4, -0.2, 0.1, 1.0, 0.5, -0.4, 0.3, 0.2, 0.6, -0.7, 0.8]
+        fn = lambda: femasm.fem_assemble_general(plan.handle, q.data_ptr(), coef, out.data_ptr(), s)
+        units = plan.nme
+    elif name in ("jvp", "vjp", "vjp_ws"):
+        _, nnz = plan.query("STIFF")
+        gen = torch.Generator(device=dev).manual_seed(171)
+        G = torch.randn(nnz, dtype=torch.float64, device=dev, generator=gen)
+        dq = torch.randn(q.shape, dtype=torch.float64, device=dev, generator=gen)
+        slot = plan.slot_map()
+        dA = torch.empty(nnz, dtype=torch.float64, device=dev)
+        gq = torch.empty_like(q)
+        wbytes = femasm.fem_vjp_work_bytes(plan.handle, 2)
+        work = torch.empty(max(wbytes // 8, 1), dtype=torch.float64, device=dev)
+        keep += [G, dq, slot, dA, gq, work]
+        if name == "jvp":
+            fn = lambda: femasm.fem_assemble_jvp(plan.handle, 2, q.data_ptr(), None, dq.data_ptr(),
+                                                None, dA.data_ptr(), s)
+        elif name == "vjp":
+            fn = lambda: femasm.fem_assemble_vjp(plan.handle, 2, q.data_ptr(), None, G.data_ptr(),
+                                                slot.data_ptr(), gq.data_ptr(), None, s)
+        else:
+            fn = lambda: femasm.fem_assemble_vjp_ws(plan.handle, 2, q.data_ptr(), None,
+                                                   G.data_ptr(), slot.data_ptr(), work.data_ptr(),
+                                                   wbytes, gq.data_ptr(), None, s)
+        units = plan.nme
+    else:
+        facets = torch.from_numpy(mg.boundary_facets(mesh)).to(dev)
+        bplan = femasm.BoundaryPlan(facets, plan.nq)
+        wb = torch.from_numpy(mg.lognormal_field(plan.nq, 120)).to(dev)
+        vb = torch.empty(max(bplan.nnz, 1), dtype=torch.float64, device=dev)
+        keep += [facets, bplan, wb, vb]
+        fn = lambda: femasm.fem_boundary_mass(bplan.handle, q.data_ptr(), wb.data_ptr(),
+                                             vb.data_ptr(), s)
+        units = bplan.nf
+    wall, per = time_launches(fn, stream, steps, warmup)
+    plan.sync_status()
+    return {"ms": statistics.mean(per), "wall_ms_per_step": wall / steps * 1e3,
+            "units_per_s": units / (statistics.mean(per) / 1e3), "units": units}
+
+
 def extras(torch, femasm, mg, plan, q, stream, steps, mesh):
     import numpy as np
     import oracle
@@ -341,6 +406,9 @@ def main():
                     help="only run a plain device copy of known size (HBM counter calibration)")
     ap.add_argument("--pk", type=int, choices=sorted(PK_CUBES), default=None,
                     help="only time the 3D P_k mass of degree K on about 1e6 nodes")
+    ap.add_argument("--next", choices=NEXT_OPS, default=None,
+                    help="only time one operator beyond the P1 four on the 128^3 cube "
+                         "(elements/s; boundary: facets/s)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the assembly is measured on one MI355X; "
@@ -377,6 +445,18 @@ def main():
                                                  f"{PK_CUBES[args.pk]}^3 cubes x 6 Kuhn tets, "
                                                  f"jitter 0.15h", **{x: r[x] for x in ("nq", "nme", "nnz")}},
                           "pk": r}), flush=True)
+        return
+    if args.next is not None:
+        r = next_run(torch, femasm, mg, args.next, stream, args.steps, args.warmup)
+        unit = "facets/s" if args.next == "boundary" else "elements/s"
+        print(json.dumps({"metric": f"{args.next} on the 128^3 Kuhn cube (3D, FP64)",
+                          "value": r["units_per_s"], "unit": unit, "n_gpus": 1,
+                          "steps": args.steps, "warmup": args.warmup,
+                          "ms_per_step": r["wall_ms_per_step"], "kernel_ms": r["ms"],
+                          "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+                          "config": {"workload": f"{args.next}, unit cube 128^3 cubes x 6 Kuhn "
+                                                 "tets, jitter 0.15h, permuted elements"}}),
+              flush=True)
         return
     cfg = mg.config_large_3d(args.n)
     mesh = cfg["mesh"]
