@@ -8,10 +8,12 @@
 // hipGraph and replayed.  Each item runs the same row-gather tile routine as
 // the single-mesh kernel, so batched values equal per-mesh values bit for bit.
 #include <algorithm>
+#include <atomic>
 #include <memory>
 #include <numeric>
 
 #include "femasm_impl.h"
+#include "host_threads.h"
 #include "rowgather.h"
 
 namespace femasm {
@@ -205,13 +207,28 @@ static fem_status fem_batch_create_impl(int32_t nmesh, const int32_t *d, const i
     B->q_off.assign(nmesh + 1, 0);
     B->w_off.assign(nmesh + 1, 0);
     std::vector<BatchMesh> hm(nmesh);
-    for (int32_t m = 0; m < nmesh; ++m) {
-        fem_plan p = nullptr;
-        fem_status st = fem_assemble_symbolic(d[m], nq[m], nme[m], me[m], stream, &p);
-        if (st != FEM_OK) {
+    // the meshes' plans are independent: a few are built at a time (a small
+    // mesh leaves a plan build's own threads idle), each on the caller's
+    // device; the batch takes them in mesh order, so it does not depend on
+    // the workers
+    std::vector<fem_plan> plans(nmesh, nullptr);
+    std::vector<fem_status> pst(nmesh, FEM_OK);
+    int dev0 = 0;
+    (void)hipGetDevice(&dev0);
+    std::atomic<int32_t> next{0};
+    run_threads(std::min<int32_t>(8, nmesh), [&](int) {
+        (void)hipSetDevice(dev0);
+        for (int32_t m; (m = next.fetch_add(1)) < nmesh;)
+            pst[m] = fem_assemble_symbolic(d[m], nq[m], nme[m], me[m], stream, &plans[m]);
+    });
+    for (int32_t m = 0; m < nmesh; ++m)
+        if (pst[m] != FEM_OK) {
+            for (fem_plan x : plans) fem_plan_destroy(x);
             free_batch(B.get());
-            return st;
+            return pst[m];
         }
+    for (int32_t m = 0; m < nmesh; ++m) {
+        fem_plan p = plans[m];
         B->plans.push_back(p);
         B->has_d[p->d] = true;
         B->q_off[m + 1] = B->q_off[m] + int64_t(p->d) * p->nq;
