@@ -21,8 +21,11 @@
 // sums); else one thread per CSR row adds the tangent element rows of its
 // vertex into an LDS tile of the workgroup's CSR range, in ascending element
 // number (the row-gather scheme of the numeric phase), then the tile is
-// written coalesced.  VJP: kLanes lanes per vertex, each lane summing its share of
-// the vertex's incidences, partial sums combined in a fixed order.
+// written coalesced.  VJP: kVjpLanes lanes per vertex, each lane summing its
+// share of the vertex's incidences, partial sums combined in a fixed order.
+// Workspace VJP: the same terms evaluated once per element into a caller
+// buffer, then summed per vertex with the same lanes and order, so the two
+// forms agree bit for bit.
 #include <cstdlib>
 #include <cstring>
 
