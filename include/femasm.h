@@ -21,6 +21,12 @@
  * values are bitwise reproducible from run to run and A is exactly
  * symmetric.  The pattern is structural (explicit zeros are kept).
  *
+ * Around that path: elasticity with nodal Lame fields and the general
+ * second-order operator on the same plan; the adjoint of a^T (S + M_w) b and
+ * the JVP / VJP of the assembly map; batched assembly of many meshes; the
+ * P_k Lagrange mass (Appendix D) and the boundary mass of (d-1)-simplices on
+ * plans of their own (fem_pk_*, fem_boundary_*).
+ *
  * Conventions for every entry point:
  *  - All array arguments are DEVICE pointers unless marked "host".
  *  - Indices are 0-based.  Mesh arrays are row-major structure-of-arrays:
