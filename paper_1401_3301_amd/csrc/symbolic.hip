@@ -230,7 +230,15 @@ static fem_status fem_assemble_symbolic_impl(int32_t d, int64_t nq, int64_t nme,
     // ---- device plan.  The block layouts need only the pattern and the
     // incidences: they are built on another thread while this one orders the
     // elements and uploads the plan arrays (no return before the join).
-    std::unique_ptr<fem_plan_s> p(new fem_plan_s());
+    // the plan's device arrays are freed with it unless it is handed out
+    // (also when an exception unwinds through here)
+    struct PlanFree {
+        void operator()(fem_plan_s *x) const {
+            free_plan_arrays(x);
+            delete x;
+        }
+    };
+    std::unique_ptr<fem_plan_s, PlanFree> p(new fem_plan_s());
     p->d = d;
     p->nq = nq;
     p->nme = nme;
@@ -300,10 +308,7 @@ static fem_status fem_assemble_symbolic_impl(int32_t d, int64_t nq, int64_t nme,
     if (st == FEM_OK) st = upload(&p->part, std::vector<double>(size_t((int64_t(d) * nq + 255) / 256 + 1), 0.0));
     if (layouts.joinable()) layouts.join();
     if (st == FEM_OK) st = sb;
-    if (st != FEM_OK) {
-        free_plan_arrays(p.get());
-        return st;
-    }
+    if (st != FEM_OK) return st;   // p's deleter frees what was uploaded
     p->h_rp = std::move(rp);
     for (int M : {1, d}) p->launch[M] = row_launch_for(p->h_rp, nq, M, kLdsCap);
     *out = p.release();
