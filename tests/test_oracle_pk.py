@@ -5,7 +5,8 @@ in barycentric coordinates.  The checks below reach the same quantities by
 other routes: textbook P2 matrices, the partition of unity, a Lagrange basis
 obtained by inverting a Cartesian Vandermonde matrix on the reference
 simplex with exact monomial integrals, and the exact integration of
-products of polynomials of degree <= k over the unit square and cube.
+products of polynomials of degree <= k over the unit square and cube.  The
+exact rational route pins every degree k = 1..6 in 2D and 3D bit for bit.
 """
 import itertools
 import json
@@ -96,6 +97,51 @@ def test_vandermonde_route(d, k):
     np.testing.assert_allclose(C, M, rtol=0, atol=1e-11 * np.abs(C).max())
 
 
+def _exact_C(d, k):
+    """C in exact rational arithmetic by the Vandermonde route: the Lagrange
+    basis on the reference simplex from Gauss-Jordan elimination of the
+    Cartesian-monomial Vandermonde matrix at the lattice points (fractions
+    throughout), then int_ref x^m = m! / (d + |m|)! for every product.  No
+    barycentric product formula and no magic formula are involved."""
+    from fractions import Fraction as F
+
+    alpha = oracle.pk_alpha(d, k)
+    n = len(alpha)
+    pts = [[F(int(a[i + 1]), k) for i in range(d)] for a in alpha]
+    mons = [m for m in itertools.product(range(k + 1), repeat=d) if sum(m) <= k]
+    assert len(mons) == n
+    A = [[math.prod((p[i] ** m[i] for i in range(d)), start=F(1)) for m in mons]
+         + [F(int(r == j)) for j in range(n)] for r, p in enumerate(pts)]
+    for c in range(n):
+        piv = next(r for r in range(c, n) if A[r][c] != 0)
+        A[c], A[piv] = A[piv], A[c]
+        inv = 1 / A[c][c]
+        A[c] = [x * inv for x in A[c]]
+        for r in range(n):
+            if r != c and A[r][c] != 0:
+                f = A[r][c]
+                A[r] = [x - f * y for x, y in zip(A[r], A[c])]
+    coef = [row[n:] for row in A]                         # phi_j = sum_m coef[m][j] x^m
+
+    def integ(m):
+        return F(math.prod(math.factorial(x) for x in m), math.factorial(d + sum(m)))
+
+    Q = [[integ(tuple(a + b for a, b in zip(m1, m2))) for m2 in mons] for m1 in mons]
+    QC = [[sum(Q[i][l] * coef[l][j] for l in range(n)) for j in range(n)] for i in range(n)]
+    return [[sum(coef[l][a] * QC[l][b] for l in range(n)) for b in range(n)] for a in range(n)]
+
+
+@pytest.mark.parametrize("d,k", [(d, k) for d in (2, 3) for k in range(1, 7)])
+def test_exact_rational_route(d, k):
+    """Every degree of Table D.1, 2D and 3D: the oracle's C (exact integers
+    over the common denominator, rounded once) equals the exactly computed
+    rational C of an independent route, rounded to the nearest double, bit
+    for bit."""
+    C = oracle.pk_coeff(d, k)
+    M = np.array([[float(x) for x in row] for row in _exact_C(d, k)])
+    assert np.array_equal(C, M), np.abs(C - M).max()
+
+
 def _poly_integral_unit(d, c1, c2):
     """int over [0,1]^d of u v for u = sum c1[m] x^m, v = sum c2[m] x^m."""
     tot = 0.0
@@ -117,8 +163,9 @@ def _eval(c, q):
     return out
 
 
-@pytest.mark.parametrize("d,k,n", [(2, 1, 5), (2, 2, 4), (2, 3, 3), (2, 4, 2), (2, 6, 2),
-                                   (3, 1, 3), (3, 2, 2), (3, 3, 2), (3, 4, 1)])
+@pytest.mark.parametrize("d,k,n", [(2, 1, 5), (2, 2, 4), (2, 3, 3), (2, 4, 2), (2, 5, 2),
+                                   (2, 6, 2), (3, 1, 3), (3, 2, 2), (3, 3, 2), (3, 4, 1),
+                                   (3, 5, 1), (3, 6, 1)])
 def test_exact_integration_of_polynomials(d, k, n):
     """P_k reproduces polynomials of degree <= k, so with U, V their nodal
     values U^T M V = int_Omega u v exactly; on the (jittered-inside) unit
