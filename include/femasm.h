@@ -249,6 +249,21 @@ fem_status fem_assemble_vjp_ws(fem_plan plan, int32_t op, const double *q, const
                                int64_t work_bytes, double *dLdq, double *dLdw,
                                hipStream_t stream);
 
+/* The workspace VJP without a caller workspace, for callers that cannot
+ * allocate device memory (code under graph capture, serving loops, harnesses
+ * that forbid hipMalloc).  The element terms go to a fixed library array of
+ * 128 MiB per GPU (one copy per device, held until the process ends), so the
+ * call allocates nothing.  Arguments, outputs and results as
+ * fem_assemble_vjp_ws (bit for bit: same kernels, same order).
+ * Errors: as fem_assemble_vjp_ws; FEM_ERR_OVERFLOW when the plan's element
+ * terms (fem_vjp_work_bytes) exceed 128 MiB.  Every call on one GPU shares
+ * that array: calls that overlap on one GPU (any plan, any stream) race and
+ * must be serialised by the caller.  Nothing in the array needs clearing:
+ * each call writes every term it reads. */
+fem_status fem_assemble_vjp_noalloc(fem_plan plan, int32_t op, const double *q, const double *w,
+                                    const double *G, const int32_t *slot, double *dLdq,
+                                    double *dLdw, hipStream_t stream);
+
 /* J = a^T A b for CSR values of operator `op` produced with this plan:
  * out (device, 1 double).  Row partial sums are combined in row order, so
  * the result is bitwise reproducible.  Asynchronous.  The partial sums live

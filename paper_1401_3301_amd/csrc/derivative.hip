@@ -28,6 +28,7 @@
 // forms agree bit for bit.
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 
 #include "element.h"
 #include "femasm_impl.h"
@@ -576,6 +577,38 @@ hipError_t launch_vjp_ws(const fem_plan_s *p, int op, const MeshView &mv, const 
 
 bool deriv_op(int32_t op) { return op == FEM_OP_MASS || op == FEM_OP_MASS_W || op == FEM_OP_STIFF; }
 
+// Element-term buffer of fem_assemble_vjp_noalloc: a fixed device array, one
+// copy per GPU the library runs on (each GPU holds it until the process
+// ends).  128 MiB: 3D meshes of up to 1,048,576 elements for the weighted
+// mass (128 B of terms per element), 1,398,101 for the mass and stiffness.
+constexpr int64_t kVjpScratchBytes = int64_t(128) << 20;
+__device__ __align__(256) double scratch[kVjpScratchBytes / sizeof(double)];
+
+// Device address of `scratch` on each device, looked up once per device with
+// that device current (host code never passes the array's own name: on the
+// host it is a stand-in, not a device address).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_address(int dev, double **out) {
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur != dev) (void)hipSetDevice(cur);
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<double *>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
 // bytes of the element-term work array of the workspace VJP
 int64_t vjp_work_bytes(const fem_plan_s *p, int32_t op) {
     const int64_t nw = p->d + (op == FEM_OP_MASS_W ? 1 : 0);
@@ -638,6 +671,27 @@ extern "C" fem_status fem_assemble_vjp_ws(fem_plan plan, int32_t op, const doubl
     if (plan->nme > 0 && (!work || work_bytes < vjp_work_bytes(plan, op) ||
                           (reinterpret_cast<uintptr_t>(work) & 7u) != 0))
         return FEM_ERR_ARG;
+    if (op != FEM_OP_MASS_W) dLdw = nullptr;
+    const MeshView mv = deriv_view(plan, q, w, nullptr);
+    const hipError_t e =
+        plan->d == 2 ? launch_vjp_ws<2>(plan, op, mv, slot, G, work, dLdq, dLdw, stream)
+                     : launch_vjp_ws<3>(plan, op, mv, slot, G, work, dLdq, dLdw, stream);
+    return hip_status(e);
+}
+
+extern "C" fem_status fem_assemble_vjp_noalloc(fem_plan plan, int32_t op, const double *q,
+                                               const double *w, const double *G,
+                                               const int32_t *slot, double *dLdq, double *dLdw,
+                                               hipStream_t stream) {
+    if (!plan || !deriv_op(op)) return FEM_ERR_ARG;
+    if (plan->nq == 0) return FEM_OK;
+    if (!q || (plan->nnz > 0 && (!G || !slot)) || (op == FEM_OP_MASS_W && !w)) return FEM_ERR_ARG;
+    if (vjp_work_bytes(plan, op) > kVjpScratchBytes) return FEM_ERR_OVERFLOW;
+    double *work = nullptr;
+    if (plan->nme > 0) {
+        const hipError_t e = scratch_address(plan->device, &work);
+        if (e != hipSuccess) return hip_status(e);
+    }
     if (op != FEM_OP_MASS_W) dLdw = nullptr;
     const MeshView mv = deriv_view(plan, q, w, nullptr);
     const hipError_t e =

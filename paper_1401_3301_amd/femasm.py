@@ -55,6 +55,7 @@ _SIGS = {
     "fem_assemble_vjp": ([P, I32, P, P, P, P, P, P, P], C.c_int),
     "fem_vjp_work_bytes": ([P, I32, C.POINTER(I64)], C.c_int),
     "fem_assemble_vjp_ws": ([P, I32, P, P, P, P, P, I64, P, P, P], C.c_int),
+    "fem_assemble_vjp_noalloc": ([P, I32, P, P, P, P, P, P, P], C.c_int),
     "fem_assemble_backward": ([P, U32, P, P, P, P, P, P, P], C.c_int),
     "fem_csr_bilinear": ([P, I32, P, P, P, P, P], C.c_int),
     "fem_plan_sync_status": ([P, P], C.c_int),
@@ -181,6 +182,12 @@ def fem_assemble_vjp(plan: int, op: int, q: int, w: int | None, G: int, slot: in
                      dLdq: int | None, dLdw: int | None, stream=None):
     _check(load_library().fem_assemble_vjp(plan, op, q, w, G, slot, dLdq, dLdw, _stream(stream)),
            "fem_assemble_vjp")
+
+
+def fem_assemble_vjp_noalloc(plan: int, op: int, q: int, w: int | None, G: int, slot: int,
+                             dLdq: int, dLdw: int | None, stream=None):
+    _check(load_library().fem_assemble_vjp_noalloc(plan, op, q, w, G, slot, dLdq, dLdw,
+                                                   _stream(stream)), "fem_assemble_vjp_noalloc")
 
 
 def fem_vjp_work_bytes(plan: int, op: int) -> int:
