@@ -82,21 +82,37 @@ const char *fem_status_str(fem_status s);
  * `sparse` pattern).  Validates me, builds the CSR pattern of the scalar
  * operator (row i holds every vertex that shares an element with i, i
  * included), the element-to-CSR slot addressing used by the numeric phase,
- * and a locality-ordered copy of the connectivity.  The plan depends only on
- * me: one plan serves every q, w, lambda, mu and operator.
+ * and a locality-ordered copy of the connectivity, all with GPU kernels on
+ * `stream`.  The plan depends only on me: one plan serves every q, w,
+ * lambda, mu and operator.
  *   d      2 or 3
  *   nq     number of vertices (>= 0); vertices no element uses get empty rows
  *   nme    number of elements (>= 0)
- *   me     device, (d+1)*nme int32, layout above (may be NULL when nme == 0)
+ *   me     device, (d+1)*nme int32, layout above (may be NULL when nme == 0);
+ *          not read after the call returns
  *   stream work is ordered on it; the call is synchronous (it returns once
- *          the plan is complete)
+ *          the pattern and slot addressing are complete)
  *   out    receives the plan (host pointer to a handle)
+ * The vertex-block layouts of the block kernels are then built by a library
+ * host thread and published when complete (fem_plan_layouts); numeric calls
+ * made before that run the row-gather kernel, whose values are the same bit
+ * for bit (FEMASM_LAYOUTS=sync in the environment builds them before
+ * returning).
  * Errors: FEM_ERR_ARG, FEM_ERR_INDEX (index out of range, repeated vertex),
- * FEM_ERR_OVERFLOW (nnz >= 2^31, a row with more than 255 entries, or
- * (d+1)*nme >= 2^31), FEM_ERR_NOMEM, FEM_ERR_DEVICE.
+ * FEM_ERR_OVERFLOW (nnz >= 2^31, (d+1)*nme >= 2^31, or a vertex in more
+ * than 16384/(d+1) elements), FEM_ERR_NOMEM, FEM_ERR_DEVICE.
  */
 fem_status fem_assemble_symbolic(int32_t d, int64_t nq, int64_t nme, const int32_t *me,
                                  hipStream_t stream, fem_plan *out);
+
+/* State of the plan's vertex-block layouts: *state = 0 while the library's
+ * host thread is still building them, 1 once they are published (the block
+ * kernels serve the numeric calls), 2 when the build has finished without
+ * them (the row-gather kernel serves every call).  With wait != 0 the call
+ * blocks until the build has finished.  Returns FEM_OK, or the error that
+ * ended a failed build (FEM_ERR_NOMEM, FEM_ERR_DEVICE; the plan stays usable
+ * with the row-gather kernel).  state: host pointer, may be NULL. */
+fem_status fem_plan_layouts(fem_plan plan, int32_t wait, int32_t *state);
 
 /* Matrix sizes of operator `op` for this plan: nrows (nq, or d*nq for
  * FEM_OP_ELAS) and nnz (scalar nnz, or d*d times it).  Host out-pointers. */

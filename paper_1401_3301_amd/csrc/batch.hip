@@ -219,7 +219,11 @@ static fem_status fem_batch_create_impl(int32_t nmesh, const int32_t *d, const i
     run_threads(std::min<int32_t>(8, nmesh), [&](int) {
         (void)hipSetDevice(dev0);
         for (int32_t m; (m = next.fetch_add(1)) < nmesh;)
+        {
             pst[m] = fem_assemble_symbolic(d[m], nq[m], nme[m], me[m], stream, &plans[m]);
+            // the batch concatenates the meshes' block layouts
+            if (pst[m] == FEM_OK) wait_layouts(plans[m]);
+        }
     });
     for (int32_t m = 0; m < nmesh; ++m)
         if (pst[m] != FEM_OK) {

@@ -263,7 +263,7 @@ static fem_status up(T **dst, const std::vector<T> &src) {
     *dst = nullptr;
     hipError_t e = hipMalloc(reinterpret_cast<void **>(dst), sizeof(T) * std::max<size_t>(1, src.size()));
     if (e == hipSuccess && !src.empty())
-        e = hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
+        e = copy_sync(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
     return hip_status(e);
 }
 
@@ -433,7 +433,7 @@ static hipError_t launch_block_t(const fem_plan_data *p, const double *q, const 
 
 bool launch_block(const fem_plan_data *p, int op, const double *q, const double *w,
                   double *values, hipStream_t s, hipError_t *err) {
-    if (!p->blk.ok || op == FEM_OP_ELAS) return false;
+    if (!layouts_ready(p) || !p->blk.ok || op == FEM_OP_ELAS) return false;
     hipError_t e;
     if (p->d == 2) {
         switch (op) {

@@ -67,7 +67,7 @@ __global__ void __launch_bounds__(256) k_jvp(MeshView mv, const double *__restri
         const int64_t nq = mv.nq;
         for (int t = mv.inc_ptr[i]; t < mv.inc_ptr[i + 1]; ++t) {
             const uint32_t ea = mv.inc_elem[t];
-            const uint32_t off = mv.inc_off[t];
+            const uint64_t off = mv.inc_off[t];
             const int64_t e = ea & 0x3fffffffu;
             const int al = int(ea >> 30);
             int v[NL];
@@ -128,14 +128,14 @@ __global__ void __launch_bounds__(256) k_jvp(MeshView mv, const double *__restri
                     for (int x = 0; x < D; ++x) Ngb[x] = cdot<D>(N[x], g[b]);
                     const double de =
                         vol * ((tr * cdot<D>(ga, g[b]) - cdot<D>(Nga, g[b])) - cdot<D>(ga, Ngb));
-                    const int pos = (off >> (8 * b)) & 255u;
+                    const int pos = int((off >> (16 * b)) & 0xffffu);
                     my[pos] += de;
                 }
             } else if constexpr (OP == FEM_OP_MASS) {
                 const double k = ad / Fact<D>::mass_den;
 #pragma unroll
                 for (int b = 0; b < NL; ++b) {
-                    const int pos = (off >> (8 * b)) & 255u;
+                    const int pos = int((off >> (16 * b)) & 0xffffu);
                     my[pos] += ((b == al) ? 2.0 * k : k) * tr;
                 }
             } else {
@@ -156,7 +156,7 @@ __global__ void __launch_bounds__(256) k_jvp(MeshView mv, const double *__restri
 #pragma unroll
                 for (int b = 0; b < NL; ++b) {
                     const double f = (b == al) ? 2.0 * k : k;
-                    const int pos = (off >> (8 * b)) & 255u;
+                    const int pos = int((off >> (16 * b)) & 0xffffu);
                     my[pos] += f * ((ws + (wa + wl[b])) * tr + (dws + (dwa + dwl[b])));
                 }
             }
@@ -629,6 +629,9 @@ extern "C" fem_status fem_assemble_jvp(fem_plan plan, int32_t op, const double *
     // the vertex-pair kernel (FEMASM_KERNEL=rowgather forces the row-gather one)
     const char *sel = getenv("FEMASM_KERNEL");
     if (!sel || strcmp(sel, "rowgather") != 0) {
+        // the two JVP routes round differently: always the pair kernel when
+        // the mesh has its layout
+        wait_layouts(plan);
         const int jop = op == FEM_OP_MASS ? kOpJvpMass : op == FEM_OP_MASS_W ? kOpJvpMassW
                                                                             : kOpJvpStiff;
         hipError_t e = hipSuccess;

@@ -3,7 +3,11 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+#include <condition_variable>
 #include <cstdint>
+#include <mutex>
+#include <thread>
 #include <vector>
 
 #include "../../include/femasm.h"
@@ -96,15 +100,53 @@ struct fem_plan_data {
     int32_t *porig = nullptr;     // [nme] plan element -> caller element number
     int32_t *inc_ptr = nullptr;   // [nq+1] vertex -> incidence range
     uint32_t *inc_elem = nullptr; // [(d+1)*nme] plan element | (local vertex << 30)
-    uint32_t *inc_off = nullptr;  // [(d+1)*nme] byte b = position of local vertex b in the row
-    int32_t *status = nullptr;    // [1] sticky error word
+    uint64_t *inc_off = nullptr;  // [(d+1)*nme] bits 16b..16b+15: position of local vertex b in the row
+    int32_t *status = nullptr;    // [2] sticky error word, then a scratch word of the symbolic phase
     double *part = nullptr;       // [d*nq/256 + 1] row-block partial sums of fem_csr_bilinear
     std::vector<int32_t> h_rp;    // host copy of rp (launch geometry)
     RowLaunch launch[4];          // indexed by M
     BlockPlan blk;                // block-kernel layout (scalar operators)
     PairPlan pscal;               // pair-kernel layout, scalar operators
     PairPlan pvec;                // pair-kernel layout, elasticity
+    // The block layouts above are built on a host thread after the symbolic
+    // call returns (kLayout* states); until they are published the numeric
+    // calls take the row-gather kernel, which produces the same bits.
+    std::atomic<int> layout_state{0};
+    fem_status layout_status = FEM_OK;   // of the build (FEM_OK unless it failed)
+    std::mutex layout_mu;
+    std::condition_variable layout_cv;
+    std::thread layout_thread;
 };
+constexpr int kLayoutBuilding = 0;   // the host thread is still building
+constexpr int kLayoutReady = 1;      // published: the block kernels may run
+constexpr int kLayoutNone = 2;       // finished; no layout (row-gather only)
+
+// Synchronous copies of the layout builders on a stream of their own that
+// does not synchronise with the null stream (the layout thread runs while
+// the caller's work proceeds).
+inline hipError_t copy_sync(void *dst, const void *src, size_t bytes, hipMemcpyKind kind) {
+    hipStream_t st = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(dst, src, bytes, kind, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    const hipError_t e2 = hipStreamDestroy(st);
+    return e != hipSuccess ? e : e2;
+}
+
+// True when the block layouts are published (acquire: their arrays are
+// complete and visible).
+inline bool layouts_ready(const fem_plan_data *p) {
+    return p->layout_state.load(std::memory_order_acquire) == kLayoutReady;
+}
+// Blocks until the layout build has finished (ready or none).
+void wait_layouts(fem_plan_data *p);
+
+// CSR pattern, incidences and element order on the GPU (pattern.hip).
+// Allocates and fills rp, ci, pme, porig, inc_ptr, inc_elem, inc_off,
+// status and part of p (freed with the plan), sets nnz, max_row and h_rp.
+// Synchronous on stream s.
+fem_status build_pattern_gpu(fem_plan_data *p, const int32_t *me, hipStream_t s);
 
 }  // namespace femasm
 
@@ -155,7 +197,7 @@ struct MeshView {
     const int32_t *rp;
     const int32_t *inc_ptr;
     const uint32_t *inc_elem;
-    const uint32_t *inc_off;
+    const uint64_t *inc_off;
     const int32_t *pme;
     const double *q;
     const double *w;
@@ -174,7 +216,7 @@ struct BatchMesh {
     const int32_t *rp;
     const int32_t *inc_ptr;
     const uint32_t *inc_elem;
-    const uint32_t *inc_off;
+    const uint64_t *inc_off;
     const int32_t *pme;
     int64_t nq;
     int64_t q_off;

@@ -61,7 +61,7 @@ __global__ void k_pattern_vec(const int32_t *__restrict__ rp, const int32_t *__r
 // slot[k*(d+1)^2 + b*(d+1) + a] = CSR position of (me[a,k], me[b,k]).
 __global__ void k_slot_map(const int32_t *__restrict__ rp, const int32_t *__restrict__ inc_ptr,
                            const uint32_t *__restrict__ inc_elem,
-                           const uint32_t *__restrict__ inc_off,
+                           const uint64_t *__restrict__ inc_off,
                            const int32_t *__restrict__ porig, int64_t nq, int NL,
                            int32_t *__restrict__ slot) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -71,7 +71,7 @@ __global__ void k_slot_map(const int32_t *__restrict__ rp, const int32_t *__rest
         const int64_t k = porig[ea & 0x3fffffffu];
         const int a = int(ea >> 30);
         for (int b = 0; b < NL; ++b) {
-            const int pos = (inc_off[t] >> (8 * b)) & 255u;
+            const int pos = int((inc_off[t] >> (16 * b)) & 0xffffu);
             slot[k * NL * NL + int64_t(b) * NL + a] = rp[i] + pos;
         }
     }
@@ -189,6 +189,7 @@ extern "C" fem_status fem_assemble_elasticity_nodal(fem_plan plan, const double 
     if (nnz >= (int64_t(1) << 31)) return FEM_ERR_OVERFLOW;
     if (nnz > 0 && (!q || !lam || !mu || !values)) return FEM_ERR_ARG;
     if (nnz == 0) return FEM_OK;
+    wait_layouts(plan);   // these operators run on the block layouts only
     hipError_t e = hipSuccess;
     if (launch_pair(plan, kOpElasNodal, q, lam, 0.0, 0.0, values, stream, &e, mu))
         return hip_status(e);
@@ -203,6 +204,7 @@ extern "C" fem_status fem_assemble_general(fem_plan plan, const double *q, const
     const int d = plan->d;
     double gco[kGeneralCoef] = {};
     for (int i = 0; i < d * d + 2 * d + 1; ++i) gco[i] = coef[i];
+    wait_layouts(plan);   // these operators run on the block layouts only
     hipError_t e = hipSuccess;
     if (launch_pair(plan, kOpGeneral, q, nullptr, 0.0, 0.0, values, stream, &e, nullptr, gco))
         return hip_status(e);

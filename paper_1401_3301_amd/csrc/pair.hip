@@ -639,7 +639,7 @@ fem_status up(T **dst, const std::vector<T> &src) {
     *dst = nullptr;
     hipError_t e = hipMalloc(reinterpret_cast<void **>(dst), sizeof(T) * std::max<size_t>(1, src.size()));
     if (e == hipSuccess && !src.empty())
-        e = hipMemcpy(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
+        e = copy_sync(*dst, src.data(), sizeof(T) * src.size(), hipMemcpyHostToDevice);
     return hip_status(e);
 }
 
@@ -872,6 +872,7 @@ bool launch_pair(const fem_plan_data *p, int op, const double *q, const double *
                  double mu, double *values, hipStream_t s, hipError_t *err, const double *w2,
                  const double *gco, const double *dq) {
     // the (a, b)-coded layout serves elasticity and the non-symmetric operator
+    if (!layouts_ready(p)) return false;   // still being built (or none)
     const PairPlan &P = is_elas(op) || op == kOpGeneral ? p->pvec : p->pscal;
     if (!P.ok) return false;
     const hipError_t e =

@@ -101,7 +101,7 @@ __device__ __forceinline__ void assemble_row_tile(const MeshView &mv, int64_t r0
         const int64_t nq = mv.nq;
         for (int t = t0; t < t1; ++t) {
             const uint32_t ea = mv.inc_elem[t];
-            const uint32_t off = mv.inc_off[t];
+            const uint64_t off = mv.inc_off[t];
             const int64_t e = ea & 0x3fffffffu;
             const int al = int(ea >> 30);
             int v[NL];
@@ -121,7 +121,7 @@ __device__ __forceinline__ void assemble_row_tile(const MeshView &mv, int64_t r0
                     const double k = ad / Fact<D>::mass_den;
 #pragma unroll
                     for (int b = 0; b < NL; ++b) {
-                        const int pos = (off >> (8 * b)) & 255u;
+                        const int pos = int((off >> (16 * b)) & 0xffffu);
                         my[pos] += (b == al) ? 2.0 * k : k;
                     }
                 } else {
@@ -135,7 +135,7 @@ __device__ __forceinline__ void assemble_row_tile(const MeshView &mv, int64_t r0
                     const double wa = sel<D>(wl, al);
 #pragma unroll
                     for (int b = 0; b < NL; ++b) {
-                        const int pos = (off >> (8 * b)) & 255u;
+                        const int pos = int((off >> (16 * b)) & 0xffffu);
                         const double f = (b == al) ? 2.0 * k : k;
                         my[pos] += f * (ws + (wa + wl[b]));
                     }
@@ -156,7 +156,7 @@ __device__ __forceinline__ void assemble_row_tile(const MeshView &mv, int64_t r0
                     const double inv = 1.0 / (Fact<D>::dfact * fabs(E.det));
 #pragma unroll
                     for (int b = 0; b < NL; ++b) {
-                        const int pos = (off >> (8 * b)) & 255u;
+                        const int pos = int((off >> (16 * b)) & 0xffffu);
                         my[pos] += cdot<D>(ca, E.c[b]) * inv;
                     }
                 } else {
@@ -170,7 +170,7 @@ __device__ __forceinline__ void assemble_row_tile(const MeshView &mv, int64_t r0
                     const double chal = cal * sc;
 #pragma unroll
                     for (int b = 0; b < NL; ++b) {
-                        const int pos = (off >> (8 * b)) & 255u;
+                        const int pos = int((off >> (16 * b)) & 0xffffu);
 #pragma unroll
                         for (int n = 0; n < D; ++n)
                             my[M * pos + n] = fma(chal, E.c[b][n] * sc, my[M * pos + n]);

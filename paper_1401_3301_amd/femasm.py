@@ -44,6 +44,7 @@ D = C.c_double
 _SIGS = {
     "fem_status_str": ([C.c_int], C.c_char_p),
     "fem_assemble_symbolic": ([I32, I64, I64, P, P, C.POINTER(P)], C.c_int),
+    "fem_plan_layouts": ([P, I32, C.POINTER(I32)], C.c_int),
     "fem_plan_query": ([P, I32, C.POINTER(I64), C.POINTER(I64)], C.c_int),
     "fem_plan_info": ([P, C.POINTER(I32), C.POINTER(I64), C.POINTER(I64), C.POINTER(I32)], C.c_int),
     "fem_plan_pattern": ([P, I32, P, P, P], C.c_int),
@@ -130,6 +131,13 @@ def fem_assemble_symbolic(d: int, nq: int, nme: int, me_ptr: int, stream=None) -
     _check(load_library().fem_assemble_symbolic(d, nq, nme, me_ptr, _stream(stream), C.byref(out)),
            "fem_assemble_symbolic")
     return out.value
+
+
+def fem_plan_layouts(plan: int, wait: bool = False) -> int:
+    """State of the plan's block layouts (0 building, 1 ready, 2 none)."""
+    st = I32()
+    _check(load_library().fem_plan_layouts(plan, 1 if wait else 0, C.byref(st)), "fem_plan_layouts")
+    return st.value
 
 
 def fem_plan_query(plan: int, op: int):
@@ -330,7 +338,7 @@ def _dev_f64(x, device):
 class Plan:
     """A symbolic plan for one mesh (connectivity ``me`` of shape (d+1, nme))."""
 
-    def __init__(self, me: torch.Tensor, nq: int, stream=None):
+    def __init__(self, me: torch.Tensor, nq: int, stream=None, wait_layouts: bool = True):
         load_library()
         if me.dtype != torch.int32 or not me.is_cuda or me.dim() != 2:
             raise ValueError("me must be a CUDA int32 tensor of shape (d+1, nme)")
@@ -342,6 +350,15 @@ class Plan:
         self.handle = fem_assemble_symbolic(self.d, self.nq, self.nme,
                                             self.me.data_ptr() if self.nme else 0, stream)
         self.max_row = fem_plan_info(self.handle)[3]
+        # the block layouts are built by a library thread; by default the
+        # plan is handed out once they are ready (every later call then runs
+        # the same kernel)
+        if wait_layouts:
+            fem_plan_layouts(self.handle, wait=True)
+
+    def layouts(self, wait=False):
+        """0 building, 1 ready (block kernels), 2 none (row-gather only)."""
+        return fem_plan_layouts(self.handle, wait)
 
     def __del__(self):
         h = getattr(self, "handle", None)

@@ -2,7 +2,7 @@
 has no vertex-pair layout, so the scalar operators, elasticity and the JVP
 run on the record-block / row-gather kernels (still against the oracle),
 while the pair-only operators report FEM_ERR_OVERFLOW; a row beyond 255
-entries is refused by the symbolic phase."""
+entries takes the symbolic phase's workgroup path."""
 import numpy as np
 import pytest
 
@@ -65,11 +65,17 @@ def test_long_row_uses_fallback_kernels():
     assert_parity(v, ov, oav, what="fan40 JVP")
 
 
-def test_row_beyond_255_entries_is_refused():
+def test_row_beyond_255_entries():
+    """A vertex with 300 neighbours: the symbolic phase's workgroup path builds
+    its row; values as the oracle's."""
     mesh = _fan(300)
-    with pytest.raises(femasm.FemError) as e:
-        femasm.Plan(torch.from_numpy(mesh.me).to(DEV), mesh.nq)
-    assert e.value.name == "FEM_ERR_OVERFLOW"
-    # the oracle has no such limit
-    rp, ci, v, av = oracle.assemble(mesh.q, mesh.me, "STIFF")
-    assert rp[1] - rp[0] == 301
+    plan = femasm.Plan(torch.from_numpy(mesh.me).to(DEV), mesh.nq)
+    assert plan.max_row == 301
+    q = torch.from_numpy(mesh.q).to(DEV)
+    for op in ("STIFF", "ELAS"):
+        rp, ci = (x.cpu().numpy() for x in plan.pattern(op))
+        v = plan.numeric(op, q).cpu().numpy()
+        plan.sync_status()
+        orp, oci, ov, oav = oracle.assemble(mesh.q, mesh.me, op)
+        assert np.array_equal(rp, orp) and np.array_equal(ci, oci)
+        assert_parity(v, ov, oav, what=f"fan300 {op}")
