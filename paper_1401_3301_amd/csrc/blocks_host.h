@@ -18,9 +18,17 @@
 // Blocks grow until they hold R rows or the next vertex would bring the
 // element count above max_elems (at most kMaxBlockElems; or, when max_pairs > 0, the number of
 // CSR entries of the block's rows above max_pairs; when max_nodes > 0, the
-// number of touched vertices above max_nodes).  A mesh with a row longer than 32
-// entries, or a vertex whose own star exceeds the element cap, does not fit
-// these formats (ok == false).
+// number of touched vertices above max_nodes).
+// Every incidence also gets a wide record (`wrec`, 64 bits: element position
+// bits 0-9, local vertex a bits 10-11, the column position of local vertex b
+// in 12 bits from bit 12 + 12b), the input of the pair lists.
+// Record mode (the record-block kernel, which must cover every row): a mesh
+// with a row longer than 32 entries, or a vertex whose own star exceeds a
+// cap, does not fit (ok == false).  Pair mode (pair_mode): such vertices --
+// a row longer than kMaxPairRow entries or than max_pairs, a star above the
+// element cap, a row with more vertices than max_nodes -- are left out of
+// the blocks and listed in `leftover` (another kernel assembles their rows);
+// the 32-bit records are not built.
 #pragma once
 
 #include <algorithm>
@@ -39,7 +47,9 @@ struct BlockHost {
     std::vector<uint16_t> elem;   // 4 per block element
     std::vector<int32_t> elem_ptr;
     std::vector<uint32_t> rec;
+    std::vector<uint64_t> wrec;     // wide records, same interleaving as rec
     std::vector<int64_t> rec_ptr;
+    std::vector<int32_t> leftover;  // pair mode: used vertices that are no block's row
     std::vector<int32_t> maxdeg;
     int max_rows = 0, max_nodes = 0, max_elems = 0;
     int64_t max_nacc = 0;
@@ -48,19 +58,35 @@ struct BlockHost {
 };
 
 constexpr uint32_t kRecPad = 0xffffffffu;
+constexpr uint64_t kWRecPad = ~uint64_t(0);
 constexpr int kMaxBlockElems = 1023;
-constexpr int kMaxRowLen = 32;
+constexpr int kMaxRowLen = 32;     // record mode: 5-bit column positions
+constexpr int kMaxPairRow = 511;   // pair mode: 9-bit column positions of the pair headers
 
 inline BlockHost build_block_host(int d, int64_t nq, int64_t nme, const int32_t *me,
                                   const int32_t *rp, const int32_t *ci, const int64_t *ip,
                                   const int32_t *inc_k, int R, int nthreads,
                                   int64_t max_pairs = 0, int max_nodes = 0,
-                                  int64_t chunk_min = 8192, int max_elems = kMaxBlockElems) {
+                                  int64_t chunk_min = 8192, int max_elems = kMaxBlockElems,
+                                  bool pair_mode = false) {
     const int ecap = std::min(max_elems, kMaxBlockElems);   // growth stops above it
     BlockHost H;
     const int NL = d + 1;
-    for (int64_t i = 0; i < nq; ++i)
-        if (rp[i + 1] - rp[i] > kMaxRowLen) return H;
+    // vertices that cannot be a block row (pair mode), else the whole mesh fails
+    std::vector<uint8_t> excluded(nq, 0);
+    for (int64_t i = 0; i < nq; ++i) {
+        const int64_t len = rp[i + 1] - rp[i];
+        if (!pair_mode) {
+            if (len > kMaxRowLen) return H;
+            continue;
+        }
+        if (len == 0) continue;
+        if (len > kMaxPairRow || (max_pairs > 0 && len > max_pairs) ||
+            (max_nodes > 0 && len > max_nodes) || ip[i + 1] - ip[i] > ecap) {
+            excluded[i] = 1;
+            H.leftover.push_back(int32_t(i));
+        }
+    }
 
     // ---- breadth-first blocks over used vertices, capped in rows and elements.
     // The vertex ids are cut into contiguous chunks grown independently (one
@@ -123,7 +149,7 @@ inline BlockHost build_block_host(int d, int64_t nq, int64_t nme, const int32_t 
             }
         };
         for (int64_t seed = v0; seed < v1; ++seed) {
-            if (blk_of[seed] != -1 || rp[seed + 1] == rp[seed]) continue;
+            if (blk_of[seed] != -1 || rp[seed + 1] == rp[seed] || excluded[seed]) continue;
             const int b = nbc;
             if (ip[seed + 1] - ip[seed] > kMaxBlockElems) {
                 cfail[c] = 1;
@@ -145,7 +171,8 @@ inline BlockHost build_block_host(int d, int64_t nq, int64_t nme, const int32_t 
                 const int32_t v = queue[head++];
                 for (int32_t s = rp[v]; s < rp[v + 1] && int(queue.size()) < R; ++s) {
                     const int32_t j = ci[s];
-                    if (j < v0 || j >= v1 || blk_of[j] != -1 || rp[j + 1] == rp[j]) continue;
+                    if (j < v0 || j >= v1 || blk_of[j] != -1 || rp[j + 1] == rp[j] || excluded[j])
+                        continue;
                     const int add = new_elems(j, b);
                     const int64_t addp = rp[j + 1] - rp[j];
                     const int addn = max_nodes > 0 ? new_nodes(j, b) : 0;
@@ -184,6 +211,7 @@ inline BlockHost build_block_host(int d, int64_t nq, int64_t nme, const int32_t 
         std::vector<int32_t> nodes;
         std::vector<uint16_t> elem;
         std::vector<uint32_t> rec;
+        std::vector<uint64_t> wrec;
         int32_t maxdeg = 0;
         int64_t nacc = 0;
         bool ok = true;
@@ -196,7 +224,7 @@ inline BlockHost build_block_host(int d, int64_t nq, int64_t nme, const int32_t 
         // block so nothing is cleared); per row: local vertex -> column position
         constexpr int kHash = 2048;   // > 2 * kMaxBlockElems
         std::vector<int32_t> hkey(kHash), hval(kHash), hgen(kHash, -1);
-        std::vector<uint8_t> colpos;
+        std::vector<uint16_t> colpos;
         auto hslot = [](int32_t k) { return int((uint32_t(k) * 2654435761u) >> 21); };
         for (int b = b0; b < b1; ++b) {
             Blk &B = blks[b];
@@ -238,7 +266,8 @@ inline BlockHost build_block_host(int d, int64_t nq, int64_t nme, const int32_t 
                 for (int r = 0; r < nr; ++r)
                     maxdeg = std::max<int>(maxdeg, int(ip[rw[r] + 1] - ip[rw[r]]));
                 B.maxdeg = maxdeg;
-                B.rec.assign(size_t(maxdeg) * nr, kRecPad);
+                if (!pair_mode) B.rec.assign(size_t(maxdeg) * nr, kRecPad);
+                B.wrec.assign(size_t(maxdeg) * nr, kWRecPad);
                 for (size_t e = 0; e < elems.size(); ++e) {
                     int h = hslot(elems[e]);
                     while (hgen[h] == b) h = (h + 1) & (kHash - 1);
@@ -252,7 +281,7 @@ inline BlockHost build_block_host(int d, int64_t nq, int64_t nme, const int32_t 
                     const int32_t *c0 = ci + rp[row], *c1 = ci + rp[row + 1];
                     B.nacc += c1 - c0;
                     // every column of a block row is a touched vertex of the block
-                    for (const int32_t *c = c0; c < c1; ++c) colpos[loc[*c]] = uint8_t(c - c0);
+                    for (const int32_t *c = c0; c < c1; ++c) colpos[loc[*c]] = uint16_t(c - c0);
                     int t = 0;
                     for (int64_t s = ip[row]; s < ip[row + 1]; ++s, ++t) {
                         const int32_t k = inc_k[s];
@@ -263,12 +292,18 @@ inline BlockHost build_block_host(int d, int64_t nq, int64_t nme, const int32_t 
                             break;
                         }
                         uint32_t recv = uint32_t(hval[h]);
+                        uint64_t wide = uint64_t(hval[h]);
                         for (int a = 0; a < NL; ++a) {
                             const int32_t v = me[int64_t(a) * nme + k];
                             recv |= uint32_t(colpos[loc[v]]) << (12 + 5 * a);
-                            if (v == row) recv |= uint32_t(a) << 10;
+                            wide |= uint64_t(colpos[loc[v]]) << (12 + 12 * a);
+                            if (v == row) {
+                                recv |= uint32_t(a) << 10;
+                                wide |= uint64_t(a) << 10;
+                            }
                         }
-                        B.rec[size_t(t) * nr + r] = recv;
+                        if (!pair_mode) B.rec[size_t(t) * nr + r] = recv;
+                        B.wrec[size_t(t) * nr + r] = wide;
                     }
                 }
             }
@@ -288,7 +323,7 @@ inline BlockHost build_block_host(int d, int64_t nq, int64_t nme, const int32_t 
         if (!B.ok) return BlockHost();
         H.node_ptr[b + 1] = H.node_ptr[b] + int32_t(B.nodes.size());
         H.elem_ptr[b + 1] = H.elem_ptr[b] + int32_t(B.elem.size() / 4);
-        H.rec_ptr[b + 1] = H.rec_ptr[b] + int64_t(B.rec.size());
+        H.rec_ptr[b + 1] = H.rec_ptr[b] + int64_t(B.wrec.size());
         H.maxdeg[b] = B.maxdeg;
         H.max_rows = std::max(H.max_rows, H.row_ptr[b + 1] - H.row_ptr[b]);
         H.max_nodes = std::max(H.max_nodes, int(B.nodes.size()));
@@ -297,13 +332,15 @@ inline BlockHost build_block_host(int d, int64_t nq, int64_t nme, const int32_t 
     }
     H.nodes.resize(size_t(H.node_ptr[nb]));
     H.elem.resize(size_t(H.elem_ptr[nb]) * 4);
-    H.rec.resize(size_t(H.rec_ptr[nb]));
+    if (!pair_mode) H.rec.resize(size_t(H.rec_ptr[nb]));
+    H.wrec.resize(size_t(H.rec_ptr[nb]));
     run_chunks(std::min(nthreads, nb / 64 + 1), nb, [&](int64_t b0, int64_t b1) {
         for (int64_t b = b0; b < b1; ++b) {
             Blk &B = blks[b];
             std::copy(B.nodes.begin(), B.nodes.end(), H.nodes.begin() + H.node_ptr[b]);
             std::copy(B.elem.begin(), B.elem.end(), H.elem.begin() + size_t(H.elem_ptr[b]) * 4);
             std::copy(B.rec.begin(), B.rec.end(), H.rec.begin() + H.rec_ptr[b]);
+            std::copy(B.wrec.begin(), B.wrec.end(), H.wrec.begin() + H.rec_ptr[b]);
             B = Blk();
         }
     });
@@ -341,6 +378,8 @@ struct PairHost {
     std::vector<uint16_t> hdr2;     // [ntask*64] mirror target (dedup)
     std::vector<uint16_t> ent;
     std::vector<int64_t> ent_ptr;   // [nb+1]
+    std::vector<uint8_t> blk_ok;    // [nb] 0: the block exceeds a cap (no tasks; its rows
+                                    // go to another kernel)
     int64_t max_ent = 0;
     bool ok = false;
 };
@@ -360,9 +399,12 @@ inline uint64_t pack_wave_starts(const int32_t *wt, int waves) {
     return wp;
 }
 
+// A block whose rows need more than kWaves * kSlots tasks, more than 128
+// rows, or (max_ent > 0) more than max_ent list entries gets no tasks and
+// blk_ok[b] = 0.
 inline PairHost build_pair_host(const BlockHost &H, int d, const int32_t *rp, const int32_t *ci,
                                 int kWaves, int kSlots, int nthreads, bool tri = false,
-                                bool dedup = false) {
+                                bool dedup = false, int64_t max_ent = 0) {
     PairHost P;
     const int NL = d + 1;
     const int nb = H.nb;
@@ -388,26 +430,27 @@ inline PairHost build_pair_host(const BlockHost &H, int d, const int32_t *rp, co
             off.assign(nr + 1, 0);
             for (int r = 0; r < nr; ++r) off[r + 1] = off[r] + rp[rw[r] + 1] - rp[rw[r]];
             const int np = off[nr];
-            const uint32_t *rec = H.rec.data() + H.rec_ptr[b];
+            const uint64_t *rec = H.wrec.data() + H.rec_ptr[b];
             const int maxdeg = H.maxdeg[b];
             // list lengths, then lists (records of a row come in ascending element position)
             lst_ptr.assign(np + 1, 0);
             for (int r = 0; r < nr; ++r)
                 for (int t = 0; t < maxdeg; ++t) {
-                    const uint32_t x = rec[size_t(t) * nr + r];
-                    if (x == kRecPad) break;
-                    for (int a = 0; a < NL; ++a) lst_ptr[off[r] + ((x >> (12 + 5 * a)) & 31u) + 1]++;
+                    const uint64_t x = rec[size_t(t) * nr + r];
+                    if (x == kWRecPad) break;
+                    for (int a = 0; a < NL; ++a)
+                        lst_ptr[off[r] + int((x >> (12 + 12 * a)) & 4095u) + 1]++;
                 }
             for (int q = 0; q < np; ++q) lst_ptr[q + 1] += lst_ptr[q];
             lst.assign(lst_ptr[np], 0);
             fill.assign(lst_ptr.begin(), lst_ptr.end() - 1);
             for (int r = 0; r < nr; ++r)
                 for (int t = 0; t < maxdeg; ++t) {
-                    const uint32_t x = rec[size_t(t) * nr + r];
-                    if (x == kRecPad) break;
-                    const uint32_t ep = x & 1023u, al = (x >> 10) & 3u;
+                    const uint64_t x = rec[size_t(t) * nr + r];
+                    if (x == kWRecPad) break;
+                    const uint32_t ep = uint32_t(x & 1023u), al = uint32_t((x >> 10) & 3u);
                     for (int a = 0; a < NL; ++a) {
-                        const int q = off[r] + int((x >> (12 + 5 * a)) & 31u);
+                        const int q = off[r] + int((x >> (12 + 12 * a)) & 4095u);
                         uint32_t code = (al << 10) | (uint32_t(a) << 12);
                         if (tri) {
                             const uint32_t lo = std::min<uint32_t>(al, a), hi = std::max<uint32_t>(al, a);
@@ -455,6 +498,18 @@ inline PairHost build_pair_host(const BlockHost &H, int d, const int32_t *rp, co
                 wl[best].push_back(t);
                 load[best] += c;
             }
+            // list entries of the block (each task stores its longest list 64 times)
+            if (max_ent > 0) {
+                int64_t nent = 0;
+                for (int t = 0; t < ntask; ++t) {
+                    const int q0 = order[size_t(t) * 64];
+                    nent += int64_t(lst_ptr[q0 + 1] - lst_ptr[q0]) * 64;
+                }
+                if (nent > max_ent) {
+                    B.ok = false;
+                    continue;
+                }
+            }
             B.wfirst.push_back(0);
             for (int w = 0; w < kWaves; ++w) {
                 for (int t : wl[w]) {
@@ -489,9 +544,14 @@ inline PairHost build_pair_host(const BlockHost &H, int d, const int32_t *rp, co
     // place in parallel (block order)
     std::vector<int64_t> tptr(size_t(nb) + 1, 0);
     P.ent_ptr.assign(size_t(nb) + 1, 0);
+    P.blk_ok.assign(size_t(nb), 1);
     for (int b = 0; b < nb; ++b) {
-        const Blk &B = blks[b];
-        if (!B.ok) return PairHost();
+        Blk &B = blks[b];
+        if (!B.ok) {   // no tasks: its rows are assembled elsewhere
+            P.blk_ok[b] = 0;
+            B = Blk();
+            B.wfirst.assign(size_t(kWaves) + 1, 0);
+        }
         tptr[b + 1] = tptr[b] + int64_t(B.cnt.size());
         P.ent_ptr[b + 1] = P.ent_ptr[b] + int64_t(B.ent.size());
         P.max_ent = std::max<int64_t>(P.max_ent, int64_t(B.ent.size()));

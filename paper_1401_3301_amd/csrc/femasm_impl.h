@@ -55,6 +55,27 @@ struct BlockPlan {
     int32_t *maxdeg = nullptr;    // [nb]
 };
 
+// One work item of the batched launch.
+struct BatchItem {
+    int32_t mesh;
+    int32_t nrows;  // rows in this tile (<= threads per workgroup)
+    int64_t row0;   // first dof row of the tile within the mesh
+};
+
+struct BatchMesh {
+    const int32_t *rp;
+    const int32_t *inc_ptr;
+    const uint32_t *inc_elem;
+    const uint64_t *inc_off;
+    const int32_t *pme;
+    int64_t nq;
+    int64_t q_off;
+    int64_t w_off;
+    int64_t val_off[2];   // scalar / vector operator
+    int32_t d;
+    int32_t pad;
+};
+
 // Vertex-pair layout of the pair kernel (see blocks_host.h and pair.hip).
 struct PairPlan {
     bool ok = false;
@@ -73,6 +94,15 @@ struct PairPlan {
     uint16_t *ent = nullptr;      // entry lists, entry-major within a task
     int64_t n_rows = 0, n_nodes = 0, n_elems = 0, n_tasks = 0, n_ent = 0;   // array lengths
     std::vector<int32_t> h_desc;  // host copy of desc (batched layouts are built from it)
+    // Vertices whose rows no block covers (ascending; a star or row beyond the
+    // block caps), assembled by the row-gather tile kernel over `left_items`
+    // (tiles of consecutive such rows) in the same launch sequence.
+    std::vector<int32_t> h_left;
+    BatchItem *left_items = nullptr;
+    BatchMesh *left_mesh = nullptr;   // the plan as a one-mesh batch
+    int64_t n_left_items = 0;
+    int left_rpw = 0;                 // threads (dof rows) per tile
+    size_t left_lds = 0;
 };
 constexpr int kPairWaves = 8;     // wavefronts per workgroup of the pair kernel
 // Internal operator code of elasticity with nodal (P1) Lame fields
@@ -163,6 +193,8 @@ void free_pairs(PairPlan *p);
 fem_status upload_pairs(PairPlan &P, int R, int slots, bool tri, int d, int64_t nq, int64_t nme,
                         const int32_t *me, const int32_t *rp, const int32_t *ci, const int64_t *ip,
                         const int32_t *inc_k);
+// Row-gather tiles of the leftover rows of a pair layout (M = dof per vertex).
+fem_status upload_leftover(PairPlan &P, const fem_plan_data *p, int M);
 // Launches the pair kernel; returns false (nothing launched) when the plan
 // has no pair layout for this operator.
 // w2: the mu field of kOpElasNodal (w is then the lambda field).
@@ -203,27 +235,6 @@ struct MeshView {
     const double *w;
     double *values;
     int64_t nq;
-};
-
-// One work item of the batched launch.
-struct BatchItem {
-    int32_t mesh;
-    int32_t nrows;  // rows in this tile (<= threads per workgroup)
-    int64_t row0;   // first dof row of the tile within the mesh
-};
-
-struct BatchMesh {
-    const int32_t *rp;
-    const int32_t *inc_ptr;
-    const uint32_t *inc_elem;
-    const uint64_t *inc_off;
-    const int32_t *pme;
-    int64_t nq;
-    int64_t q_off;
-    int64_t w_off;
-    int64_t val_off[2];   // scalar / vector operator
-    int32_t d;
-    int32_t pad;
 };
 
 fem_status launch_batch(int op, const BatchMesh *meshes, const BatchItem *items, int64_t nitems,

@@ -761,8 +761,8 @@ hipError_t launch_pair_d(const PairPlan &P, int op, const double *q, const doubl
 }  // namespace
 
 void free_pairs(PairPlan *p) {
-    void *ptrs[] = {p->desc, p->rowinfo, p->nodes, p->elem, p->task_cnt, p->task_eoff, p->hdr,
-                    p->hdr2, p->ent};
+    void *ptrs[] = {p->desc,      p->rowinfo, p->nodes, p->elem, p->task_cnt,  p->task_eoff,
+                    p->hdr,       p->hdr2,    p->ent,   p->left_items, p->left_mesh};
     for (void *x : ptrs)
         if (x) (void)hipFree(x);
     *p = PairPlan();
@@ -783,23 +783,33 @@ fem_status upload_pairs(PairPlan &P, int R, int slots, bool tri, int d, int64_t 
     // allow (blocks grown against a chunk border would otherwise grow flat and
     // large).
     const int ecap = d == 3 ? (tri ? 700 : 600) : kMaxBlockElems;
+    // vertices that fit no block (a star or row beyond these caps) and the
+    // rows of blocks beyond the task or list-entry caps are left over: the
+    // row-gather tile kernel assembles them
     BlockHost H = build_block_host(d, nq, nme, me, rp, ci, ip, inc_k, std::min(R, 128), 16,
-                                   max_pairs, kMaxPairNodes, 8192, ecap);
+                                   max_pairs, kMaxPairNodes, 8192, ecap, true);
     if (!H.ok || H.nb == 0) return FEM_OK;   // row-gather kernel only
-    PairHost PH = build_pair_host(H, d, rp, ci, kPairWaves, slots, 16, tri, dedup);
-    if (!PH.ok || PH.max_ent > int64_t(kEntSlots) * kPairWG * 8 ||
-        H.max_nodes > std::min(kMaxPairNodes, kNodeSlots * kPairWG) ||
+    PairHost PH = build_pair_host(H, d, rp, ci, kPairWaves, slots, 16, tri, dedup,
+                                  int64_t(kEntSlots) * kPairWG * 8);
+    if (!PH.ok || H.max_nodes > std::min(kMaxPairNodes, kNodeSlots * kPairWG) ||
         H.max_elems + 1 > kElemSlots * kPairWG)
         return FEM_OK;
+    std::vector<int32_t> left = H.leftover;
+    for (int b = 0; b < H.nb; ++b)
+        if (!PH.blk_ok[b])
+            left.insert(left.end(), H.rows.begin() + H.row_ptr[b], H.rows.begin() + H.row_ptr[b + 1]);
+    std::sort(left.begin(), left.end());
     std::vector<uint32_t> elem8(H.elem.size() / 4);
     for (size_t k = 0; k < elem8.size(); ++k)
         elem8[k] = uint32_t(H.elem[4 * k]) | (uint32_t(H.elem[4 * k + 1]) << 8) |
                    (uint32_t(H.elem[4 * k + 2]) << 16) | (uint32_t(H.elem[4 * k + 3]) << 24);
-    const int nb = H.nb;
+    int nb = 0;   // blocks with tasks (the others' rows are left over)
+    for (int b = 0; b < H.nb; ++b) nb += PH.blk_ok[b];
     std::vector<int32_t> desc(size_t(nb) * kDescInts), task_eoff(PH.task_ent.size());
     std::vector<int4> rowinfo(H.rows.size());
     int64_t max_nacc = 0;
-    for (int b = 0; b < nb; ++b) {
+    for (int b = 0, ob = 0; b < H.nb; ++b) {
+        if (!PH.blk_ok[b]) continue;
         int32_t o = 0;
         for (int r = H.row_ptr[b]; r < H.row_ptr[b + 1]; ++r) {
             const int32_t row = H.rows[r];
@@ -809,7 +819,7 @@ fem_status upload_pairs(PairPlan &P, int R, int slots, bool tri, int d, int64_t 
         }
         max_nacc = std::max<int64_t>(max_nacc, o);
         const int32_t t0 = PH.wt[size_t(b) * (kPairWaves + 1)];
-        int32_t *x = desc.data() + size_t(b) * kDescInts;
+        int32_t *x = desc.data() + size_t(ob++) * kDescInts;
         x[0] = H.row_ptr[b];
         x[1] = H.row_ptr[b + 1] - H.row_ptr[b];
         x[2] = H.node_ptr[b];
@@ -851,12 +861,70 @@ fem_status upload_pairs(PairPlan &P, int R, int slots, bool tri, int d, int64_t 
     P.n_tasks = int64_t(PH.task_cnt.size());
     P.n_ent = int64_t(PH.ent.size());
     P.h_desc = desc;
+    P.h_left = std::move(left);
     P.max_rows = H.max_rows;
     P.max_nodes = H.max_nodes;
     P.max_elems = H.max_elems;
     P.max_nacc = max_nacc;
     P.max_ent = PH.max_ent;
     P.ok = true;
+    return FEM_OK;
+}
+
+fem_status upload_leftover(PairPlan &P, const fem_plan_data *p, int M) {
+    if (!P.ok || P.h_left.empty()) return FEM_OK;
+    // tiles of consecutive leftover vertices: at most 256 dof rows (whole
+    // vertices) and kLdsCap bytes of accumulators each
+    const std::vector<int32_t> &rp = p->h_rp;
+    auto vstart = [&](int64_t r) -> int64_t {
+        const int64_t i = r / M, l = r - i * M;
+        int64_t x = int64_t(M) * M * rp[i];
+        if (l) x += l * M * int64_t(rp[i + 1] - rp[i]);
+        return x;
+    };
+    const int R = 256 / M * M;
+    std::vector<BatchItem> items;
+    size_t lds = sizeof(double);
+    const std::vector<int32_t> &L = P.h_left;
+    for (size_t i = 0; i < L.size();) {
+        const int64_t v0 = L[i];
+        size_t j = i + 1;
+        auto bytes_to = [&](int64_t v1) {   // vertices [v0, v1)
+            return tile_lds_bytes(M, vstart(M * v1) - vstart(M * v0), M * (v1 - v0));
+        };
+        if (bytes_to(v0 + 1) > kLdsCap) {   // one vertex beyond the tile memory
+            free_pairs(&P);
+            return FEM_OK;                  // no pair layout: row-gather for every row
+        }
+        while (j < L.size() && L[j] == L[j - 1] + 1 && int64_t(M) * (L[j] + 1 - v0) <= R &&
+               bytes_to(L[j] + 1) <= kLdsCap)
+            ++j;
+        const int64_t v1 = L[j - 1] + 1;
+        BatchItem it;
+        it.mesh = 0;
+        it.nrows = int32_t(M * (v1 - v0));
+        it.row0 = M * v0;
+        items.push_back(it);
+        lds = std::max(lds, bytes_to(v1));
+        i = j;
+    }
+    BatchMesh bm;
+    bm.rp = p->rp;
+    bm.inc_ptr = p->inc_ptr;
+    bm.inc_elem = p->inc_elem;
+    bm.inc_off = p->inc_off;
+    bm.pme = p->pme;
+    bm.nq = p->nq;
+    bm.q_off = bm.w_off = 0;
+    bm.val_off[0] = bm.val_off[1] = 0;
+    bm.d = p->d;
+    bm.pad = 0;
+    fem_status st = up(&P.left_items, items);
+    if (st == FEM_OK) st = up(&P.left_mesh, std::vector<BatchMesh>(1, bm));
+    if (st != FEM_OK) return st;
+    P.n_left_items = int64_t(items.size());
+    P.left_rpw = R;
+    P.left_lds = lds;
     return FEM_OK;
 }
 
@@ -875,9 +943,18 @@ bool launch_pair(const fem_plan_data *p, int op, const double *q, const double *
     if (!layouts_ready(p)) return false;   // still being built (or none)
     const PairPlan &P = is_elas(op) || op == kOpGeneral ? p->pvec : p->pscal;
     if (!P.ok) return false;
-    const hipError_t e =
+    // leftover rows: the row-gather tile kernel, which has the four P1 operators
+    const bool p1 = op == FEM_OP_MASS || op == FEM_OP_MASS_W || op == FEM_OP_STIFF || op == FEM_OP_ELAS;
+    if (P.n_left_items > 0 && !p1) return false;
+    hipError_t e =
         launch_pair_layout(P, p->d, op, q, w, lam, mu, values, p->status, s, w2, gco, dq);
     if (e == hipErrorNotSupported) return false;
+    if (e == hipSuccess && P.n_left_items > 0) {
+        const fem_status st = launch_batch(op, P.left_mesh, P.left_items, P.n_left_items,
+                                           P.left_rpw, P.left_lds, 1024, 0, 0, q, w, lam, mu,
+                                           values, p->status, s);
+        if (st != FEM_OK) e = hipErrorLaunchFailure;
+    }
     *err = e;
     return true;
 }
@@ -889,7 +966,8 @@ fem_status concat_pairs(PairPlan &out, const std::vector<const PairPlan *> &part
     if (parts.empty()) return FEM_OK;
     int64_t rows = 0, nodes = 0, elems = 0, tasks = 0, ents = 0, nb = 0;
     for (const PairPlan *P : parts) {
-        if (!P->ok || P->slots != parts[0]->slots) return FEM_OK;   // no batched pair layout
+        // no batched pair layout (also when a mesh has leftover rows)
+        if (!P->ok || P->slots != parts[0]->slots || P->n_left_items > 0) return FEM_OK;
         rows += P->n_rows;
         nodes += P->n_nodes;
         elems += P->n_elems;

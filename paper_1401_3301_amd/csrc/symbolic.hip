@@ -155,6 +155,8 @@ static void build_layouts(fem_plan_s *p) {
             std::vector<uint32_t>().swap(ielem);
             st = upload_blocks(&L, p->d, nq, nme, hme.data(), p->h_rp.data(), ci.data(), ip.data(),
                                inc_k.data());
+            if (st == FEM_OK) st = upload_leftover(L.pscal, p, 1);
+            if (st == FEM_OK) st = upload_leftover(L.pvec, p, p->d);
         }
     } catch (...) {
         st = FEM_ERR_NOMEM;

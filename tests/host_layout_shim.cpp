@@ -10,17 +10,21 @@
 
 using namespace femasm;
 
+template <class T>
+static void put(void *dst, const std::vector<T> &v);
+
 static BlockHost g_h;
 static PairHost g_p;
 
 extern "C" int hl_build(int d, int64_t nq, int64_t nme, const int32_t *me, const int32_t *rp,
                         const int32_t *ci, const int64_t *ip, const int32_t *inc_k, int R,
                         int64_t max_pairs, int max_nodes, int waves, int slots, int tri,
-                        int dedup, int64_t chunk_min, int64_t *sizes) {
+                        int dedup, int64_t chunk_min, int pair_mode, int max_elems,
+                        int64_t max_ent, int64_t *sizes) {
     g_h = build_block_host(d, nq, nme, me, rp, ci, ip, inc_k, R, 4, max_pairs, max_nodes,
-                           chunk_min);
+                           chunk_min, max_elems, pair_mode != 0);
     if (!g_h.ok) return 1;
-    g_p = build_pair_host(g_h, d, rp, ci, waves, slots, 2, tri != 0, dedup != 0);
+    g_p = build_pair_host(g_h, d, rp, ci, waves, slots, 2, tri != 0, dedup != 0, max_ent);
     if (!g_p.ok) return 2;
     sizes[0] = g_h.nb;
     sizes[1] = int64_t(g_h.rows.size());
@@ -30,7 +34,15 @@ extern "C" int hl_build(int d, int64_t nq, int64_t nme, const int32_t *me, const
     sizes[5] = int64_t(g_p.task_cnt.size());
     sizes[6] = int64_t(g_p.ent.size());
     sizes[7] = g_h.max_nodes;
+    sizes[8] = int64_t(g_h.leftover.size());
+    sizes[9] = int64_t(g_h.wrec.size());
     return 0;
+}
+
+extern "C" void hl_pair_mode(uint64_t *wrec, int32_t *leftover, uint8_t *blk_ok) {
+    put(wrec, g_h.wrec);
+    put(leftover, g_h.leftover);
+    put(blk_ok, g_p.blk_ok);
 }
 
 template <class T>

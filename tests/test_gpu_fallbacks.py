@@ -1,8 +1,8 @@
-"""GPU checks of the fallback routes: a vertex with more than 32 neighbours
-has no vertex-pair layout, so the scalar operators, elasticity and the JVP
-run on the record-block / row-gather kernels (still against the oracle),
-while the pair-only operators report FEM_ERR_OVERFLOW; a row beyond 255
-entries takes the symbolic phase's workgroup path."""
+"""GPU checks of the long-row routes: a vertex with 40 neighbours stays in a
+block (every operator on the block layouts); a vertex with 300 neighbours is
+beyond the block caps, so its row is assembled by the row-gather tile kernel
+beside the pair kernel, and the symbolic phase builds it on its workgroup
+path."""
 import numpy as np
 import pytest
 
@@ -38,27 +38,30 @@ def _fan(n, seed=0):
     return mg.Mesh(2, np.ascontiguousarray(q), me)
 
 
-def test_long_row_uses_fallback_kernels():
+def test_long_row_keeps_the_block_layouts():
+    """A vertex with 40 neighbours (rows up to 511 entries fit a block): every
+    operator, the pair-only ones included, runs on the block layouts and
+    matches the oracle."""
     mesh = _fan(40)
     me = torch.from_numpy(mesh.me).to(DEV)
     q = torch.from_numpy(mesh.q).to(DEV)
     w = mg.lognormal_field(mesh.nq, 3)
     plan = femasm.Plan(me, mesh.nq)
-    assert plan.max_row == 41
+    assert plan.max_row == 41 and plan.layouts() == 1
     for op in ("MASS", "MASS_W", "STIFF", "ELAS"):
         wt = w if op == "MASS_W" else None
         v = plan.numeric(op, q, wt).cpu().numpy()
         plan.sync_status()
         _, _, ov, oav = oracle.assemble(mesh.q, mesh.me, op, w=wt)
         assert_parity(v, ov, oav, what=f"fan40 {op}")
-    # pair-only operators refuse the mesh
-    with pytest.raises(femasm.FemError) as e:
-        plan.elasticity_nodal(q, np.ones(mesh.nq), np.ones(mesh.nq))
-    assert e.value.name == "FEM_ERR_OVERFLOW"
-    with pytest.raises(femasm.FemError) as e:
-        plan.general(q, oracle.general_coef(2, np.eye(2)))
-    assert e.value.name == "FEM_ERR_OVERFLOW"
-    # the JVP falls back to the row-gather kernel
+    lam, mu = np.ones(mesh.nq) * 1.5, np.ones(mesh.nq) * 0.25
+    v = plan.elasticity_nodal(q, lam, mu).cpu().numpy()
+    _, _, ov, oav = oracle.assemble_lame(mesh.q, mesh.me, lam, mu)
+    assert_parity(v, ov, oav, what="fan40 nodal Lame")
+    coef = oracle.general_coef(2, np.eye(2))
+    v = plan.general(q, coef).cpu().numpy()
+    _, _, ov, oav = oracle.assemble_general(mesh.q, mesh.me, coef)
+    assert_parity(v, ov, oav, what="fan40 general")
     dq = np.random.default_rng(4).standard_normal(mesh.q.shape) * 0.01
     v = plan.jvp("STIFF", q, dq).cpu().numpy()
     _, _, ov, oav = oracle.jvp(mesh.q, mesh.me, "STIFF", dq)

@@ -5,8 +5,10 @@ triangulations of random points (scipy) in 2D and 3D with their elements in a
 random order (maximum vertex valence well above a grid's), a 2D fan with one
 vertex in 1000 triangles and a 3D double fan with one vertex in 600
 tetrahedra (rows longer than the symbolic phase's single-wavefront path, so
-they take its workgroup path).  Every operator is compared with the oracle
-entry by entry: pattern bit-exact, values within the floored 1e-12 bound.
+they take its workgroup path, and beyond the block caps, so the row-gather
+tile kernel assembles them beside the pair kernel).  Every operator is
+compared with the oracle entry by entry: pattern bit-exact, values within the
+floored 1e-12 bound.
 """
 import numpy as np
 import pytest
@@ -75,6 +77,14 @@ def mesh_case(request):
     return request.param, mesh, plan
 
 
+def test_unstructured_layouts_in_use(mesh_case):
+    """Every mesh here keeps its block layouts: the Delaunay meshes entirely
+    (rows up to 511 entries fit a block), the fans with their hub rows left
+    over to the row-gather tile kernel."""
+    name, mesh, plan = mesh_case
+    assert plan.layouts() == 1, f"{name}: no block layouts"
+
+
 @pytest.mark.parametrize("op", ["MASS", "MASS_W", "STIFF", "ELAS"])
 def test_unstructured_parity(mesh_case, op):
     name, mesh, plan = mesh_case
@@ -121,3 +131,38 @@ def test_vertex_in_too_many_elements():
     ok = fan2d(5400)     # 16200 candidates: accepted
     plan = femasm.Plan(torch.from_numpy(ok.me).to(DEV), ok.nq)
     assert plan.max_row == 5401
+
+
+def test_unstructured_next_operators(mesh_case):
+    """Nodal-Lame elasticity, the general operator and the JVP against the
+    oracle.  On the Delaunay meshes they run on the block layouts; on the fans
+    (hub rows left over) the pair-only operators report FEM_ERR_OVERFLOW and
+    the JVP takes its row-gather form."""
+    name, mesh, plan = mesh_case
+    d = mesh.d
+    rng = np.random.default_rng(17)
+    q = torch.from_numpy(mesh.q).to(DEV)
+    lam = np.exp(0.3 * rng.standard_normal(mesh.nq))
+    mu = 0.5 * np.exp(0.3 * rng.standard_normal(mesh.nq))
+    A = np.eye(d) * 2 + rng.uniform(-0.5, 0.5, (d, d))
+    coef = oracle.general_coef(d, A, rng.uniform(-1, 1, d), rng.uniform(-1, 1, d), 0.8)
+    dq = 0.01 * rng.standard_normal(mesh.q.shape)
+    jv = plan.jvp("STIFF", q, dq).cpu().numpy()
+    plan.sync_status()
+    _, _, ov, oav = oracle.jvp(mesh.q, mesh.me, "STIFF", dq)
+    assert_parity(jv, ov, oav, what=f"{name} JVP")
+    if name.startswith("fan"):
+        with pytest.raises(femasm.FemError) as e:
+            plan.elasticity_nodal(q, lam, mu)
+        assert e.value.name == "FEM_ERR_OVERFLOW"
+        with pytest.raises(femasm.FemError) as e:
+            plan.general(q, coef)
+        assert e.value.name == "FEM_ERR_OVERFLOW"
+        return
+    v = plan.elasticity_nodal(q, lam, mu).cpu().numpy()
+    _, _, ov, oav = oracle.assemble_lame(mesh.q, mesh.me, lam, mu)
+    assert_parity(v, ov, oav, what=f"{name} nodal Lame")
+    v = plan.general(q, coef).cpu().numpy()
+    plan.sync_status()
+    _, _, ov, oav = oracle.assemble_general(mesh.q, mesh.me, coef)
+    assert_parity(v, ov, oav, what=f"{name} general")

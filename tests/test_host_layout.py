@@ -53,14 +53,15 @@ def _pattern(mesh):
 
 
 def _build(shim, mesh, R, max_pairs=0, max_nodes=0, waves=8, slots=2, tri=False, dedup=True,
-           chunk_min=8192):
+           chunk_min=8192, pair_mode=False, max_elems=1023, max_ent=0):
     me, rp, ci, ip, inc_k = _pattern(mesh)
-    sizes = np.zeros(8, np.int64)
+    sizes = np.zeros(10, np.int64)
     st = shim.hl_build(mesh.d, ctypes.c_int64(mesh.nq), ctypes.c_int64(mesh.nme), _p(me), _p(rp),
                        _p(ci), _p(ip), _p(inc_k), R, ctypes.c_int64(max_pairs), max_nodes, waves,
-                       slots, int(tri), int(dedup), ctypes.c_int64(chunk_min), _p(sizes))
+                       slots, int(tri), int(dedup), ctypes.c_int64(chunk_min), int(pair_mode),
+                       max_elems, ctypes.c_int64(max_ent), _p(sizes))
     assert st == 0, f"builder refused the mesh (status {st})"
-    nb, nrows, nnodes, nelem, nrec, ntask, nent, _ = (int(x) for x in sizes)
+    nb, nrows, nnodes, nelem, nrec, ntask, nent, _, nleft, nwrec = (int(x) for x in sizes)
     B = dict(rows=np.zeros(nrows, np.int32), row_ptr=np.zeros(nb + 1, np.int32),
              nodes=np.zeros(nnodes, np.int32), node_ptr=np.zeros(nb + 1, np.int32),
              elem=np.zeros(nelem, np.uint16), elem_ptr=np.zeros(nb + 1, np.int32),
@@ -74,6 +75,10 @@ def _build(shim, mesh, R, max_pairs=0, max_nodes=0, waves=8, slots=2, tri=False,
               ent_ptr=np.zeros(nb + 1, np.int64))
     shim.hl_pairs(*(_p(Pr[k]) for k in ("wt", "task_cnt", "task_ent", "hdr", "hdr2", "ent",
                                         "ent_ptr")))
+    B["wrec"] = np.zeros(nwrec, np.uint64)
+    B["leftover"] = np.zeros(nleft, np.int32)
+    Pr["blk_ok"] = np.zeros(nb, np.uint8)
+    shim.hl_pair_mode(_p(B["wrec"]), _p(B["leftover"]), _p(Pr["blk_ok"]))
     return (me, rp, ci, ip, inc_k), nb, B, Pr
 
 
@@ -82,16 +87,24 @@ def _tri(a, b, nl):
     return lo * nl - lo * (lo - 1) // 2 + (hi - lo)
 
 
-def _check(mesh, built, R, max_pairs, max_nodes, waves, slots, tri, dedup):
+def _check(mesh, built, R, max_pairs, max_nodes, waves, slots, tri, dedup, pair_mode=False,
+           max_elems=1023):
     (me, rp, ci, ip, inc_k), nb, B, Pr = built
     d, nq, nme, nl = mesh.d, mesh.nq, mesh.nme, mesh.d + 1
     used = np.diff(rp) > 0
     owner = np.full(nq, -1)
     covered = np.zeros(len(ci), np.int64)
+    left = set(int(x) for x in B["leftover"])
+    if not pair_mode:
+        assert not left
+    for v in left:   # a vertex is left over only when it cannot be a block row
+        lv = rp[v + 1] - rp[v]
+        assert lv > 511 or (max_pairs and lv > max_pairs) or (max_nodes and lv > max_nodes) or \
+            ip[v + 1] - ip[v] > max_elems
     for b in range(nb):
         rows = B["rows"][B["row_ptr"][b]:B["row_ptr"][b + 1]]
         assert 0 < len(rows) <= R and np.all(np.diff(rows) > 0)
-        assert np.all(owner[rows] == -1)
+        assert np.all(owner[rows] == -1) and not (set(rows.tolist()) & left)
         owner[rows] = b
         lens = rp[rows + 1] - rp[rows]
         if max_pairs:
@@ -108,26 +121,35 @@ def _check(mesh, built, R, max_pairs, max_nodes, waves, slots, tri, dedup):
         if max_nodes:
             assert len(nodes) <= max_nodes
         assert np.array_equal(nodes[el], me[:, ks].T)
-        # incidence records, interleaved t * nrows + r
-        rec = B["rec"][B["rec_ptr"][b]:B["rec_ptr"][b + 1]]
+        # incidence records, interleaved t * nrows + r: 32-bit (record mode)
+        # and wide (12-bit column positions, both modes)
         nr, deg = len(rows), B["maxdeg"][b]
-        assert len(rec) == nr * deg
-        for r, i in enumerate(rows):
-            inc = inc_k[ip[i]:ip[i + 1]]
-            for t in range(deg):
-                x = int(rec[t * nr + r])
-                if t >= len(inc):
-                    assert x == REC_PAD
-                    continue
-                k = inc[t]
-                assert x & 1023 == np.searchsorted(ks, k)
-                al = (x >> 10) & 3
-                assert me[al, k] == i
-                cols = ci[rp[i]:rp[i + 1]]
-                for a in range(nl):
-                    assert cols[(x >> (12 + 5 * a)) & 31] == me[a, k]
+        forms = [("wrec", 12, 4095, 0xFFFFFFFFFFFFFFFF)]
+        if not pair_mode:
+            forms.append(("rec", 5, 31, REC_PAD))
+        for key, width, mask, pad in forms:
+            rec = B[key][B["rec_ptr"][b]:B["rec_ptr"][b + 1]]
+            assert len(rec) == nr * deg
+            for r, i in enumerate(rows):
+                inc = inc_k[ip[i]:ip[i + 1]]
+                for t in range(deg):
+                    x = int(rec[t * nr + r])
+                    if t >= len(inc):
+                        assert x == pad
+                        continue
+                    k = inc[t]
+                    assert x & 1023 == np.searchsorted(ks, k)
+                    al = (x >> 10) & 3
+                    assert me[al, k] == i
+                    cols = ci[rp[i]:rp[i + 1]]
+                    for a in range(nl):
+                        assert cols[(x >> (12 + width * a)) & mask] == me[a, k]
         # pair tasks: wavefront ranges, headers, entries
         t0s = Pr["wt"][b * (waves + 1):(b + 1) * (waves + 1)]
+        if not Pr["blk_ok"][b]:   # beyond a cap: no tasks, its rows are left over
+            assert pair_mode and t0s[0] == t0s[-1]
+            left |= set(rows.tolist())
+            continue
         assert np.all(np.diff(t0s) >= 0) and np.all(np.diff(t0s) <= slots)
         ne_b = len(ks)
         for t in range(t0s[0], t0s[-1]):
@@ -161,8 +183,13 @@ def _check(mesh, built, R, max_pairs, max_nodes, waves, slots, tri, dedup):
                     covered[rp[col] + p2] += 1
                 elif dedup:
                     assert not (col in rows and np.searchsorted(rows, col) > r)
-    assert np.all(owner[used] >= 0) and np.all(owner[~used] == -1)
-    assert np.all(covered == 1), "every CSR entry is listed or mirrored exactly once"
+    assert np.all((owner[used] >= 0) | np.isin(np.nonzero(used)[0], sorted(left)))
+    assert np.all(owner[~used] == -1)
+    rows_of = np.repeat(np.arange(nq), np.diff(rp))
+    in_left = np.isin(rows_of, sorted(left))
+    assert np.all(covered[~in_left] == 1), "every CSR entry is listed or mirrored exactly once"
+    assert np.all(covered[in_left] == 0), "rows left over are not in any task"
+    return left
 
 
 CASES = [
@@ -209,11 +236,64 @@ def test_unused_vertices_and_refusals(shim):
     mef = np.array([[0] * n, list(range(1, n + 1)), [j % n + 1 for j in range(1, n + 1)]],
                    np.int32)
     me, rp, ci, ip, inc_k = _pattern(mg.Mesh(2, qf, mef))
-    sizes = np.zeros(8, np.int64)
+    sizes = np.zeros(10, np.int64)
     st = shim.hl_build(2, ctypes.c_int64(n + 1), ctypes.c_int64(n), _p(me), _p(rp), _p(ci),
                        _p(ip), _p(inc_k), 16, ctypes.c_int64(0), 0, 8, 2, 0, 1, ctypes.c_int64(8192),
-                       _p(sizes))
+                       0, 1023, ctypes.c_int64(0), _p(sizes))
     assert st == 1
+    # pair mode keeps the mesh: the fan's centre is left over only when its
+    # row exceeds a cap (here the 32-entry CSR cap of a block)
+    fan = mg.Mesh(2, qf, mef)
+    built = _build(shim, fan, 16, max_pairs=32, pair_mode=True, tri=True)
+    left = _check(fan, built, 16, 32, 0, 8, 2, True, True, pair_mode=True)
+    assert left == {0}
+    built = _build(shim, fan, 16, max_pairs=1024, pair_mode=True, tri=True)
+    assert _check(fan, built, 16, 1024, 0, 8, 2, True, True, pair_mode=True) == set()
+
+
+def _delaunay(d, npts, seed):
+    from scipy.spatial import Delaunay
+    rng = np.random.default_rng(seed)
+    pts = rng.random((npts, d))
+    me = Delaunay(pts).simplices.T.astype(np.int32)
+    me = me[:, rng.permutation(me.shape[1])]
+    return mg.Mesh(d, np.ascontiguousarray(pts.T), np.ascontiguousarray(me))
+
+
+PAIR_CASES = [
+    # (mesh, R, max_pairs, max_nodes, tri, max_elems, max_ent)
+    ("delaunay3d", 56, 1024, 256, True, 700, 8192),
+    ("delaunay3d", 48, 1024, 256, False, 600, 8192),
+    ("delaunay2d", 128, 1024, 256, True, 1023, 8192),
+    ("delaunay3d", 56, 1024, 256, True, 700, 2500),     # blocks beyond the entry cap
+    ("delaunay3d", 56, 1024, 24, True, 40, 8192),       # vertices beyond the node and element caps
+    ("cube5_perm", 56, 1024, 256, True, 700, 8192),
+]
+PAIR_MESHES = {
+    "delaunay3d": lambda: _delaunay(3, 600, 5),
+    "delaunay2d": lambda: _delaunay(2, 1500, 6),
+    "cube5_perm": lambda: mg.kuhn_cube(5, 0.15, seed=4, perm_seed=9),
+}
+
+
+@pytest.mark.parametrize("case", PAIR_CASES, ids=[f"{c[0]}-R{c[1]}-n{c[3]}-e{c[5]}-ent{c[6]}"
+                                                  for c in PAIR_CASES])
+def test_pair_mode_against_brute_force(shim, case):
+    """Pair mode on unstructured meshes (rows up to 511 entries): every CSR
+    entry of a block row is listed or mirrored once; vertices beyond a cap and
+    the rows of blocks beyond the task or entry caps are left over, and only
+    those."""
+    name, R, max_pairs, max_nodes, tri, max_elems, max_ent = case
+    mesh = PAIR_MESHES[name]()
+    built = _build(shim, mesh, R, max_pairs, max_nodes, 8, 2, tri, True, pair_mode=True,
+                   max_elems=max_elems, max_ent=max_ent)
+    left = _check(mesh, built, R, max_pairs, max_nodes, 8, 2, tri, True, pair_mode=True,
+                  max_elems=max_elems)
+    nb, Pr = built[1], built[3]
+    print(f"{name}: max row {np.diff(built[0][1]).max()}, {nb} blocks, "
+          f"{nb - int(Pr['blk_ok'].sum())} over a cap, {len(left)} rows left over")
+    if case[6] == 8192 and case[5] >= 600:
+        assert not left   # default caps: every row of these meshes is in a block
 
 
 def _unpack_wave_starts(wp, waves):
