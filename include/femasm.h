@@ -323,22 +323,37 @@ fem_status fem_batch_plan(fem_batch batch, int32_t index, fem_plan *plan);
  * thread in ascending element order).  Synchronous (rebuilds the work list). */
 fem_status fem_batch_set_params(fem_batch batch, int32_t block_threads, int32_t wg_per_cu);
 
+/* Layout tunables of the vertex-pair kernel for the operators of `op`'s
+ * kind (the scalar operators share one layout, elasticity has its own):
+ * rows per vertex block for the 3D and the 2D meshes (16..128) and tasks of
+ * 64 pairs per wavefront (1, 2 or 4).  Rebuilds every mesh's layout of that
+ * kind and the concatenated layouts (synchronous, host work; not
+ * concurrently with numeric calls on the batch).  Scheduling only: the
+ * values stay the same bit for bit.  FEM_ERR_ARG for values out of range. */
+fem_status fem_batch_set_pair_layout(fem_batch batch, int32_t op, int32_t rows_3d,
+                                     int32_t rows_2d, int32_t slots);
+
 /* Kernel family of fem_batch_numeric:
  *   FEM_BATCH_PAIR (default)  the vertex-pair kernel over the concatenated
  *                             pair layouts of all meshes, one persistent
- *                             launch per dimension present
+ *                             launch over both dimensions (workgroups split
+ *                             between the 2D and the 3D blocks in proportion
+ *                             to their work; one launch per dimension if the
+ *                             two layouts' slot counts differ or their LDS
+ *                             does not fit)
+ *   FEM_BATCH_PAIR_SPLIT      the same kernel, one persistent launch per
+ *                             dimension present
  *   FEM_BATCH_ROWGATHER       one persistent launch of the row-gather kernel
  *                             over (mesh, row tile) items (fem_batch_set_params)
- * Both give the same values bit for bit; FEM_BATCH_PAIR falls back to the
+ * All give the same values bit for bit; the pair forms fall back to the
  * row-gather launch when a mesh has no pair layout.  FEM_ERR_ARG for another
  * value. */
-enum { FEM_BATCH_ROWGATHER = 0, FEM_BATCH_PAIR = 1 };
+enum { FEM_BATCH_ROWGATHER = 0, FEM_BATCH_PAIR = 1, FEM_BATCH_PAIR_SPLIT = 2 };
 fem_status fem_batch_set_kernel(fem_batch batch, int32_t kernel);
 
 /*
  * CSR values of operator `op` for every mesh of the batch: one persistent
- * launch (row-gather) or one per dimension present (pair; see
- * fem_batch_set_kernel).  q_cat, w_cat are the per-mesh arrays concatenated at q_off /
+ * launch (see fem_batch_set_kernel).  q_cat, w_cat are the per-mesh arrays concatenated at q_off /
  * w_off; values_cat receives mesh b's values at nnz_off[b].  No host
  * synchronisation, no allocation, fixed kernel arguments: safe to capture
  * in a hipGraph and replay.

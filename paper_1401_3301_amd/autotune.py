@@ -1,13 +1,16 @@
 """Autotuner for the batched assembly.
 
-Times ``fem_batch_numeric`` for each candidate -- the vertex-pair kernel, or
-the persistent row-gather kernel with a given number of threads per
-workgroup and workgroups per compute unit -- with HIP events on the current
-stream and keeps the fastest.  The candidates differ only in how the work is
-scheduled, never in the values (every CSR entry is summed in ascending
-element number with the same expressions), so any choice gives
-bitwise-identical output.  Results are cached in a JSON file keyed by GPU
-architecture, operator and a size signature of the batch.
+Times ``fem_batch_numeric`` for each candidate -- the vertex-pair kernel with
+a given layout (rows per vertex block of the 3D and of the 2D meshes, tasks
+of 64 pairs per wavefront; the layouts are rebuilt for each) in one launch
+over both dimensions or one launch per dimension, or the
+persistent row-gather kernel with a given number of threads per workgroup
+and workgroups per compute unit -- with HIP events on the current stream and
+keeps the fastest.  The candidates differ only in how the work is scheduled,
+never in the values (every CSR entry is summed in ascending element number
+with the same expressions), so any choice gives bitwise-identical output.
+Results are cached in a JSON file keyed by GPU architecture, operator and a
+size signature of the batch.
 """
 from __future__ import annotations
 
@@ -19,8 +22,20 @@ import torch
 
 from . import femasm
 
-CANDIDATES = [("pair", 256, 2)] + [("rowgather", bt, w) for bt in (64, 128, 256)
-                                   for w in (1, 2, 4, 8)]
+PAIR_ROWS_3D = {"scalar": (40, 56, 72), "elas": (32, 48, 64)}
+
+
+def candidates(op: str):
+    kind = "elas" if op == "ELAS" else "scalar"
+    layouts = [(r3, 128, s) for r3 in PAIR_ROWS_3D[kind] for s in (1, 2)]
+    layouts.append((PAIR_ROWS_3D[kind][1], 96, 2))
+    # per layout: one launch over both dimensions, or one per dimension
+    pair = [(k,) + lay for lay in layouts for k in ("pair", "pair_split")]
+    return pair + [("rowgather", bt, w) for bt, w in ((256, 1), (256, 2), (128, 4))]
+
+
+def _key(params):
+    return params[0] + ":" + "x".join(str(x) for x in params[1:])
 
 
 def default_cache_path() -> str:
@@ -65,23 +80,23 @@ def tune(batch: femasm.Batch, op: str, q_cat, w_cat=None, reps: int = 5,
             cache = json.load(open(cache_path))
         except (OSError, ValueError):
             cache = {}
-    if not force and key in cache and len(cache[key]["params"]) == 3:
+    if not force and key in cache and tuple(cache[key]["params"]) in candidates(op):
         params = tuple(cache[key]["params"])
-        batch.configure(params)
+        batch.configure(params, op)
         return params, cache[key].get("times", {})
     nnz = batch.offsets(op).nnz[-1]
     out = torch.empty(max(nnz, 1), dtype=torch.float64, device=batch.device)
     times = {}
-    for cand in CANDIDATES:
+    for cand in candidates(op):
         try:
-            batch.configure(cand)
+            batch.configure(cand, op)
         except femasm.FemError:
             continue
-        times["%s:%dx%d" % cand] = _time(batch, op, q_cat, w_cat, out, reps)
+        times[_key(cand)] = _time(batch, op, q_cat, w_cat, out, reps)
     best = min(times, key=times.get)
-    kern, rest = best.split(":")
+    kern, rest = best.split(":")   # e.g. "pair_split:56x128x2"
     params = (kern,) + tuple(int(x) for x in rest.split("x"))
-    batch.configure(params)
+    batch.configure(params, op)
     cache[key] = {"params": list(params), "times": times}
     os.makedirs(os.path.dirname(cache_path) or ".", exist_ok=True)
     tmp = cache_path + ".tmp"

@@ -115,10 +115,13 @@ static void free_batch(fem_batch_s *b) {
         for (PairPlan &P : row) free_pairs(&P);
 }
 
-// One pair layout per (scalar / elasticity, d) over all meshes of that d.
-static fem_status build_pair_layouts(fem_batch_s *B) {
+// One pair layout per (scalar / elasticity, d) over all meshes of that d
+// (vec_only >= 0: only that kind).
+static fem_status build_pair_layouts(fem_batch_s *B, int vec_only = -1) {
     for (int vec = 0; vec < 2; ++vec)
         for (int d = 2; d <= 3; ++d) {
+            if (vec_only >= 0 && vec != vec_only) continue;
+            free_pairs(&B->pairs[vec][d]);
             std::vector<const PairPlan *> parts;
             std::vector<int64_t> qo, wo, vo, nq;
             for (size_t m = 0; m < B->plans.size(); ++m) {
@@ -290,7 +293,9 @@ extern "C" fem_status fem_batch_create(int32_t nmesh, const int32_t *d, const in
 }
 
 extern "C" fem_status fem_batch_set_kernel(fem_batch batch, int32_t kernel) {
-    if (!batch || (kernel != FEM_BATCH_ROWGATHER && kernel != FEM_BATCH_PAIR)) return FEM_ERR_ARG;
+    if (!batch || (kernel != FEM_BATCH_ROWGATHER && kernel != FEM_BATCH_PAIR &&
+                   kernel != FEM_BATCH_PAIR_SPLIT))
+        return FEM_ERR_ARG;
     batch->kernel = kernel;
     return FEM_OK;
 }
@@ -330,6 +335,32 @@ extern "C" fem_status fem_batch_set_params(fem_batch batch, int32_t block_thread
     return st;
 }
 
+extern "C" fem_status fem_batch_set_pair_layout(fem_batch batch, int32_t op, int32_t rows_3d,
+                                                int32_t rows_2d, int32_t slots) {
+    if (!batch || op < FEM_OP_MASS || op > FEM_OP_ELAS || rows_3d < 16 || rows_3d > 128 ||
+        rows_2d < 16 || rows_2d > 128 || (slots != 1 && slots != 2 && slots != 4))
+        return FEM_ERR_ARG;
+    const bool vec = op == FEM_OP_ELAS;
+    std::vector<fem_status> st(batch->plans.size(), FEM_OK);
+    std::atomic<size_t> next{0};
+    int dev0 = 0;
+    (void)hipGetDevice(&dev0);
+    try {
+        run_threads(int(std::min<size_t>(8, batch->plans.size())), [&](int) {
+            (void)hipSetDevice(dev0);
+            for (size_t m; (m = next.fetch_add(1)) < batch->plans.size();) {
+                fem_plan p = batch->plans[m];
+                st[m] = rebuild_pair_layout(p, vec, p->d == 3 ? rows_3d : rows_2d, slots);
+            }
+        });
+    } catch (...) {
+        return FEM_ERR_NOMEM;
+    }
+    for (fem_status x : st)
+        if (x != FEM_OK) return x;
+    return build_pair_layouts(batch, vec ? 1 : 0);
+}
+
 extern "C" fem_status fem_batch_numeric(fem_batch batch, int32_t op, const double *q_cat,
                                         const double *w_cat, double lambda, double mu,
                                         double *values_cat, hipStream_t stream) {
@@ -341,12 +372,20 @@ extern "C" fem_status fem_batch_numeric(fem_batch batch, int32_t op, const doubl
         const int64_t M = vec ? p->d : 1;
         if (M * M * p->nnz >= (int64_t(1) << 31)) return FEM_ERR_OVERFLOW;
     }
-    if (batch->kernel == FEM_BATCH_PAIR) {
-        // one pair launch per dimension present; any layout missing or too
+    if (batch->kernel == FEM_BATCH_PAIR || batch->kernel == FEM_BATCH_PAIR_SPLIT) {
+        // one persistent pair launch over both dimensions (one per dimension
+        // when the mixed launch does not fit); any layout missing or too
         // large for LDS: the row-gather launch below covers every mesh
         bool ok = true;
         for (int d = 2; d <= 3; ++d)
             if (batch->has_d[d] && !batch->pairs[vec][d].ok) ok = false;
+        if (ok && batch->kernel == FEM_BATCH_PAIR && batch->has_d[2] && batch->has_d[3]) {
+            const hipError_t e = launch_pair_mixed(batch->pairs[vec][2], batch->pairs[vec][3], op,
+                                                   q_cat, w_cat, lambda, mu, values_cat,
+                                                   batch->status, stream);
+            if (e == hipSuccess) return FEM_OK;
+            if (e != hipErrorNotSupported) return hip_status(e);
+        }
         for (int d = 2; d <= 3 && ok; ++d) {
             if (!batch->has_d[d]) continue;
             const hipError_t e = launch_pair_layout(batch->pairs[vec][d], d, op, q_cat, w_cat,

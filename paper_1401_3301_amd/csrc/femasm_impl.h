@@ -171,6 +171,10 @@ inline bool layouts_ready(const fem_plan_data *p) {
 }
 // Blocks until the layout build has finished (ready or none).
 void wait_layouts(fem_plan_data *p);
+// Rebuilds one pair layout of the plan (vec: elasticity) with R rows per
+// block and `slots` tasks per wavefront, synchronously; not concurrently
+// with numeric calls on the plan.
+fem_status rebuild_pair_layout(fem_plan_data *p, bool vec, int R, int slots);
 
 // CSR pattern, incidences and element order on the GPU (pattern.hip).
 // Allocates and fills rp, ci, pme, porig, inc_ptr, inc_elem, inc_off,
@@ -210,6 +214,12 @@ hipError_t launch_pair_layout(const PairPlan &P, int d, int op, const double *q,
                               double lam, double mu, double *values, int32_t *status,
                               hipStream_t s, const double *w2 = nullptr,
                               const double *gco = nullptr, const double *dq = nullptr);
+// One persistent launch over a 2D and a 3D pair layout (the batched
+// assembly of meshes of both dimensions; the four P1 operators, equal slot
+// counts; hipErrorNotSupported: nothing launched).
+hipError_t launch_pair_mixed(const PairPlan &P2, const PairPlan &P3, int op, const double *q,
+                             const double *w, double lam, double mu, double *values,
+                             int32_t *status, hipStream_t s);
 // Concatenates per-mesh pair layouts into one (block descriptors carry each
 // mesh's coordinate / weight / value offsets and vertex count).  out.ok is
 // false when some part has no layout or the slot counts differ.

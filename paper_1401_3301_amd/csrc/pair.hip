@@ -23,6 +23,7 @@
 // coordinates) is hidden behind the previous block's work.
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <thread>
 #include <vector>
 
@@ -315,9 +316,11 @@ __device__ __forceinline__ void element_values(const double (&P)[D + 1][D], cons
     }
 }
 
+// The persistent loop of one workgroup: workgroup wg of nwg (a multiple of 8)
+// walks its XCD's share of the layout's blocks.
 template <int D, int OP, int S>
-__global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, double mu,
-                                                  int32_t *status) {
+__device__ __forceinline__ void pair_run(const PairView &pv, double lam, double mu,
+                                         int32_t *status, const int wg, const int nwg) {
     using O = PairOp<D, OP>;
     constexpr int NL = D + 1;
     constexpr int NV = O::NV;
@@ -342,7 +345,7 @@ __global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, doubl
     const int MN = pv.max_nodes;
     // blocks of this workgroup: XCD x (workgroups x, x+8, ...) owns a
     // contiguous range of blocks, walked with stride J
-    const int xcd = blockIdx.x & 7, jj = blockIdx.x >> 3, J = gridDim.x >> 3;
+    const int xcd = wg & 7, jj = wg >> 3, J = nwg >> 3;
     const int per = pv.nb >> 3, rem = pv.nb & 7;
     const int xs = xcd * per + (xcd < rem ? xcd : rem);
     const int xn = per + (xcd < rem ? 1 : 0);
@@ -634,6 +637,23 @@ __global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, doubl
     if (any != 0ull && (threadIdx.x & 63) == __ffsll((long long)any) - 1) atomicOr(status, bad);
 }
 
+template <int D, int OP, int S>
+__global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, double mu,
+                                                  int32_t *status) {
+    pair_run<D, OP, S>(pv, lam, mu, status, int(blockIdx.x), int(gridDim.x));
+}
+
+// One persistent launch over a 2D and a 3D layout (a batch with meshes of
+// both dimensions): every workgroup walks its share of the 2D blocks, then
+// its share of the 3D blocks, so the two parts balance over the whole grid.
+template <int OP, int S>
+__global__ void __launch_bounds__(kPairWG) k_pair_mixed(PairView pv2, PairView pv3, double lam,
+                                                        double mu, int32_t *status) {
+    pair_run<2, OP, S>(pv2, lam, mu, status, int(blockIdx.x), int(gridDim.x));
+    __syncthreads();   // the LDS is reused
+    pair_run<3, OP, S>(pv3, lam, mu, status, int(blockIdx.x), int(gridDim.x));
+}
+
 template <class T>
 fem_status up(T **dst, const std::vector<T> &src) {
     *dst = nullptr;
@@ -676,12 +696,9 @@ PairLds pair_lds(const PairPlan &P) {
     return PairLds{pv, align16(o)};
 }
 
-template <int D, int OP, int S>
-hipError_t launch_pair_t(const PairPlan &P, const double *q, const double *w, const double *w2,
-                         const double *gco, const double *dq, double lam, double mu,
-                         double *values, int32_t *status, hipStream_t s) {
-    PairLds L = pair_lds<D, OP>(P);
-    if (L.bytes > 160 * 1024) return hipErrorNotSupported;   // caller falls back
+template <int D, int OP>
+PairView make_view(const PairPlan &P, const PairLds &L, const double *q, const double *w,
+                   const double *w2, const double *gco, const double *dq, double *values) {
     PairView pv = L.pv;
     pv.desc = P.desc;
     pv.rowinfo = P.rowinfo;
@@ -700,30 +717,63 @@ hipError_t launch_pair_t(const PairPlan &P, const double *q, const double *w, co
     pv.values = values;
     pv.nb = P.nb;
     pv.max_nodes = P.max_nodes;
-    const void *fn = reinterpret_cast<const void *>(&k_pair<D, OP, S>);
-    // persistent grid: resident workgroups per CU x CUs, a multiple of the 8 XCDs
-    static thread_local int cached[2][9][3] = {};
-    static thread_local size_t cached_lds[2][9][3] = {};
-    const int si = S == 1 ? 0 : (S == 2 ? 1 : 2);
-    int &occ = cached[D - 2][OP][si];
-    if (occ == 0 || cached_lds[D - 2][OP][si] != L.bytes) {
-        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        int n = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, kPairWG, L.bytes) != hipSuccess ||
-            n < 1)
-            n = 1;
-        occ = n;
-        cached_lds[D - 2][OP][si] = L.bytes;
-    }
+    return pv;
+}
+
+// Resident workgroups per CU of a kernel at this LDS size (cached per kernel).
+int resident_wgs(const void *fn, size_t lds) {
+    static std::mutex mu;
+    static std::vector<std::pair<std::pair<const void *, size_t>, int>> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    for (const auto &c : cache)
+        if (c.first.first == fn && c.first.second == lds) return c.second;
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, kPairWG, lds) != hipSuccess || n < 1)
+        n = 1;
+    cache.push_back({{fn, lds}, n});
+    return n;
+}
+
+int device_cus() {
     int dev = 0, cus = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (cus < 8) cus = 8;
-    int64_t grid = int64_t(occ) * cus / 8 * 8;
+    return std::max(cus, 8);
+}
+
+template <int D, int OP, int S>
+hipError_t launch_pair_t(const PairPlan &P, const double *q, const double *w, const double *w2,
+                         const double *gco, const double *dq, double lam, double mu,
+                         double *values, int32_t *status, hipStream_t s) {
+    PairLds L = pair_lds<D, OP>(P);
+    if (L.bytes > 160 * 1024) return hipErrorNotSupported;   // caller falls back
+    const PairView pv = make_view<D, OP>(P, L, q, w, w2, gco, dq, values);
+    const void *fn = reinterpret_cast<const void *>(&k_pair<D, OP, S>);
+    // persistent grid: resident workgroups per CU x CUs, a multiple of the 8 XCDs
+    int64_t grid = int64_t(resident_wgs(fn, L.bytes)) * device_cus() / 8 * 8;
     const int64_t need = (int64_t(P.nb) + 7) / 8 * 8;
     grid = std::max<int64_t>(8, std::min(grid, need));
     hipLaunchKernelGGL((k_pair<D, OP, S>), dim3(unsigned(grid)), dim3(kPairWG), L.bytes, s, pv,
                        lam, mu, status);
+    return hipGetLastError();
+}
+
+template <int OP, int S>
+hipError_t launch_pair_mixed_t(const PairPlan &P2, const PairPlan &P3, const double *q,
+                               const double *w, double lam, double mu, double *values,
+                               int32_t *status, hipStream_t s) {
+    const PairLds L2 = pair_lds<2, OP>(P2), L3 = pair_lds<3, OP>(P3);
+    const size_t bytes = std::max(L2.bytes, L3.bytes);
+    if (bytes > 160 * 1024) return hipErrorNotSupported;
+    const PairView pv2 = make_view<2, OP>(P2, L2, q, w, nullptr, nullptr, nullptr, values);
+    const PairView pv3 = make_view<3, OP>(P3, L3, q, w, nullptr, nullptr, nullptr, values);
+    const void *fn = reinterpret_cast<const void *>(&k_pair_mixed<OP, S>);
+    int64_t grid = int64_t(resident_wgs(fn, bytes)) * device_cus() / 8 * 8;
+    const int64_t need = (int64_t(std::max(P2.nb, P3.nb)) + 7) / 8 * 8;
+    grid = std::max<int64_t>(8, std::min(grid, need));
+    hipLaunchKernelGGL((k_pair_mixed<OP, S>), dim3(unsigned(grid)), dim3(kPairWG), bytes, s, pv2,
+                       pv3, lam, mu, status);
     return hipGetLastError();
 }
 
@@ -934,6 +984,27 @@ hipError_t launch_pair_layout(const PairPlan &P, int d, int op, const double *q,
                               const double *dq) {
     return d == 2 ? launch_pair_d<2>(P, op, q, w, w2, gco, dq, lam, mu, values, status, s)
                   : launch_pair_d<3>(P, op, q, w, w2, gco, dq, lam, mu, values, status, s);
+}
+
+hipError_t launch_pair_mixed(const PairPlan &P2, const PairPlan &P3, int op, const double *q,
+                             const double *w, double lam, double mu, double *values,
+                             int32_t *status, hipStream_t s) {
+    if (P2.slots != P3.slots) return hipErrorNotSupported;
+#define FEMASM_MIXED(OPC, SS) \
+    return launch_pair_mixed_t<OPC, SS>(P2, P3, q, w, lam, mu, values, status, s);
+#define FEMASM_MIXED_S(OPC)                           \
+    if (P2.slots == 4) { FEMASM_MIXED(OPC, 4) }       \
+    if (P2.slots == 1) { FEMASM_MIXED(OPC, 1) }       \
+    FEMASM_MIXED(OPC, 2)
+    switch (op) {
+        case FEM_OP_MASS: FEMASM_MIXED_S(FEM_OP_MASS)
+        case FEM_OP_MASS_W: FEMASM_MIXED_S(FEM_OP_MASS_W)
+        case FEM_OP_STIFF: FEMASM_MIXED_S(FEM_OP_STIFF)
+        case FEM_OP_ELAS: FEMASM_MIXED_S(FEM_OP_ELAS)
+        default: return hipErrorNotSupported;
+    }
+#undef FEMASM_MIXED_S
+#undef FEMASM_MIXED
 }
 
 bool launch_pair(const fem_plan_data *p, int op, const double *q, const double *w, double lam,

@@ -114,47 +114,59 @@ extern "C" const char *fem_status_str(fem_status s) {
     return "FEM_ERR_UNKNOWN";
 }
 
+// What the host-built block layouts need, copied back from the plan's
+// device arrays: the connectivity in caller layout, the CSR columns and the
+// incidences as caller element numbers.
+struct LayoutInput {
+    std::vector<int32_t> me, ci, inc_k;
+    std::vector<int64_t> ip;
+};
+
+static fem_status layout_input(const fem_plan_s *p, LayoutInput &in) {
+    const int NL = p->d + 1;
+    const int64_t nq = p->nq, nme = p->nme, ninc = int64_t(NL) * nme, nnz = p->nnz;
+    std::vector<int32_t> pme(static_cast<size_t>(ninc)), porig(static_cast<size_t>(nme)),
+        ip32(static_cast<size_t>(nq + 1));
+    std::vector<uint32_t> ielem(static_cast<size_t>(ninc));
+    in.ci.resize(static_cast<size_t>(nnz));
+    hipError_t e = hipSuccess;
+    auto d2h = [&](void *dst, const void *src, size_t bytes) {
+        if (e == hipSuccess && bytes > 0) e = copy_sync(dst, src, bytes, hipMemcpyDeviceToHost);
+    };
+    d2h(pme.data(), p->pme, sizeof(int32_t) * pme.size());
+    d2h(porig.data(), p->porig, sizeof(int32_t) * porig.size());
+    d2h(in.ci.data(), p->ci, sizeof(int32_t) * in.ci.size());
+    d2h(ip32.data(), p->inc_ptr, sizeof(int32_t) * ip32.size());
+    d2h(ielem.data(), p->inc_elem, sizeof(uint32_t) * ielem.size());
+    if (e != hipSuccess) return hip_status(e);
+    in.me.resize(static_cast<size_t>(ninc));
+    in.inc_k.resize(static_cast<size_t>(ninc));
+    in.ip.resize(static_cast<size_t>(nq + 1));
+    parallel_ranges(nme, [&](int64_t b, int64_t en) {
+        for (int64_t q = b; q < en; ++q)
+            for (int a = 0; a < NL; ++a) in.me[size_t(a * nme + porig[q])] = pme[size_t(q * NL + a)];
+    });
+    parallel_ranges(ninc, [&](int64_t b, int64_t en) {
+        for (int64_t t = b; t < en; ++t) in.inc_k[t] = porig[ielem[t] & 0x3fffffffu];
+    });
+    for (int64_t i = 0; i <= nq; ++i) in.ip[i] = ip32[i];
+    return FEM_OK;
+}
+
 // The layout thread: copies the plan's incidences and connectivity back to
 // the host, builds the block layouts there (blocks_host.h), uploads them and
 // publishes them.  Device copies run on streams of their own.
 static void build_layouts(fem_plan_s *p) {
-    const int NL = p->d + 1;
-    const int64_t nq = p->nq, nme = p->nme, ninc = int64_t(NL) * nme, nnz = p->nnz;
     fem_plan_data L;   // the layouts under construction
     L.device = p->device;
     fem_status st = FEM_OK;
     try {
         (void)hipSetDevice(p->device);
-        std::vector<int32_t> pme(static_cast<size_t>(ninc)), porig(static_cast<size_t>(nme)),
-            ci(static_cast<size_t>(nnz)), ip32(static_cast<size_t>(nq + 1));
-        std::vector<uint32_t> ielem(static_cast<size_t>(ninc));
-        hipError_t e = hipSuccess;
-        auto d2h = [&](void *dst, const void *src, size_t bytes) {
-            if (e == hipSuccess && bytes > 0) e = copy_sync(dst, src, bytes, hipMemcpyDeviceToHost);
-        };
-        d2h(pme.data(), p->pme, sizeof(int32_t) * pme.size());
-        d2h(porig.data(), p->porig, sizeof(int32_t) * porig.size());
-        d2h(ci.data(), p->ci, sizeof(int32_t) * ci.size());
-        d2h(ip32.data(), p->inc_ptr, sizeof(int32_t) * ip32.size());
-        d2h(ielem.data(), p->inc_elem, sizeof(uint32_t) * ielem.size());
-        if (e != hipSuccess) {
-            st = hip_status(e);
-        } else {
-            // caller layout of me, incidences as caller element numbers
-            std::vector<int32_t> hme(static_cast<size_t>(ninc)), inc_k(static_cast<size_t>(ninc));
-            std::vector<int64_t> ip(static_cast<size_t>(nq + 1));
-            parallel_ranges(nme, [&](int64_t b, int64_t en) {
-                for (int64_t q = b; q < en; ++q)
-                    for (int a = 0; a < NL; ++a) hme[size_t(a * nme + porig[q])] = pme[size_t(q * NL + a)];
-            });
-            parallel_ranges(ninc, [&](int64_t b, int64_t en) {
-                for (int64_t t = b; t < en; ++t) inc_k[t] = porig[ielem[t] & 0x3fffffffu];
-            });
-            for (int64_t i = 0; i <= nq; ++i) ip[i] = ip32[i];
-            std::vector<int32_t>().swap(pme);
-            std::vector<uint32_t>().swap(ielem);
-            st = upload_blocks(&L, p->d, nq, nme, hme.data(), p->h_rp.data(), ci.data(), ip.data(),
-                               inc_k.data());
+        LayoutInput in;
+        st = layout_input(p, in);
+        if (st == FEM_OK) {
+            st = upload_blocks(&L, p->d, p->nq, p->nme, in.me.data(), p->h_rp.data(), in.ci.data(),
+                               in.ip.data(), in.inc_k.data());
             if (st == FEM_OK) st = upload_leftover(L.pscal, p, 1);
             if (st == FEM_OK) st = upload_leftover(L.pvec, p, p->d);
         }
@@ -178,6 +190,33 @@ static void build_layouts(fem_plan_s *p) {
         p->layout_state.store(any ? kLayoutReady : kLayoutNone, std::memory_order_release);
     }
     p->layout_cv.notify_all();
+}
+
+fem_status femasm::rebuild_pair_layout(fem_plan_data *pd, bool vec, int R, int slots) {
+    fem_plan_s *p = static_cast<fem_plan_s *>(pd);
+    wait_layouts(p);
+    if (p->nme == 0 || p->nnz == 0) return FEM_OK;
+    try {
+        LayoutInput in;
+        fem_status st = layout_input(p, in);
+        if (st != FEM_OK) return st;
+        PairPlan P;
+        st = upload_pairs(P, R, slots, !vec, p->d, p->nq, p->nme, in.me.data(), p->h_rp.data(),
+                          in.ci.data(), in.ip.data(), in.inc_k.data());
+        if (st == FEM_OK) st = upload_leftover(P, p, vec ? p->d : 1);
+        if (st != FEM_OK) {
+            free_pairs(&P);
+            return st;
+        }
+        std::lock_guard<std::mutex> lock(p->layout_mu);
+        PairPlan &dst = vec ? p->pvec : p->pscal;
+        free_pairs(&dst);
+        dst = std::move(P);
+        if (dst.ok) p->layout_state.store(kLayoutReady, std::memory_order_release);
+        return FEM_OK;
+    } catch (...) {
+        return FEM_ERR_NOMEM;
+    }
 }
 
 static fem_status fem_assemble_symbolic_impl(int32_t d, int64_t nq, int64_t nme, const int32_t *me,

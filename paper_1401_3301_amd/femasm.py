@@ -19,6 +19,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfemasm.so")
 
 FEM_OP = {"MASS": 0, "MASS_W": 1, "STIFF": 2, "ELAS": 3}
+# pair layouts the library builds by default: (rows per 3D block, rows per 2D
+# block, tasks per wavefront) of the scalar operators and of elasticity
+PAIR_LAYOUT_DEFAULT = {0: (56, 128, 2), 1: (48, 128, 2)}
 FEM_STATUS = {0: "FEM_OK", 1: "FEM_ERR_ARG", 2: "FEM_ERR_INDEX", 3: "FEM_ERR_DEGENERATE",
               4: "FEM_ERR_OVERFLOW", 5: "FEM_ERR_NOMEM", 6: "FEM_ERR_DEVICE"}
 
@@ -66,6 +69,7 @@ _SIGS = {
     "fem_batch_plan": ([P, I32, C.POINTER(P)], C.c_int),
     "fem_batch_set_params": ([P, I32, I32], C.c_int),
     "fem_batch_set_kernel": ([P, I32], C.c_int),
+    "fem_batch_set_pair_layout": ([P, I32, I32, I32, I32], C.c_int),
     "fem_batch_numeric": ([P, I32, P, P, D, D, P, P], C.c_int),
     "fem_batch_sync_status": ([P, P], C.c_int),
     "fem_batch_destroy": ([P], None),
@@ -259,11 +263,16 @@ def fem_batch_set_params(batch: int, block_threads: int, wg_per_cu: int):
            "fem_batch_set_params")
 
 
-FEM_BATCH_KERNEL = {"rowgather": 0, "pair": 1}
+FEM_BATCH_KERNEL = {"rowgather": 0, "pair": 1, "pair_split": 2}
 
 
 def fem_batch_set_kernel(batch: int, kernel: int):
     _check(load_library().fem_batch_set_kernel(batch, kernel), "fem_batch_set_kernel")
+
+
+def fem_batch_set_pair_layout(batch: int, op: int, rows_3d: int, rows_2d: int, slots: int):
+    _check(load_library().fem_batch_set_pair_layout(batch, op, rows_3d, rows_2d, slots),
+           "fem_batch_set_pair_layout")
 
 
 def fem_batch_numeric(batch: int, op: int, q_cat: int, w_cat: int | None, lam: float, mu: float,
@@ -494,7 +503,11 @@ class Batch:
         self.device = self.mes[0].device
         self.handle = fem_batch_create(self.d, self.nq, self.nme,
                                        [m.data_ptr() for m in self.mes], stream)
-        self.params = ("pair", 256, 2)
+        # pair-layout settings per kind (0 scalar operators, 1 elasticity):
+        # (rows per 3D block, rows per 2D block, tasks per wavefront), the
+        # library's defaults until configured
+        self.layout = {0: PAIR_LAYOUT_DEFAULT[0], 1: PAIR_LAYOUT_DEFAULT[1]}
+        self.params = ("pair",) + self.layout[0]
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -517,13 +530,26 @@ class Batch:
         fem_batch_set_params(self.handle, block_threads, wg_per_cu)
         self.params = (self.params[0], block_threads, wg_per_cu)
 
-    def configure(self, params):
-        """params = (kernel, block_threads, wg_per_cu), kernel 'pair' or
-        'rowgather'; the last two apply to the row-gather launch."""
-        kernel, bt, w = params
-        fem_batch_set_params(self.handle, bt, w)
-        fem_batch_set_kernel(self.handle, FEM_BATCH_KERNEL[kernel])
-        self.params = (kernel, bt, w)
+    def configure(self, params, op="STIFF"):
+        """params = ("pair" | "pair_split", rows_3d, rows_2d, slots): the
+        vertex-pair kernel with that layout for the operators of op's kind
+        (rebuilt when it changes), in one launch over both dimensions or one
+        per dimension; or ("rowgather", block_threads, wg_per_cu): the
+        row-gather launch with those tunables.  Values are the same for every
+        setting."""
+        kind = 1 if _op(op) == FEM_OP["ELAS"] else 0
+        if params[0] in ("pair", "pair_split"):
+            layout = tuple(int(x) for x in params[1:4])
+            if layout != self.layout[kind]:
+                fem_batch_set_pair_layout(self.handle, _op(op), *layout)
+                self.layout[kind] = layout
+            fem_batch_set_kernel(self.handle, FEM_BATCH_KERNEL[params[0]])
+            self.params = (params[0],) + layout
+        else:
+            kernel, bt, w = params
+            fem_batch_set_params(self.handle, bt, w)
+            fem_batch_set_kernel(self.handle, FEM_BATCH_KERNEL[kernel])
+            self.params = (kernel, bt, w)
 
     def numeric(self, op, q_cat, w_cat=None, lam=1.0, mu=0.5, out=None, stream=None):
         nnz = self.offsets(op).nnz[-1]

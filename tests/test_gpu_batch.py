@@ -2,8 +2,9 @@
 element counts log-uniform in [1e3, 2e5]) in persistent launches.
 
 Checks: batched values are bitwise equal to per-mesh fem_assemble_numeric
-values for every mesh, for both kernel families (vertex pairs, row-gather)
-and every tuning parameter set; a subset matches the oracle; a captured
+values for every mesh, for both kernel families (vertex pairs in one launch
+over both dimensions, row-gather), pair layouts rebuilt with other block
+sizes and every tuning parameter set; a subset matches the oracle; a captured
 hipGraph replays to the eager result several times with eager work in
 between.
 """
@@ -58,14 +59,16 @@ def test_batch_sizes(batch):
 def test_batched_equals_per_mesh(batch, op):
     B, meshes, ws, q_cat, w_cat = batch
     ref = _per_mesh(B, op, q_cat, w_cat)
-    for params in [("pair", 256, 2), ("rowgather", 256, 2), ("rowgather", 128, 4),
+    default = ("pair",) + femasm.PAIR_LAYOUT_DEFAULT[1 if op == "ELAS" else 0]
+    split = ("pair_split",) + default[1:]
+    for params in [default, split, ("pair", 40, 96, 1), ("rowgather", 256, 2), ("rowgather", 128, 4),
                    ("rowgather", 64, 8), ("rowgather", 256, 1)]:
-        B.configure(params)
+        B.configure(params, op)
         out = torch.full_like(ref, np.nan)
         B.numeric(op, q_cat, w_cat, out=out)
         B.sync_status()
         assert torch.equal(out, ref), f"{op} batched != per-mesh with params {params}"
-    B.configure(("pair", 256, 2))
+    B.configure(default, op)
 
 
 @pytest.mark.parametrize("op", ["MASS_W", "STIFF", "ELAS"])
@@ -84,10 +87,10 @@ def test_batched_vs_oracle_subset(batch, op):
         assert np.array_equal(rp.cpu().numpy(), orp) and np.array_equal(ci.cpu().numpy(), oci)
 
 
-@pytest.mark.parametrize("kernel", ["pair", "rowgather"])
+@pytest.mark.parametrize("kernel", ["pair", "pair_split", "rowgather"])
 def test_graph_capture_replay(batch, kernel):
     B, meshes, ws, q_cat, w_cat = batch
-    B.configure((kernel, 256, 2))
+    B.configure((kernel, 56, 128, 2) if kernel.startswith("pair") else (kernel, 256, 2))
     offs = B.offsets("STIFF")
     out_s = torch.empty(offs.nnz[-1], dtype=torch.float64, device=DEV)
     out_m = torch.empty(offs.nnz[-1], dtype=torch.float64, device=DEV)
@@ -113,7 +116,7 @@ def test_graph_capture_replay(batch, kernel):
         torch.cuda.synchronize()
         assert torch.equal(out_s, ref_s), f"replay {rep} STIFF"
         assert torch.equal(out_m, ref_m), f"replay {rep} MASS_W"
-    B.configure(("pair", 256, 2))
+    B.configure(("pair", 56, 128, 2))
 
 
 def test_autotuner(batch, tmp_path):
@@ -122,11 +125,12 @@ def test_autotuner(batch, tmp_path):
     ref = _per_mesh(B, "STIFF", q_cat, w_cat)
     cache = str(tmp_path / "tune.json")
     params, times = autotune.tune(B, "STIFF", q_cat, w_cat, reps=2, cache_path=cache)
-    assert params in autotune.CANDIDATES and len(times) >= 6
+    assert params in autotune.candidates("STIFF") and len(times) >= 8
+    assert sum(k.startswith("pair") for k in times) >= 12   # layout variants timed, both forms
     assert B.params == params
     out = B.numeric("STIFF", q_cat, w_cat)
     assert torch.equal(out, ref)
     B.configure(("rowgather", 64, 1))
     again, _ = autotune.tune(B, "STIFF", q_cat, w_cat, cache_path=cache)   # from the cache
     assert again == params and B.params == params
-    B.configure(("pair", 256, 2))
+    B.configure(("pair", 56, 128, 2))
