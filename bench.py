@@ -337,6 +337,30 @@ def extras(torch, femasm, mg, plan, q, stream, steps, mesh):
                       "batched_elements_per_s": 2 * nel / tg, "create_s": t_create,
                       "tuning_s": t_tune, "params": list(batch.params), "tuning_ms": tune_times}
     del graph
+    # an unstructured mesh: Delaunay tetrahedra of 400,000 random points
+    # (Morton-numbered vertices, permuted elements), stiffness and elasticity
+    print("[bench] Delaunay mesh ...", file=sys.stderr, flush=True)
+    mu_ = mg.delaunay_mesh(3, 400_000, seed=90, perm_seed=91)
+    t0 = time.perf_counter()
+    pu = femasm.Plan(torch.from_numpy(mu_.me).to(q.device), mu_.nq, wait_layouts=False)
+    torch.cuda.synchronize()
+    t_sym_u = time.perf_counter() - t0
+    pu.layouts(wait=True)
+    qu = torch.from_numpy(mu_.q).to(q.device)
+    out["delaunay_3d"] = {"points": mu_.nq, "nme": mu_.nme, "max_row": pu.max_row,
+                          "symbolic_s": t_sym_u, "block_layouts": pu.layouts()}
+    for opu in ("STIFF", "ELAS"):
+        nnz_u = pu.query(opu)[1]
+        vu = torch.empty(nnz_u, dtype=torch.float64, device=q.device)
+        fnu = lambda: femasm.fem_assemble_numeric(pu.handle, femasm.FEM_OP[opu], qu.data_ptr(),
+                                                  None, 1.0, 0.5, vu.data_ptr(), stream.cuda_stream)
+        wu, peru = time_launches(fnu, stream, steps, 3)
+        tu = statistics.mean(peru) / 1e3
+        ab = algorithmic_bytes(3, mu_.nq, mu_.nme, nnz_u)
+        out["delaunay_3d"][opu] = {"ms": tu * 1e3, "nnz": nnz_u, "elements_per_s": mu_.nme / tu,
+                                   "alg_GBps": ab / tu / 1e9, "frac": ab / tu / 1e9 / PEAK_HBM_GBS}
+        del vu
+    del pu, qu
     # the 2D workload: 2048^2 cells, stiffness / weighted mass / elasticity
     c2 = mg.config_large_2d()
     m2 = c2["mesh"]

@@ -136,6 +136,7 @@ using namespace femasm;
 extern "C" fem_status fem_assemble_backward(fem_plan plan, uint32_t op_mask, const double *q,
                                             const double *w, const double *a, const double *b,
                                             double *dJdw, double *dJdq, hipStream_t stream) {
+    PhaseRange range("femasm: backward (adjoint)");
     const uint32_t allowed = (1u << FEM_OP_STIFF) | (1u << FEM_OP_MASS_W);
     if (!plan || (op_mask & ~allowed) || op_mask == 0) return FEM_ERR_ARG;
     if (plan->nq == 0) return FEM_OK;

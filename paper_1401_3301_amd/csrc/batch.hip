@@ -283,6 +283,7 @@ static fem_status fem_batch_create_impl(int32_t nmesh, const int32_t *d, const i
 extern "C" fem_status fem_batch_create(int32_t nmesh, const int32_t *d, const int64_t *nq,
                                        const int64_t *nme, const int32_t *const *me,
                                        hipStream_t stream, fem_batch *out) {
+    PhaseRange range("femasm: batch create");
     // host allocations (or threads) can fail for very large batches: report
     // it, never throw across the ABI
     try {
@@ -364,6 +365,7 @@ extern "C" fem_status fem_batch_set_pair_layout(fem_batch batch, int32_t op, int
 extern "C" fem_status fem_batch_numeric(fem_batch batch, int32_t op, const double *q_cat,
                                         const double *w_cat, double lambda, double mu,
                                         double *values_cat, hipStream_t stream) {
+    PhaseRange range("femasm: batch numeric");
     if (!batch || op < FEM_OP_MASS || op > FEM_OP_ELAS || !q_cat || !values_cat)
         return FEM_ERR_ARG;
     if (op == FEM_OP_MASS_W && !w_cat) return FEM_ERR_ARG;

@@ -623,6 +623,7 @@ using namespace femasm;
 extern "C" fem_status fem_assemble_jvp(fem_plan plan, int32_t op, const double *q, const double *w,
                                        const double *dq, const double *dw, double *dvalues,
                                        hipStream_t stream) {
+    PhaseRange range("femasm: JVP");
     if (!plan || !deriv_op(op)) return FEM_ERR_ARG;
     if (plan->nnz == 0) return FEM_OK;
     if (!q || !dq || !dvalues || (op == FEM_OP_MASS_W && (!w || !dw))) return FEM_ERR_ARG;
@@ -648,6 +649,7 @@ extern "C" fem_status fem_assemble_jvp(fem_plan plan, int32_t op, const double *
 extern "C" fem_status fem_assemble_vjp(fem_plan plan, int32_t op, const double *q, const double *w,
                                        const double *G, const int32_t *slot, double *dLdq,
                                        double *dLdw, hipStream_t stream) {
+    PhaseRange range("femasm: VJP");
     if (!plan || !deriv_op(op)) return FEM_ERR_ARG;
     if (plan->nq == 0) return FEM_OK;
     if (!q || (plan->nnz > 0 && (!G || !slot)) || (op == FEM_OP_MASS_W && !w)) return FEM_ERR_ARG;

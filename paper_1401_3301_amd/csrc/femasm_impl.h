@@ -10,9 +10,21 @@
 #include <thread>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/femasm.h"
 
 namespace femasm {
+
+// A named profiler range (roctx) over a phase of the library, shown by
+// rocprofv3 --marker-trace; next to free when no profiler is attached.
+// Host time: for the asynchronous entry points it covers the launches.
+struct PhaseRange {
+    explicit PhaseRange(const char *name) { roctxRangePushA(name); }
+    ~PhaseRange() { roctxRangePop(); }
+    PhaseRange(const PhaseRange &) = delete;
+    PhaseRange &operator=(const PhaseRange &) = delete;
+};
 
 // Largest dynamic LDS block a numeric workgroup may request.
 constexpr size_t kLdsCap = 64 * 1024;

@@ -143,6 +143,7 @@ static MeshView plan_view(const fem_plan_s *p, const double *q, const double *w,
 extern "C" fem_status fem_assemble_numeric(fem_plan plan, int32_t op, const double *q,
                                            const double *w, double lambda, double mu,
                                            double *values, hipStream_t stream) {
+    PhaseRange range("femasm: numeric");
     if (!plan || op < FEM_OP_MASS || op > FEM_OP_ELAS) return FEM_ERR_ARG;
     const int64_t M = op == FEM_OP_ELAS ? plan->d : 1;
     if (M * M * plan->nnz >= (int64_t(1) << 31)) return FEM_ERR_OVERFLOW;
@@ -184,6 +185,7 @@ extern "C" fem_status fem_assemble_numeric(fem_plan plan, int32_t op, const doub
 extern "C" fem_status fem_assemble_elasticity_nodal(fem_plan plan, const double *q,
                                                    const double *lam, const double *mu,
                                                    double *values, hipStream_t stream) {
+    PhaseRange range("femasm: numeric (nodal Lame)");
     if (!plan) return FEM_ERR_ARG;
     const int64_t nnz = int64_t(plan->d) * plan->d * plan->nnz;
     if (nnz >= (int64_t(1) << 31)) return FEM_ERR_OVERFLOW;
@@ -198,6 +200,7 @@ extern "C" fem_status fem_assemble_elasticity_nodal(fem_plan plan, const double 
 
 extern "C" fem_status fem_assemble_general(fem_plan plan, const double *q, const double *coef,
                                           double *values, hipStream_t stream) {
+    PhaseRange range("femasm: numeric (general operator)");
     if (!plan || !coef) return FEM_ERR_ARG;
     if (plan->nnz > 0 && (!q || !values)) return FEM_ERR_ARG;
     if (plan->nnz == 0) return FEM_OK;

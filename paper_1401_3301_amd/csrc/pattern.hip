@@ -278,6 +278,7 @@ int key_bits(int64_t nkeys) {
 }  // namespace
 
 fem_status build_pattern_gpu(fem_plan_data *p, const int32_t *me, hipStream_t s) {
+    PhaseRange range("femasm: symbolic (GPU pattern)");
     const int d = p->d, NL = d + 1;
     const int64_t nq = p->nq, nme = p->nme, ninc = int64_t(NL) * nme;
     Scratch tmp;

@@ -367,6 +367,7 @@ static fem_status fem_pk_symbolic_impl(int32_t d, int32_t k, int64_t nq, int64_t
 
 extern "C" fem_status fem_pk_symbolic(int32_t d, int32_t k, int64_t nq, int64_t nme,
                                       const int32_t *me, hipStream_t stream, fem_pk_plan *out) {
+    PhaseRange range("femasm: P_k symbolic");
     // host allocations (or threads) can fail for very large meshes: report
     // it, never throw across the ABI
     try {
@@ -397,6 +398,7 @@ extern "C" fem_status fem_boundary_symbolic(int32_t d, int64_t nq, int64_t nf,
 
 extern "C" fem_status fem_boundary_mass(fem_pk_plan plan, const double *q, const double *w,
                                         double *values, hipStream_t stream) {
+    PhaseRange range("femasm: boundary mass");
     if (!plan || !plan->boundary || (plan->nme > 0 && !q) || (plan->nnz > 0 && !values))
         return FEM_ERR_ARG;
     if (plan->nnz == 0) return FEM_OK;
@@ -442,6 +444,7 @@ extern "C" fem_status fem_pk_pattern(fem_pk_plan plan, int32_t *row_ptr, int32_t
 
 extern "C" fem_status fem_pk_mass(fem_pk_plan plan, const double *q, double *values,
                                   hipStream_t stream) {
+    PhaseRange range("femasm: P_k mass");
     if (!plan || plan->boundary || (plan->nme > 0 && !q) || (plan->nnz > 0 && !values))
         return FEM_ERR_ARG;
     if (plan->nnz == 0) return FEM_OK;

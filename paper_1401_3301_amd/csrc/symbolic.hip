@@ -157,6 +157,7 @@ static fem_status layout_input(const fem_plan_s *p, LayoutInput &in) {
 // the host, builds the block layouts there (blocks_host.h), uploads them and
 // publishes them.  Device copies run on streams of their own.
 static void build_layouts(fem_plan_s *p) {
+    PhaseRange range("femasm: block layouts (host thread)");
     fem_plan_data L;   // the layouts under construction
     L.device = p->device;
     fem_status st = FEM_OK;
@@ -193,6 +194,7 @@ static void build_layouts(fem_plan_s *p) {
 }
 
 fem_status femasm::rebuild_pair_layout(fem_plan_data *pd, bool vec, int R, int slots) {
+    PhaseRange range("femasm: pair layout rebuild");
     fem_plan_s *p = static_cast<fem_plan_s *>(pd);
     wait_layouts(p);
     if (p->nme == 0 || p->nnz == 0) return FEM_OK;

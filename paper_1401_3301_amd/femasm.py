@@ -10,6 +10,8 @@ or no GPU is visible, loading raises :class:`FemasmUnavailable`.
 from __future__ import annotations
 
 import ctypes as C
+import functools
+import inspect
 import os
 from dataclasses import dataclass
 
@@ -333,6 +335,27 @@ def fem_boundary_mass(plan: int, q: int, w: int | None, values: int, stream=None
 
 
 # ------------------------------------------------------------ torch helpers
+def _on_stream(fn):
+    """Runs a method with the caller's stream (its `stream` argument, a
+    torch.cuda.Stream or a raw handle) current, so that the tensors it
+    allocates -- converted inputs, outputs, work arrays -- belong to that
+    stream for the caching allocator and are not handed out again before the
+    stream's work on them has ended."""
+    sig = inspect.signature(fn)
+
+    @functools.wraps(fn)
+    def wrapper(*args, **kw):
+        bound = sig.bind(*args, **kw)
+        stream = bound.arguments.get("stream")
+        if stream is None:
+            return fn(*args, **kw)
+        s = stream if isinstance(stream, torch.cuda.Stream) else torch.cuda.ExternalStream(int(stream))
+        bound.arguments["stream"] = s
+        with torch.cuda.stream(s):
+            return fn(*bound.args, **bound.kwargs)
+    return wrapper
+
+
 def _op(op) -> int:
     return FEM_OP[op] if isinstance(op, str) else int(op)
 
@@ -378,6 +401,7 @@ class Plan:
     def query(self, op):
         return fem_plan_query(self.handle, _op(op))
 
+    @_on_stream
     def pattern(self, op="STIFF", stream=None):
         nrows, nnz = self.query(op)
         rp = torch.empty(nrows + 1, dtype=torch.int32, device=self.device)
@@ -385,12 +409,14 @@ class Plan:
         fem_plan_pattern(self.handle, _op(op), rp.data_ptr(), ci.data_ptr(), stream)
         return rp, ci[:nnz]
 
+    @_on_stream
     def slot_map(self, stream=None):
         n = (self.d + 1) ** 2 * self.nme
         s = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
         fem_plan_slot_map(self.handle, s.data_ptr(), stream)
         return s[:n]
 
+    @_on_stream
     def numeric(self, op, q, w=None, lam=1.0, mu=0.5, out=None, stream=None):
         nrows, nnz = self.query(op)
         q = _dev_f64(q, self.device)
@@ -401,6 +427,7 @@ class Plan:
                              out.data_ptr(), stream)
         return out[:nnz]
 
+    @_on_stream
     def elasticity_nodal(self, q, lam, mu, out=None, stream=None):
         """Elasticity with nodal Lame fields lam, mu (nq values each)."""
         _, nnz = self.query("ELAS")
@@ -411,6 +438,7 @@ class Plan:
                                       out.data_ptr(), stream)
         return out[:nnz]
 
+    @_on_stream
     def general(self, q, coef, out=None, stream=None):
         """General operator with constant coefficients coef = [A, b, c, a0]."""
         _, nnz = self.query("STIFF")
@@ -422,6 +450,7 @@ class Plan:
         fem_assemble_general(self.handle, q.data_ptr(), list(coef), out.data_ptr(), stream)
         return out[:nnz]
 
+    @_on_stream
     def jvp(self, op, q, dq, w=None, dw=None, out=None, stream=None):
         """Directional derivative of the operator's CSR values along (dq, dw)."""
         _, nnz = self.query(op)
@@ -436,6 +465,7 @@ class Plan:
         """Bytes of the work buffer of the workspace VJP for operator `op`."""
         return fem_vjp_work_bytes(self.handle, _op(op))
 
+    @_on_stream
     def vjp(self, op, q, G, w=None, slot=None, want_w=True, stream=None, work=None):
         """Gradient of sum(G * A) with respect to q (d, nq) and, for MASS_W, w.
         With `work` (a device tensor of at least vjp_work_bytes(op) bytes) the
@@ -458,6 +488,7 @@ class Plan:
                                 stream)
         return gq, gw
 
+    @_on_stream
     def backward(self, q, w, a, b, op_mask=("STIFF", "MASS_W"), want_w=True, want_q=True,
                  stream=None):
         mask = 0
@@ -470,6 +501,7 @@ class Plan:
                               _ptr(gw), _ptr(gq), stream)
         return gw, gq
 
+    @_on_stream
     def bilinear(self, op, values, a, b, stream=None):
         out = torch.empty(1, dtype=torch.float64, device=self.device)
         a = _dev_f64(a, self.device)
@@ -551,6 +583,7 @@ class Batch:
             fem_batch_set_kernel(self.handle, FEM_BATCH_KERNEL[kernel])
             self.params = (kernel, bt, w)
 
+    @_on_stream
     def numeric(self, op, q_cat, w_cat=None, lam=1.0, mu=0.5, out=None, stream=None):
         nnz = self.offsets(op).nnz[-1]
         if out is None:
@@ -586,12 +619,14 @@ class PkPlan:
             fem_pk_destroy(h)
             self.handle = None
 
+    @_on_stream
     def pattern(self, stream=None):
         rp = torch.empty(self.nq + 1, dtype=torch.int32, device=self.device)
         ci = torch.empty(max(self.nnz, 1), dtype=torch.int32, device=self.device)
         fem_pk_pattern(self.handle, rp.data_ptr(), ci.data_ptr(), stream)
         return rp, ci[:self.nnz]
 
+    @_on_stream
     def mass(self, q, out=None, stream=None):
         q = _dev_f64(q, self.device)
         if out is None:
@@ -626,12 +661,14 @@ class BoundaryPlan:
             fem_pk_destroy(h)
             self.handle = None
 
+    @_on_stream
     def pattern(self, stream=None):
         rp = torch.empty(self.nq + 1, dtype=torch.int32, device=self.device)
         ci = torch.empty(max(self.nnz, 1), dtype=torch.int32, device=self.device)
         fem_pk_pattern(self.handle, rp.data_ptr(), ci.data_ptr(), stream)
         return rp, ci[:self.nnz]
 
+    @_on_stream
     def mass(self, q, w=None, out=None, stream=None):
         q = _dev_f64(q, self.device)
         w = _dev_f64(w, self.device)

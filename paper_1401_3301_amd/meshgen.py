@@ -28,6 +28,8 @@ Rules (all seeds feed ``numpy.random.default_rng``):
   axes, with vertices c, c+e_p0, c+e_p0+e_p1, c+(1,1,1); the permutations are
   taken in lexicographic order, elements cube by cube (cubes in id order).
   ``perm_seed`` optionally permutes the element order (columns of ``me``).
+* ``delaunay_mesh(d, npts, seed)``: Delaunay triangulation of random
+  points (unstructured meshes, vertex valence up to several tens).
 * P_k meshes ``pk_mesh(mesh, k)`` (Appendix D): the nodal points of P_k
   Lagrange elements on the straight simplices of a P1 mesh.  Local node
   ``I(alpha)`` of an element is the multi-index ``alpha`` in N^(d+1),
@@ -234,6 +236,31 @@ def boundary_facets(mesh: Mesh) -> np.ndarray:
     f = np.concatenate(faces)
     uniq, cnt = np.unique(f, axis=0, return_counts=True)
     return np.ascontiguousarray(uniq[cnt == 1].T.astype(np.int32))
+
+
+def delaunay_mesh(d: int, npts: int, seed: int, perm_seed: int | None = None,
+                  morton: bool = True) -> Mesh:
+    """Unstructured mesh: the Delaunay triangulation (scipy / Qhull) of
+    ``npts`` uniform random points in the unit square or cube (seeded).  With
+    ``morton`` the points are numbered along a Morton (Z-order) curve of
+    their coordinates quantised to 2^16 (2D) or 2^10 (3D) cells per axis --
+    the locality order a mesh generator would give them; ``perm_seed``
+    optionally permutes the element order."""
+    from scipy.spatial import Delaunay
+    rng = np.random.default_rng(seed)
+    pts = rng.random((npts, d))
+    if morton:
+        bits = 16 if d == 2 else 10
+        cell = np.minimum((pts * (1 << bits)).astype(np.int64), (1 << bits) - 1)
+        code = np.zeros(npts, np.int64)
+        for b in range(bits):
+            for x in range(d):
+                code |= ((cell[:, x] >> b) & 1) << (b * d + x)
+        pts = pts[np.argsort(code, kind="stable")]
+    me = Delaunay(pts).simplices.T.astype(np.int32)
+    if perm_seed is not None:
+        me = me[:, np.random.default_rng(perm_seed).permutation(me.shape[1])]
+    return Mesh(d, np.ascontiguousarray(pts.T), np.ascontiguousarray(me))
 
 
 def lognormal_field(nq: int, seed: int, sigma: float = 0.5) -> np.ndarray:
