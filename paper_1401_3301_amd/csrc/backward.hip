@@ -133,7 +133,7 @@ __global__ void __launch_bounds__(256)
 
 using namespace femasm;
 
-extern "C" fem_status fem_assemble_backward(fem_plan plan, uint32_t op_mask, const double *q,
+static fem_status fem_assemble_backward_impl(fem_plan plan, uint32_t op_mask, const double *q,
                                             const double *w, const double *a, const double *b,
                                             double *dJdw, double *dJdq, hipStream_t stream) {
     PhaseRange range("femasm: backward (adjoint)");
@@ -159,4 +159,11 @@ extern "C" fem_status fem_assemble_backward(fem_plan plan, uint32_t op_mask, con
         hipLaunchKernelGGL(k_backward<3>, dim3(grid), dim3(256), 0, stream, mv, a, b, op_mask,
                            dJdw, dJdq, plan->status);
     return hip_status(hipGetLastError());
+}
+
+extern "C" fem_status fem_assemble_backward(fem_plan plan, uint32_t op_mask, const double *q,
+                                            const double *w, const double *a, const double *b,
+                                            double *dJdw, double *dJdq, hipStream_t stream) {
+    return debug_check(fem_assemble_backward_impl(plan, op_mask, q, w, a, b, dJdw, dJdq, stream),
+                       stream, plan ? plan->status : nullptr);
 }

@@ -362,7 +362,7 @@ extern "C" fem_status fem_batch_set_pair_layout(fem_batch batch, int32_t op, int
     return build_pair_layouts(batch, vec ? 1 : 0);
 }
 
-extern "C" fem_status fem_batch_numeric(fem_batch batch, int32_t op, const double *q_cat,
+static fem_status fem_batch_numeric_impl(fem_batch batch, int32_t op, const double *q_cat,
                                         const double *w_cat, double lambda, double mu,
                                         double *values_cat, hipStream_t stream) {
     PhaseRange range("femasm: batch numeric");
@@ -401,6 +401,14 @@ extern "C" fem_status fem_batch_numeric(fem_batch batch, int32_t op, const doubl
                         batch->block_threads, batch->lds[vec], batch->cus * batch->wg_per_cu,
                         batch->has_d[2], batch->has_d[3], q_cat, w_cat, lambda, mu, values_cat,
                         batch->status, stream);
+}
+
+extern "C" fem_status fem_batch_numeric(fem_batch batch, int32_t op, const double *q_cat,
+                                        const double *w_cat, double lambda, double mu,
+                                        double *values_cat, hipStream_t stream) {
+    const fem_status st =
+        fem_batch_numeric_impl(batch, op, q_cat, w_cat, lambda, mu, values_cat, stream);
+    return debug_check(st, stream, batch ? batch->status : nullptr);
 }
 
 extern "C" fem_status fem_batch_sync_status(fem_batch batch, hipStream_t stream) {

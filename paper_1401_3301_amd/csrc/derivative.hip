@@ -620,7 +620,7 @@ int64_t vjp_work_bytes(const fem_plan_s *p, int32_t op) {
 
 using namespace femasm;
 
-extern "C" fem_status fem_assemble_jvp(fem_plan plan, int32_t op, const double *q, const double *w,
+static fem_status fem_assemble_jvp_impl(fem_plan plan, int32_t op, const double *q, const double *w,
                                        const double *dq, const double *dw, double *dvalues,
                                        hipStream_t stream) {
     PhaseRange range("femasm: JVP");
@@ -646,7 +646,14 @@ extern "C" fem_status fem_assemble_jvp(fem_plan plan, int32_t op, const double *
     return hip_status(e);
 }
 
-extern "C" fem_status fem_assemble_vjp(fem_plan plan, int32_t op, const double *q, const double *w,
+extern "C" fem_status fem_assemble_jvp(fem_plan plan, int32_t op, const double *q, const double *w,
+                                       const double *dq, const double *dw, double *dvalues,
+                                       hipStream_t stream) {
+    return debug_check(fem_assemble_jvp_impl(plan, op, q, w, dq, dw, dvalues, stream),
+                       stream, plan ? plan->status : nullptr);
+}
+
+static fem_status fem_assemble_vjp_impl(fem_plan plan, int32_t op, const double *q, const double *w,
                                        const double *G, const int32_t *slot, double *dLdq,
                                        double *dLdw, hipStream_t stream) {
     PhaseRange range("femasm: VJP");
@@ -658,6 +665,13 @@ extern "C" fem_status fem_assemble_vjp(fem_plan plan, int32_t op, const double *
     const hipError_t e = plan->d == 2 ? launch_vjp<2>(plan, op, mv, slot, G, dLdq, dLdw, stream)
                                       : launch_vjp<3>(plan, op, mv, slot, G, dLdq, dLdw, stream);
     return hip_status(e);
+}
+
+extern "C" fem_status fem_assemble_vjp(fem_plan plan, int32_t op, const double *q, const double *w,
+                                       const double *G, const int32_t *slot, double *dLdq,
+                                       double *dLdw, hipStream_t stream) {
+    return debug_check(fem_assemble_vjp_impl(plan, op, q, w, G, slot, dLdq, dLdw, stream),
+                       stream, plan ? plan->status : nullptr);
 }
 
 extern "C" fem_status fem_vjp_work_bytes(fem_plan plan, int32_t op, int64_t *bytes) {

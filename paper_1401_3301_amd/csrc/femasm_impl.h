@@ -176,6 +176,12 @@ inline hipError_t copy_sync(void *dst, const void *src, size_t bytes, hipMemcpyK
     return e != hipSuccess ? e : e2;
 }
 
+// FEMASM_DEBUG=1 in the environment: the asynchronous entry points
+// synchronise their stream after their launches and report a launch or
+// kernel error, or a degenerate element (the status word, then cleared),
+// from the call itself.  A debugging aid; off by default.
+fem_status debug_check(fem_status st, hipStream_t s, int32_t *status_word);
+
 // True when the block layouts are published (acquire: their arrays are
 // complete and visible).
 inline bool layouts_ready(const fem_plan_data *p) {

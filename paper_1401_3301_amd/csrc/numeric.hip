@@ -140,7 +140,7 @@ static MeshView plan_view(const fem_plan_s *p, const double *q, const double *w,
     return mv;
 }
 
-extern "C" fem_status fem_assemble_numeric(fem_plan plan, int32_t op, const double *q,
+static fem_status fem_assemble_numeric_impl(fem_plan plan, int32_t op, const double *q,
                                            const double *w, double lambda, double mu,
                                            double *values, hipStream_t stream) {
     PhaseRange range("femasm: numeric");
@@ -182,7 +182,14 @@ extern "C" fem_status fem_assemble_numeric(fem_plan plan, int32_t op, const doub
     return hip_status(e);
 }
 
-extern "C" fem_status fem_assemble_elasticity_nodal(fem_plan plan, const double *q,
+extern "C" fem_status fem_assemble_numeric(fem_plan plan, int32_t op, const double *q,
+                                           const double *w, double lambda, double mu,
+                                           double *values, hipStream_t stream) {
+    return debug_check(fem_assemble_numeric_impl(plan, op, q, w, lambda, mu, values, stream),
+                       stream, plan ? plan->status : nullptr);
+}
+
+static fem_status fem_assemble_elasticity_nodal_impl(fem_plan plan, const double *q,
                                                    const double *lam, const double *mu,
                                                    double *values, hipStream_t stream) {
     PhaseRange range("femasm: numeric (nodal Lame)");
@@ -198,7 +205,14 @@ extern "C" fem_status fem_assemble_elasticity_nodal(fem_plan plan, const double 
     return FEM_ERR_OVERFLOW;   // no vertex-pair layout for this mesh
 }
 
-extern "C" fem_status fem_assemble_general(fem_plan plan, const double *q, const double *coef,
+extern "C" fem_status fem_assemble_elasticity_nodal(fem_plan plan, const double *q,
+                                                   const double *lam, const double *mu,
+                                                   double *values, hipStream_t stream) {
+    return debug_check(fem_assemble_elasticity_nodal_impl(plan, q, lam, mu, values, stream),
+                       stream, plan ? plan->status : nullptr);
+}
+
+static fem_status fem_assemble_general_impl(fem_plan plan, const double *q, const double *coef,
                                           double *values, hipStream_t stream) {
     PhaseRange range("femasm: numeric (general operator)");
     if (!plan || !coef) return FEM_ERR_ARG;
@@ -212,6 +226,12 @@ extern "C" fem_status fem_assemble_general(fem_plan plan, const double *q, const
     if (launch_pair(plan, kOpGeneral, q, nullptr, 0.0, 0.0, values, stream, &e, nullptr, gco))
         return hip_status(e);
     return FEM_ERR_OVERFLOW;   // no vertex-pair layout for this mesh
+}
+
+extern "C" fem_status fem_assemble_general(fem_plan plan, const double *q, const double *coef,
+                                          double *values, hipStream_t stream) {
+    return debug_check(fem_assemble_general_impl(plan, q, coef, values, stream),
+                       stream, plan ? plan->status : nullptr);
 }
 
 extern "C" fem_status fem_plan_pattern(fem_plan plan, int32_t op, int32_t *row_ptr,

@@ -92,6 +92,23 @@ RowLaunch row_launch_for(const std::vector<int32_t> &h_rp, int64_t nq, int M, si
     return best;
 }
 
+fem_status debug_check(fem_status st, hipStream_t s, int32_t *status_word) {
+    const char *env = getenv("FEMASM_DEBUG");
+    if (!env || !*env || strcmp(env, "0") == 0 || st != FEM_OK) return st;
+    hipError_t e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return hip_status(e);
+    if (!status_word) return FEM_OK;
+    int32_t word = 0;
+    e = hipMemcpy(&word, status_word, sizeof(int32_t), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && word != 0) {
+        const int32_t zero = 0;
+        e = hipMemcpy(status_word, &zero, sizeof(int32_t), hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) return hip_status(e);
+    return word ? FEM_ERR_DEGENERATE : FEM_OK;
+}
+
 void wait_layouts(fem_plan_data *p) {
     std::unique_lock<std::mutex> lock(p->layout_mu);
     p->layout_cv.wait(lock, [&] { return p->layout_state.load() != kLayoutBuilding; });

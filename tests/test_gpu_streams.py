@@ -50,3 +50,27 @@ def test_side_stream_with_converted_inputs():
     v = plan.numeric("STIFF", q32, stream=side.cuda_stream)
     torch.cuda.current_stream().wait_stream(side)
     assert torch.equal(v, ref["STIFF"])
+
+
+def test_debug_mode_reports_at_the_call(monkeypatch):
+    """FEMASM_DEBUG=1: a numeric call on a mesh with a degenerate element
+    returns FEM_ERR_DEGENERATE itself (the status word is read and cleared),
+    a good call returns normally; without it the error waits for
+    fem_plan_sync_status."""
+    m = mg.jittered_square(6, 0.1, seed=2)
+    plan = femasm.Plan(torch.from_numpy(m.me).to(DEV), m.nq)
+    q = torch.from_numpy(m.q).to(DEV)
+    qb = m.q.copy()
+    qb[:, m.me[1, 5]] = qb[:, m.me[0, 5]]
+    qb = torch.from_numpy(qb).to(DEV)
+    monkeypatch.setenv("FEMASM_DEBUG", "1")
+    plan.numeric("STIFF", q)
+    with pytest.raises(femasm.FemError) as e:
+        plan.numeric("STIFF", qb)
+    assert e.value.name == "FEM_ERR_DEGENERATE"
+    plan.sync_status()   # already cleared by the call
+    monkeypatch.delenv("FEMASM_DEBUG")
+    plan.numeric("STIFF", qb)   # no error at the call
+    with pytest.raises(femasm.FemError) as e:
+        plan.sync_status()
+    assert e.value.name == "FEM_ERR_DEGENERATE"
