@@ -101,8 +101,9 @@ struct PairPlan {
     uint32_t *elem = nullptr;     // 4 x 8-bit local vertex ids per block element
     int32_t *task_cnt = nullptr;  // entries per lane of each task
     int32_t *task_eoff = nullptr; // first entry of each task, relative to its block
-    uint16_t *hdr = nullptr;      // [ntask*64] r | p << 7 per task lane (0xffff: empty)
-    uint16_t *hdr2 = nullptr;     // [ntask*64] mirror pair written by the same lane (0xffff: none)
+    // [ntask*64] per task lane: low half the pair r | p << 7 (0xffff: empty),
+    // high half the mirror pair written by the same lane (0xffff: none)
+    uint32_t *hdr = nullptr;
     uint16_t *ent = nullptr;      // entry lists, entry-major within a task
     int64_t n_rows = 0, n_nodes = 0, n_elems = 0, n_tasks = 0, n_ent = 0;   // array lengths
     std::vector<int32_t> h_desc;  // host copy of desc (batched layouts are built from it)

@@ -41,6 +41,8 @@ constexpr int kPairWG = kPairWaves * 64;
 constexpr int kEntSlots = 8192 / 8 / kPairWG;   // uint4 entry slots per thread: <= 8192 entries
 constexpr int kNodeSlots = 512 / kPairWG;       // touched vertices per thread
 constexpr int kMaxPairNodes = 256;              // touched vertices per block: 8-bit local ids
+// s_waitcnt operand: vmcnt(0), expcnt and lgkmcnt left at their maxima
+constexpr int kWaitVmem = 0x0F70;
 constexpr int kElemSlots = 1024 / kPairWG;      // elements per thread: <= 1023 (+ dummy)
 static_assert(kEntSlots == 2 && kNodeSlots == 1 && kElemSlots == 2, "512-thread workgroups");
 static_assert(kPairWaves * 4 < (1 << kWaveStartBits) && kPairWaves * kWaveStartBits <= 64,
@@ -53,8 +55,7 @@ struct PairView {
     const uint32_t *elem;
     const int32_t *task_cnt;
     const int32_t *task_eoff;
-    const uint16_t *hdr;
-    const uint16_t *hdr2;
+    const uint32_t *hdr;
     const uint16_t *ent;
     const double *q;
     const double *w;
@@ -356,7 +357,7 @@ __device__ __forceinline__ void pair_run(const PairView &pv, double lam, double 
     uint4 rent0 = make_uint4(0, 0, 0, 0), rent1 = rent0;
     uint32_t rel[kElemSlots];   // 4 x 8-bit local vertex ids per element
     int4 rrow = make_int4(0, 0, 0, 0);
-    uint32_t rhd[S], rhd2[S];
+    uint32_t rhd[S];   // pair | mirror << 16, split where it is used
     int rcntv = 0, reoffv = 0, rns = 0;   // task entry counts / offsets, lane s = slot s
     double rq[kNodeSlots][D];
     double rw[kNodeSlots], rw2[kNodeSlots];
@@ -392,8 +393,8 @@ __device__ __forceinline__ void pair_run(const PairView &pv, double lam, double 
         reoffv = lane < rns ? pv.task_eoff[tw0 + lane] : 0;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            rhd[s] = s < rns ? pv.hdr[int64_t(tw0 + s) * 64 + lane] : kPairPad;
-            rhd2[s] = s < rns ? pv.hdr2[int64_t(tw0 + s) * 64 + lane] : kPairPad;
+            rhd[s] = s < rns ? pv.hdr[int64_t(tw0 + s) * 64 + lane]
+                             : kPairPad | (uint32_t(kPairPad) << 16);
         }
         if (tid < d.nent8) rent0 = src[tid];
         if (kPairWG + tid < d.nent8) rent1 = src[kPairWG + tid];
@@ -425,6 +426,12 @@ __device__ __forceinline__ void pair_run(const PairView &pv, double lam, double 
     bool have_prev = false;
     int bad = 0;
     for (int k = 0;; ++k) {
+        // Every load issued for this block landed during the previous block's
+        // work: wait for all of them here, once.  Without this the compiler,
+        // which cannot count loads issued under divergent conditions, waits
+        // for everything outstanding further down, including the next
+        // block's coordinate loads issued just before.
+        __builtin_amdgcn_s_waitcnt(kWaitVmem);
         // L1: coordinates of the current block into LDS
 #pragma unroll
         for (int u = 0; u < kNodeSlots; ++u) {
@@ -464,8 +471,8 @@ __device__ __forceinline__ void pair_run(const PairView &pv, double lam, double 
         const int ns = rns;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            hd[s] = rhd[s];
-            hd2[s] = rhd2[s];
+            hd[s] = rhd[s] & 0xffffu;
+            hd2[s] = rhd[s] >> 16;
             cnt[s] = __builtin_amdgcn_readlane(rcntv, s);
             eoff[s] = __builtin_amdgcn_readlane(reoffv, s);
         }
@@ -707,7 +714,6 @@ PairView make_view(const PairPlan &P, const PairLds &L, const double *q, const d
     pv.task_cnt = P.task_cnt;
     pv.task_eoff = P.task_eoff;
     pv.hdr = P.hdr;
-    pv.hdr2 = P.hdr2;
     pv.ent = P.ent;
     pv.q = q;
     pv.w = w;
@@ -812,7 +818,7 @@ hipError_t launch_pair_d(const PairPlan &P, int op, const double *q, const doubl
 
 void free_pairs(PairPlan *p) {
     void *ptrs[] = {p->desc,      p->rowinfo, p->nodes, p->elem, p->task_cnt,  p->task_eoff,
-                    p->hdr,       p->hdr2,    p->ent,   p->left_items, p->left_mesh};
+                    p->hdr,       p->ent,     p->left_items, p->left_mesh};
     for (void *x : ptrs)
         if (x) (void)hipFree(x);
     *p = PairPlan();
@@ -896,8 +902,12 @@ fem_status upload_pairs(PairPlan &P, int R, int slots, bool tri, int d, int64_t 
     if (st == FEM_OK) st = up(&P.elem, elem8);
     if (st == FEM_OK) st = up(&P.task_cnt, PH.task_cnt);
     if (st == FEM_OK) st = up(&P.task_eoff, task_eoff);
-    if (st == FEM_OK) st = up(&P.hdr, PH.hdr);
-    if (st == FEM_OK) st = up(&P.hdr2, PH.hdr2);
+    {
+        std::vector<uint32_t> hdr(PH.hdr.size());
+        for (size_t k = 0; k < hdr.size(); ++k)
+            hdr[k] = uint32_t(PH.hdr[k]) | (uint32_t(PH.hdr2[k]) << 16);
+        if (st == FEM_OK) st = up(&P.hdr, hdr);
+    }
     if (st == FEM_OK) st = up(&P.ent, PH.ent);
     if (st != FEM_OK) {
         free_pairs(&P);
@@ -1063,7 +1073,6 @@ fem_status concat_pairs(PairPlan &out, const std::vector<const PairPlan *> &part
     alloc(&out.task_cnt, tasks);
     alloc(&out.task_eoff, tasks);
     alloc(&out.hdr, 64 * tasks);
-    alloc(&out.hdr2, 64 * tasks);
     alloc(&out.ent, ents);
     int64_t r0 = 0, n0 = 0, e0 = 0, t0 = 0, eb = 0, b0 = 0;
     for (size_t m = 0; m < parts.size() && e == hipSuccess; ++m) {
@@ -1078,7 +1087,6 @@ fem_status concat_pairs(PairPlan &out, const std::vector<const PairPlan *> &part
         cp(out.task_cnt + t0, P.task_cnt, P.n_tasks);
         cp(out.task_eoff + t0, P.task_eoff, P.n_tasks);
         cp(out.hdr + 64 * t0, P.hdr, 64 * P.n_tasks);
-        cp(out.hdr2 + 64 * t0, P.hdr2, 64 * P.n_tasks);
         cp(out.ent + eb, P.ent, P.n_ent);
         for (int b = 0; b < P.nb; ++b) {
             int32_t *x = desc.data() + size_t(b0 + b) * kDescInts;
