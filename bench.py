@@ -170,7 +170,7 @@ def extras(torch, femasm, mg, plan, q, stream, steps, mesh):
     vals = torch.empty(nnz_e, dtype=torch.float64, device=q.device)
     fn = lambda: femasm.fem_assemble_numeric(plan.handle, 3, q.data_ptr(), None, 1.0, 0.5,
                                             vals.data_ptr(), stream.cuda_stream)
-    _, per = time_launches(fn, stream, max(3, steps // 4), 2)
+    _, per = time_launches(fn, stream, max(10, steps // 2), 5)
     t = statistics.mean(per) / 1e3
     ab = algorithmic_bytes(3, plan.nq, plan.nme, nnz_e)
     out["elas_3d"] = {"elements_per_s": plan.nme / t, "nnz_per_s": nnz_e / t,

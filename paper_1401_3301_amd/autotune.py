@@ -22,7 +22,7 @@ import torch
 
 from . import femasm
 
-PAIR_ROWS_3D = {"scalar": (40, 56, 72), "elas": (32, 48, 64)}
+PAIR_ROWS_3D = {"scalar": (48, 64, 72), "elas": (48, 56, 64)}
 
 
 def candidates(op: str):
@@ -94,7 +94,7 @@ def tune(batch: femasm.Batch, op: str, q_cat, w_cat=None, reps: int = 5,
             continue
         times[_key(cand)] = _time(batch, op, q_cat, w_cat, out, reps)
     best = min(times, key=times.get)
-    kern, rest = best.split(":")   # e.g. "pair_split:56x128x2"
+    kern, rest = best.split(":")   # e.g. "pair_split:64x128x2"
     params = (kern,) + tuple(int(x) for x in rest.split("x"))
     batch.configure(params, op)
     cache[key] = {"params": list(params), "times": times}

@@ -329,8 +329,11 @@ fem_status upload_blocks(fem_plan_data *p, int d, int64_t nq, int64_t nme, const
     int R = 64;
     if (const char *env = getenv("FEMASM_BLOCK_ROWS")) R = std::max(16, std::min(kMaxWG, atoi(env)));
     // pair layouts: FEMASM_PAIR_ROWS / FEMASM_ELAS_ROWS rows per block when
-    // set (16..128), else in 3D 56 (scalar operators) and 48 (elasticity),
-    // in 2D 128 for both (2D rows are short: the largest blocks the row
+    // set (16..128), else in 3D 64 for both (measured on the 128^3 cube:
+    // 64 rows 8 % faster than 56 for stiffness, 3 % faster than 48 for
+    // elasticity, whose blocks the element cap then ends first; larger
+    // blocks no faster, and beyond 72 rows the lists outgrow the LDS of two
+    // workgroups per compute unit), in 2D 128 for both (2D rows are short: the largest blocks the row
     // field allows cut element replication; measured on the 2048^2 square:
     // 128 rows 40 % faster than 56 for the scalar operators, 20 % faster
     // than 64 for elasticity); FEMASM_PAIR_SLOTS / FEMASM_ELAS_SLOTS (1, 2
@@ -342,9 +345,9 @@ fem_status upload_blocks(fem_plan_data *p, int d, int64_t nq, int64_t nme, const
         return e ? std::max(lo, std::min(hi, atoi(e))) : dflt;
     };
     auto slots_of = [](int v) { return v >= 4 ? 4 : (v <= 1 ? 1 : 2); };
-    const int Rs = env_int("FEMASM_PAIR_ROWS", d == 3 ? 56 : 128, 16, 128);
+    const int Rs = env_int("FEMASM_PAIR_ROWS", d == 3 ? 64 : 128, 16, 128);
     const int Ss = slots_of(env_int("FEMASM_PAIR_SLOTS", 2, 1, 4));
-    const int Re = env_int("FEMASM_ELAS_ROWS", d == 3 ? 48 : 128, 16, 128);
+    const int Re = env_int("FEMASM_ELAS_ROWS", d == 3 ? 64 : 128, 16, 128);
     const int Se = slots_of(env_int("FEMASM_ELAS_SLOTS", 2, 1, 4));
     // the two pair layouts are independent: built concurrently, each thread
     // on the plan's device.  The record-block layout serves the scalar

@@ -67,8 +67,8 @@ struct PairView {
     uint32_t off_w, off_row, off_rowof, off_ev, off_ent;
 };
 
-// Per-element values kept in LDS (odd slot size: consecutive elements fall on
-// different banks).  ELAS: scaled cofactors ch_a (and, with nodal Lame
+// Per-element values kept in LDS (mostly an odd slot size: consecutive
+// elements fall on different banks).  ELAS: scaled cofactors ch_a (and, with nodal Lame
 // fields, the element means lambda_K, mu_K after them); the scalar
 // operators: the packed upper triangle of the element matrix, entry (a, b),
 // a <= b, at a*(d+1) - a*(a-1)/2 + (b-a) (the pair entries carry that index).
@@ -82,7 +82,9 @@ struct PairOp {
                                : OP == kOpElasNodal ? NL * D + 2
                                : OP == kOpGeneral   ? NL * NL
                                                     : NL * (NL + 1) / 2;
-    static constexpr int NV = NV0 | 1;
+    // 3D scalar operators: ten values, unpadded (their blocks are the largest
+    // the LDS holds); the others an odd slot size
+    static constexpr int NV = (D == 3 && NV0 == 10) ? NV0 : (NV0 | 1);
     static constexpr int M = is_elas(OP) ? D : 1;
     // register sums per pair (the general operator also sums its mirror's
     // transposed entries)
@@ -838,7 +840,11 @@ fem_status upload_pairs(PairPlan &P, int R, int slots, bool tri, int d, int64_t 
     // elements keep it within the 80 KB that two workgroups per compute unit
     // allow (blocks grown against a chunk border would otherwise grow flat and
     // large).
-    const int ecap = d == 3 ? (tri ? 700 : 600) : kMaxBlockElems;
+    // FEMASM_PAIR_ELEMS / FEMASM_ELAS_ELEMS override the 3D caps.
+    int ecap = d == 3 ? (tri ? 700 : 600) : kMaxBlockElems;
+    if (d == 3)
+        if (const char *e = getenv(tri ? "FEMASM_PAIR_ELEMS" : "FEMASM_ELAS_ELEMS"))
+            ecap = std::max(64, std::min(kMaxBlockElems, atoi(e)));
     // vertices that fit no block (a star or row beyond these caps) and the
     // rows of blocks beyond the task or list-entry caps are left over: the
     // row-gather tile kernel assembles them

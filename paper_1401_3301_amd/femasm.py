@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libfemasm.so")
 FEM_OP = {"MASS": 0, "MASS_W": 1, "STIFF": 2, "ELAS": 3}
 # pair layouts the library builds by default: (rows per 3D block, rows per 2D
 # block, tasks per wavefront) of the scalar operators and of elasticity
-PAIR_LAYOUT_DEFAULT = {0: (56, 128, 2), 1: (48, 128, 2)}
+PAIR_LAYOUT_DEFAULT = {0: (64, 128, 2), 1: (64, 128, 2)}
 FEM_STATUS = {0: "FEM_OK", 1: "FEM_ERR_ARG", 2: "FEM_ERR_INDEX", 3: "FEM_ERR_DEGENERATE",
               4: "FEM_ERR_OVERFLOW", 5: "FEM_ERR_NOMEM", 6: "FEM_ERR_DEVICE"}
 
