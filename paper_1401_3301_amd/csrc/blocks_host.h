@@ -18,7 +18,9 @@
 // Blocks grow until they hold R rows or the next vertex would bring the
 // element count above max_elems (at most kMaxBlockElems; or, when max_pairs > 0, the number of
 // CSR entries of the block's rows above max_pairs; when max_nodes > 0, the
-// number of touched vertices above max_nodes).
+// number of touched vertices above max_nodes; when max_inc > 0, (d+1) times
+// the sum of the rows' star sizes above max_inc -- that sum bounds the pair
+// lists' entries before mirror pairs share a list).
 // Every incidence also gets a wide record (`wrec`, 64 bits: element position
 // bits 0-9, local vertex a bits 10-11, the column position of local vertex b
 // in 12 bits from bit 12 + 12b), the input of the pair lists.
@@ -26,7 +28,8 @@
 // with a row longer than 32 entries, or a vertex whose own star exceeds a
 // cap, does not fit (ok == false).  Pair mode (pair_mode): such vertices --
 // a row longer than kMaxPairRow entries or than max_pairs, a star above the
-// element cap, a row with more vertices than max_nodes -- are left out of
+// element cap (or (d+1) times it above max_inc), a row with more vertices
+// than max_nodes -- are left out of
 // the blocks and listed in `leftover` (another kernel assembles their rows);
 // the 32-bit records are not built.
 #pragma once
@@ -68,7 +71,7 @@ inline BlockHost build_block_host(int d, int64_t nq, int64_t nme, const int32_t 
                                   const int32_t *inc_k, int R, int nthreads,
                                   int64_t max_pairs = 0, int max_nodes = 0,
                                   int64_t chunk_min = 8192, int max_elems = kMaxBlockElems,
-                                  bool pair_mode = false) {
+                                  bool pair_mode = false, int64_t max_inc = 0) {
     const int ecap = std::min(max_elems, kMaxBlockElems);   // growth stops above it
     BlockHost H;
     const int NL = d + 1;
@@ -82,7 +85,8 @@ inline BlockHost build_block_host(int d, int64_t nq, int64_t nme, const int32_t 
         }
         if (len == 0) continue;
         if (len > kMaxPairRow || (max_pairs > 0 && len > max_pairs) ||
-            (max_nodes > 0 && len > max_nodes) || ip[i + 1] - ip[i] > ecap) {
+            (max_nodes > 0 && len > max_nodes) || ip[i + 1] - ip[i] > ecap ||
+            (max_inc > 0 && NL * (ip[i + 1] - ip[i]) > max_inc)) {
             excluded[i] = 1;
             H.leftover.push_back(int32_t(i));
         }
@@ -159,6 +163,9 @@ inline BlockHost build_block_host(int d, int64_t nq, int64_t nme, const int32_t 
             queue.push_back(int32_t(seed));
             int nel = new_elems(int32_t(seed), b);
             int64_t npairs = rp[seed + 1] - rp[seed];
+            // (d+1) x the stars of the rows: the list entries of the rows'
+            // pairs before mirror pairs are merged (capped by max_inc)
+            int64_t ninc = NL * (ip[seed + 1] - ip[seed]);
             int nnodes = max_nodes > 0 ? new_nodes(int32_t(seed), b) : 0;
             if (max_nodes > 0 && nnodes > max_nodes) {
                 cfail[c] = 1;
@@ -176,13 +183,16 @@ inline BlockHost build_block_host(int d, int64_t nq, int64_t nme, const int32_t 
                     const int add = new_elems(j, b);
                     const int64_t addp = rp[j + 1] - rp[j];
                     const int addn = max_nodes > 0 ? new_nodes(j, b) : 0;
+                    const int64_t addi = NL * (ip[j + 1] - ip[j]);
                     if (nel + add > ecap || (max_pairs > 0 && npairs + addp > max_pairs) ||
-                        (max_nodes > 0 && nnodes + addn > max_nodes)) {
+                        (max_nodes > 0 && nnodes + addn > max_nodes) ||
+                        (max_inc > 0 && ninc + addi > max_inc)) {
                         full = true;
                         break;
                     }
                     nel += add;
                     npairs += addp;
+                    ninc += addi;
                     nnodes += addn;
                     take(j, b);
                     queue.push_back(j);

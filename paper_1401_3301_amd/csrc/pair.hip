@@ -848,11 +848,13 @@ fem_status upload_pairs(PairPlan &P, int R, int slots, bool tri, int d, int64_t 
     // vertices that fit no block (a star or row beyond these caps) and the
     // rows of blocks beyond the task or list-entry caps are left over: the
     // row-gather tile kernel assembles them
+    // The list-entry cap of a block also bounds its growth (by the entries
+    // before mirror pairs are merged), so that blocks seldom end up over it.
+    const int64_t max_ent = int64_t(kEntSlots) * kPairWG * 8;
     BlockHost H = build_block_host(d, nq, nme, me, rp, ci, ip, inc_k, std::min(R, 128), 16,
-                                   max_pairs, kMaxPairNodes, 8192, ecap, true);
+                                   max_pairs, kMaxPairNodes, 8192, ecap, true, max_ent);
     if (!H.ok || H.nb == 0) return FEM_OK;   // row-gather kernel only
-    PairHost PH = build_pair_host(H, d, rp, ci, kPairWaves, slots, 16, tri, dedup,
-                                  int64_t(kEntSlots) * kPairWG * 8);
+    PairHost PH = build_pair_host(H, d, rp, ci, kPairWaves, slots, 16, tri, dedup, max_ent);
     if (!PH.ok || H.max_nodes > std::min(kMaxPairNodes, kNodeSlots * kPairWG) ||
         H.max_elems + 1 > kElemSlots * kPairWG)
         return FEM_OK;

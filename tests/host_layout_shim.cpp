@@ -20,9 +20,9 @@ extern "C" int hl_build(int d, int64_t nq, int64_t nme, const int32_t *me, const
                         const int32_t *ci, const int64_t *ip, const int32_t *inc_k, int R,
                         int64_t max_pairs, int max_nodes, int waves, int slots, int tri,
                         int dedup, int64_t chunk_min, int pair_mode, int max_elems,
-                        int64_t max_ent, int64_t *sizes) {
+                        int64_t max_ent, int64_t max_inc, int64_t *sizes) {
     g_h = build_block_host(d, nq, nme, me, rp, ci, ip, inc_k, R, 4, max_pairs, max_nodes,
-                           chunk_min, max_elems, pair_mode != 0);
+                           chunk_min, max_elems, pair_mode != 0, max_inc);
     if (!g_h.ok) return 1;
     g_p = build_pair_host(g_h, d, rp, ci, waves, slots, 2, tri != 0, dedup != 0, max_ent);
     if (!g_p.ok) return 2;

@@ -53,13 +53,13 @@ def _pattern(mesh):
 
 
 def _build(shim, mesh, R, max_pairs=0, max_nodes=0, waves=8, slots=2, tri=False, dedup=True,
-           chunk_min=8192, pair_mode=False, max_elems=1023, max_ent=0):
+           chunk_min=8192, pair_mode=False, max_elems=1023, max_ent=0, max_inc=0):
     me, rp, ci, ip, inc_k = _pattern(mesh)
     sizes = np.zeros(10, np.int64)
     st = shim.hl_build(mesh.d, ctypes.c_int64(mesh.nq), ctypes.c_int64(mesh.nme), _p(me), _p(rp),
                        _p(ci), _p(ip), _p(inc_k), R, ctypes.c_int64(max_pairs), max_nodes, waves,
                        slots, int(tri), int(dedup), ctypes.c_int64(chunk_min), int(pair_mode),
-                       max_elems, ctypes.c_int64(max_ent), _p(sizes))
+                       max_elems, ctypes.c_int64(max_ent), ctypes.c_int64(max_inc), _p(sizes))
     assert st == 0, f"builder refused the mesh (status {st})"
     nb, nrows, nnodes, nelem, nrec, ntask, nent, _, nleft, nwrec = (int(x) for x in sizes)
     B = dict(rows=np.zeros(nrows, np.int32), row_ptr=np.zeros(nb + 1, np.int32),
@@ -88,7 +88,7 @@ def _tri(a, b, nl):
 
 
 def _check(mesh, built, R, max_pairs, max_nodes, waves, slots, tri, dedup, pair_mode=False,
-           max_elems=1023):
+           max_elems=1023, max_inc=0):
     (me, rp, ci, ip, inc_k), nb, B, Pr = built
     d, nq, nme, nl = mesh.d, mesh.nq, mesh.nme, mesh.d + 1
     used = np.diff(rp) > 0
@@ -100,7 +100,7 @@ def _check(mesh, built, R, max_pairs, max_nodes, waves, slots, tri, dedup, pair_
     for v in left:   # a vertex is left over only when it cannot be a block row
         lv = rp[v + 1] - rp[v]
         assert lv > 511 or (max_pairs and lv > max_pairs) or (max_nodes and lv > max_nodes) or \
-            ip[v + 1] - ip[v] > max_elems
+            ip[v + 1] - ip[v] > max_elems or (max_inc and nl * (ip[v + 1] - ip[v]) > max_inc)
     for b in range(nb):
         rows = B["rows"][B["row_ptr"][b]:B["row_ptr"][b + 1]]
         assert 0 < len(rows) <= R and np.all(np.diff(rows) > 0)
@@ -109,6 +109,8 @@ def _check(mesh, built, R, max_pairs, max_nodes, waves, slots, tri, dedup, pair_
         lens = rp[rows + 1] - rp[rows]
         if max_pairs:
             assert lens.sum() <= max_pairs
+        if max_inc:   # growth cap: (d+1) x the rows' stars
+            assert nl * (ip[rows + 1] - ip[rows]).sum() <= max_inc
         # block elements: every element around a row, ascending
         ks = np.unique(np.concatenate([inc_k[ip[i]:ip[i + 1]] for i in rows]))
         el = B["elem"][4 * B["elem_ptr"][b]:4 * B["elem_ptr"][b + 1]].reshape(-1, 4)[:, :nl]
@@ -239,7 +241,7 @@ def test_unused_vertices_and_refusals(shim):
     sizes = np.zeros(10, np.int64)
     st = shim.hl_build(2, ctypes.c_int64(n + 1), ctypes.c_int64(n), _p(me), _p(rp), _p(ci),
                        _p(ip), _p(inc_k), 16, ctypes.c_int64(0), 0, 8, 2, 0, 1, ctypes.c_int64(8192),
-                       0, 1023, ctypes.c_int64(0), _p(sizes))
+                       0, 1023, ctypes.c_int64(0), ctypes.c_int64(0), _p(sizes))
     assert st == 1
     # pair mode keeps the mesh: the fan's centre is left over only when its
     # row exceeds a cap (here the 32-entry CSR cap of a block)
@@ -261,13 +263,15 @@ def _delaunay(d, npts, seed):
 
 
 PAIR_CASES = [
-    # (mesh, R, max_pairs, max_nodes, tri, max_elems, max_ent)
-    ("delaunay3d", 56, 1024, 256, True, 700, 8192),
-    ("delaunay3d", 48, 1024, 256, False, 600, 8192),
-    ("delaunay2d", 128, 1024, 256, True, 1023, 8192),
-    ("delaunay3d", 56, 1024, 256, True, 700, 2500),     # blocks beyond the entry cap
-    ("delaunay3d", 56, 1024, 24, True, 40, 8192),       # vertices beyond the node and element caps
-    ("cube5_perm", 56, 1024, 256, True, 700, 8192),
+    # (mesh, R, max_pairs, max_nodes, tri, max_elems, max_ent, max_inc)
+    ("delaunay3d", 64, 1024, 256, True, 700, 8192, 8192),
+    ("delaunay3d", 64, 1024, 256, False, 600, 8192, 8192),
+    ("delaunay2d", 128, 1024, 256, True, 1023, 8192, 8192),
+    ("delaunay3d", 56, 1024, 256, True, 700, 2500, 0),     # blocks beyond the entry cap
+    ("delaunay3d", 64, 1024, 256, True, 700, 2500, 2500),  # growth held under it
+    ("delaunay3d", 56, 1024, 24, True, 40, 8192, 8192),    # vertices beyond the node and element caps
+    ("delaunay3d", 64, 1024, 256, True, 700, 8192, 120),   # stars beyond the growth cap
+    ("cube5_perm", 64, 1024, 256, True, 700, 8192, 8192),
 ]
 PAIR_MESHES = {
     "delaunay3d": lambda: _delaunay(3, 600, 5),
@@ -277,23 +281,26 @@ PAIR_MESHES = {
 
 
 @pytest.mark.parametrize("case", PAIR_CASES, ids=[f"{c[0]}-R{c[1]}-n{c[3]}-e{c[5]}-ent{c[6]}"
-                                                  for c in PAIR_CASES])
+                                                  f"-inc{c[7]}" for c in PAIR_CASES])
 def test_pair_mode_against_brute_force(shim, case):
     """Pair mode on unstructured meshes (rows up to 511 entries): every CSR
     entry of a block row is listed or mirrored once; vertices beyond a cap and
     the rows of blocks beyond the task or entry caps are left over, and only
-    those."""
-    name, R, max_pairs, max_nodes, tri, max_elems, max_ent = case
+    those; with the growth cap (max_inc, as the library sets it) each block's
+    rows hold (d+1) x star sizes within it."""
+    name, R, max_pairs, max_nodes, tri, max_elems, max_ent, max_inc = case
     mesh = PAIR_MESHES[name]()
     built = _build(shim, mesh, R, max_pairs, max_nodes, 8, 2, tri, True, pair_mode=True,
-                   max_elems=max_elems, max_ent=max_ent)
+                   max_elems=max_elems, max_ent=max_ent, max_inc=max_inc)
     left = _check(mesh, built, R, max_pairs, max_nodes, 8, 2, tri, True, pair_mode=True,
-                  max_elems=max_elems)
+                  max_elems=max_elems, max_inc=max_inc)
     nb, Pr = built[1], built[3]
     print(f"{name}: max row {np.diff(built[0][1]).max()}, {nb} blocks, "
           f"{nb - int(Pr['blk_ok'].sum())} over a cap, {len(left)} rows left over")
-    if case[6] == 8192 and case[5] >= 600:
+    if case[6] == 8192 and case[5] >= 600 and case[7] == 8192:
         assert not left   # default caps: every row of these meshes is in a block
+    if max_inc == 120:
+        assert left   # the mesh has stars above 30 elements
 
 
 def _unpack_wave_starts(wp, waves):
