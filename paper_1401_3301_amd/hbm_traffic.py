@@ -5,7 +5,8 @@
 
 Each directory is a rocprofv3 ``--pmc ... --output-format csv`` output.
 FETCH_SIZE and WRITE_SIZE are read in KiB per dispatch, averaged over the
-dispatches of the named kernel, and scaled by the ratio of the true bytes of
+dispatches of the named kernel on the measured workload (those of the small
+warm-up mesh are left out), and scaled by the ratio of the true bytes of
 a plain device copy (``bench.py --copy-calibration``: 2^29 bytes read and
 written per copy) to what the same counters report for that copy.  The
 result, with the hash of the kernel sources the counters were taken on, is
@@ -30,7 +31,11 @@ def counter_mean(d: str, counter: str, kernel_sub: str) -> float:
             per[r["Dispatch_Id"]] = per.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
     if not per:
         raise SystemExit(f"no {counter} rows for kernel '{kernel_sub}' under {d}")
-    return sum(per.values()) / len(per)
+    # bench.py first runs the kernel on a small warm-up mesh: keep the
+    # dispatches of the measured workload only (within 4x of the largest)
+    top = max(per.values())
+    vals = [v for v in per.values() if v >= 0.25 * top]
+    return sum(vals) / len(vals)
 
 
 def main(argv):
