@@ -652,6 +652,18 @@ __global__ void __launch_bounds__(kPairWG) k_pair(PairView pv, double lam, doubl
     pair_run<D, OP, S>(pv, lam, mu, status, int(blockIdx.x), int(gridDim.x));
 }
 
+// The same kernel held to 128 VGPRs (four wavefronts per SIMD: two
+// 512-thread workgroups per compute unit), for the stiffness JVP: its
+// registers pass 128 by a few while its LDS allows two workgroups, and the
+// handful of spilled registers cost less than the lost occupancy (measured
+// on the 128^3 cube: 0.55 ms instead of 0.65; the weighted-mass JVP, whose
+// LDS admits one workgroup anyway, only loses by it).
+template <int D, int OP, int S>
+__global__ void __launch_bounds__(kPairWG, 4) k_pair2(PairView pv, double lam, double mu,
+                                                       int32_t *status) {
+    pair_run<D, OP, S>(pv, lam, mu, status, int(blockIdx.x), int(gridDim.x));
+}
+
 // One persistent launch over a 2D and a 3D layout (a batch with meshes of
 // both dimensions): every workgroup walks its share of the 2D blocks, then
 // its share of the 3D blocks, so the two parts balance over the whole grid.
@@ -757,13 +769,22 @@ hipError_t launch_pair_t(const PairPlan &P, const double *q, const double *w, co
     PairLds L = pair_lds<D, OP>(P);
     if (L.bytes > 160 * 1024) return hipErrorNotSupported;   // caller falls back
     const PairView pv = make_view<D, OP>(P, L, q, w, w2, gco, dq, values);
-    const void *fn = reinterpret_cast<const void *>(&k_pair<D, OP, S>);
+    constexpr bool kTwo = OP == kOpJvpStiff;
+    const void *fn;
+    if constexpr (kTwo)
+        fn = reinterpret_cast<const void *>(&k_pair2<D, OP, S>);
+    else
+        fn = reinterpret_cast<const void *>(&k_pair<D, OP, S>);
     // persistent grid: resident workgroups per CU x CUs, a multiple of the 8 XCDs
     int64_t grid = int64_t(resident_wgs(fn, L.bytes)) * device_cus() / 8 * 8;
     const int64_t need = (int64_t(P.nb) + 7) / 8 * 8;
     grid = std::max<int64_t>(8, std::min(grid, need));
-    hipLaunchKernelGGL((k_pair<D, OP, S>), dim3(unsigned(grid)), dim3(kPairWG), L.bytes, s, pv,
-                       lam, mu, status);
+    if constexpr (kTwo)
+        hipLaunchKernelGGL((k_pair2<D, OP, S>), dim3(unsigned(grid)), dim3(kPairWG), L.bytes, s,
+                           pv, lam, mu, status);
+    else
+        hipLaunchKernelGGL((k_pair<D, OP, S>), dim3(unsigned(grid)), dim3(kPairWG), L.bytes, s,
+                           pv, lam, mu, status);
     return hipGetLastError();
 }
 
