@@ -96,7 +96,7 @@ def cpu_baseline_sample(fn, units, unit, what):
             "sample": f"{what}, {dt:.1f} s"}
 
 
-NEXT_OPS = ("nodal", "general", "jvp", "vjp", "vjp_ws", "boundary")
+NEXT_OPS = ("nodal", "general", "jvp", "vjp", "vjp_ws", "vjp_slot", "boundary")
 
 
 def next_run(torch, femasm, mg, name, stream, steps, warmup):
@@ -124,12 +124,13 @@ def next_run(torch, femasm, mg, name, stream, steps, warmup):
         coef = [2.0, 0.3, -0.1, 0.2, 1.5, 0.4, -0.2, 0.1, 1.0, 0.5, -0.4, 0.3, 0.2, 0.6, -0.7, 0.8]
         fn = lambda: femasm.fem_assemble_general(plan.handle, q.data_ptr(), coef, out.data_ptr(), s)
         units = plan.nme
-    elif name in ("jvp", "vjp", "vjp_ws"):
+    elif name in ("jvp", "vjp", "vjp_ws", "vjp_slot"):
         _, nnz = plan.query("STIFF")
         gen = torch.Generator(device=dev).manual_seed(171)
         G = torch.randn(nnz, dtype=torch.float64, device=dev, generator=gen)
         dq = torch.randn(q.shape, dtype=torch.float64, device=dev, generator=gen)
         slot = plan.slot_map()
+        femasm.fem_plan_vjp_positions(plan.handle)   # vjp / vjp_ws: slot NULL, the plan's table
         dA = torch.empty(nnz, dtype=torch.float64, device=dev)
         gq = torch.empty_like(q)
         wbytes = femasm.fem_vjp_work_bytes(plan.handle, 2)
@@ -138,12 +139,13 @@ def next_run(torch, femasm, mg, name, stream, steps, warmup):
         if name == "jvp":
             fn = lambda: femasm.fem_assemble_jvp(plan.handle, 2, q.data_ptr(), None, dq.data_ptr(),
                                                 None, dA.data_ptr(), s)
-        elif name == "vjp":
+        elif name in ("vjp", "vjp_slot"):
+            sl = slot.data_ptr() if name == "vjp_slot" else None
             fn = lambda: femasm.fem_assemble_vjp(plan.handle, 2, q.data_ptr(), None, G.data_ptr(),
-                                                slot.data_ptr(), gq.data_ptr(), None, s)
+                                                sl, gq.data_ptr(), None, s)
         else:
             fn = lambda: femasm.fem_assemble_vjp_ws(plan.handle, 2, q.data_ptr(), None,
-                                                   G.data_ptr(), slot.data_ptr(), work.data_ptr(),
+                                                   G.data_ptr(), None, work.data_ptr(),
                                                    wbytes, gq.data_ptr(), None, s)
         units = plan.nme
     else:
@@ -216,22 +218,28 @@ def extras(torch, femasm, mg, plan, q, stream, steps, mesh):
     G = torch.randn(nnz_s, dtype=torch.float64, device=q.device, generator=gen)
     dq = torch.randn(q.shape, dtype=torch.float64, device=q.device, generator=gen)
     slot = plan.slot_map()
+    femasm.fem_plan_vjp_positions(plan.handle, stream.cuda_stream)
     dA = torch.empty(nnz_s, dtype=torch.float64, device=q.device)
     gq = torch.empty_like(q)
     fj = lambda: femasm.fem_assemble_jvp(plan.handle, 2, q.data_ptr(), None, dq.data_ptr(), None,
                                         dA.data_ptr(), stream.cuda_stream)
+    # the VJPs address G through the plan's position table (slot NULL); the
+    # slot-map form is timed beside them
     fv = lambda: femasm.fem_assemble_vjp(plan.handle, 2, q.data_ptr(), None, G.data_ptr(),
-                                        slot.data_ptr(), gq.data_ptr(), None, stream.cuda_stream)
+                                        None, gq.data_ptr(), None, stream.cuda_stream)
+    fvs = lambda: femasm.fem_assemble_vjp(plan.handle, 2, q.data_ptr(), None, G.data_ptr(),
+                                         slot.data_ptr(), gq.data_ptr(), None, stream.cuda_stream)
     wbytes = femasm.fem_vjp_work_bytes(plan.handle, 2)
     work = torch.empty(wbytes // 8, dtype=torch.float64, device=q.device)
     fvw = lambda: femasm.fem_assemble_vjp_ws(plan.handle, 2, q.data_ptr(), None, G.data_ptr(),
-                                             slot.data_ptr(), work.data_ptr(), wbytes,
+                                             None, work.data_ptr(), wbytes,
                                              gq.data_ptr(), None, stream.cuda_stream)
     _, pj = time_launches(fj, stream, 10, 2)
     _, pv = time_launches(fv, stream, 10, 2)
+    _, pvs = time_launches(fvs, stream, 10, 2)
     _, pvw = time_launches(fvw, stream, 10, 2)
     tj, tv = statistics.mean(pj) / 1e3, statistics.mean(pv) / 1e3
-    tvw = statistics.mean(pvw) / 1e3
+    tvs, tvw = statistics.mean(pvs) / 1e3, statistics.mean(pvw) / 1e3
     ab_j = 2 * 8 * 3 * plan.nq + 16 * plan.nme + 8 * nnz_s   # q, dq, me in; dA out
     ab_v = 2 * 8 * 3 * plan.nq + 16 * plan.nme + 8 * nnz_s   # q, me, G in; dL/dq out
     S = 200_000
@@ -243,6 +251,7 @@ def extras(torch, femasm, mg, plan, q, stream, steps, mesh):
         "jvp_ms": tj * 1e3, "vjp_ms": tv * 1e3,
         "jvp_elements_per_s": plan.nme / tj, "vjp_elements_per_s": plan.nme / tv,
         "jvp_frac": ab_j / tj / 1e9 / PEAK_HBM_GBS, "vjp_frac": ab_v / tv / 1e9 / PEAK_HBM_GBS,
+        "vjp_slot_map_ms": tvs * 1e3,
         "vjp_ws_ms": tvw * 1e3, "vjp_ws_elements_per_s": plan.nme / tvw,
         "vjp_ws_frac": ab_v / tvw / 1e9 / PEAK_HBM_GBS, "vjp_ws_work_bytes": wbytes,
         "cpu_baseline_jvp": cpu_baseline_sample(

@@ -231,7 +231,11 @@ fem_status fem_assemble_backward(fem_plan plan, uint32_t op_mask, const double *
  *   (eight partial sums, partial j over the vertex's incident elements j,
  *   j+8, ... in ascending element number, combined pairwise in a fixed
  *   tree), so bitwise reproducible.  slot is the plan's triplet-to-slot map (fem_plan_slot_map,
- *   (d+1)^2 * nme int32, device), computed once by the caller.
+ *   (d+1)^2 * nme int32, device), computed once by the caller; or NULL once
+ *   fem_plan_vjp_positions has run on the plan: the kernels then find each
+ *   upstream gradient entry through the plan's own per-element column
+ *   positions (the same addresses, read in the plan's element order rather
+ *   than the caller's), with identical outputs.
  * Both asynchronous, no allocation.  Errors: FEM_ERR_ARG (other op, null
  * arrays), FEM_ERR_OVERFLOW; degenerate elements as in
  * fem_assemble_numeric.
@@ -242,6 +246,21 @@ fem_status fem_assemble_jvp(fem_plan plan, int32_t op, const double *q, const do
 fem_status fem_assemble_vjp(fem_plan plan, int32_t op, const double *q, const double *w,
                             const double *G, const int32_t *slot, double *dLdq, double *dLdw,
                             hipStream_t stream);
+
+/*
+ * Builds, once per plan, the table that lets the VJP calls run without a
+ * caller slot map (slot = NULL): for every element in the plan's order and
+ * local entry (a, b), the position of vertex b within the CSR row of vertex
+ * a -- 8-bit when no row has more than 256 entries, else 16-bit; (d+1)^2
+ * bytes (or twice that) per element, owned and freed by the plan.  The
+ * table is a re-indexing of the slot map (Sections 3-4: the triplet-to-CSR
+ * step of `sparse`), kept in the order in which the VJP kernels visit the
+ * elements.  Allocates; the build kernel runs on `stream` and the call
+ * returns once it has completed, so later calls on any stream may use it.
+ * Later calls return FEM_OK at once.  Errors: FEM_ERR_ARG (null plan),
+ * FEM_ERR_NOMEM / FEM_ERR_DEVICE.
+ */
+fem_status fem_plan_vjp_positions(fem_plan plan, hipStream_t stream);
 
 /*
  * Workspace form of fem_assemble_vjp, for callers that can lend scratch

@@ -29,6 +29,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
+#include <type_traits>
 
 #include "element.h"
 #include "femasm_impl.h"
@@ -266,27 +267,58 @@ __device__ __forceinline__ void vjp_term(const VjpGeom<D> &V, const double (&Gk)
     }
 }
 
+// Where the VJP finds the upstream gradient of entry (a, b) of an element:
+// through the caller's slot map (indexed by caller element number), or,
+// when `slot` is null, through the plan's per-element column positions
+// (indexed by plan element number, next to the connectivity the kernels
+// read anyway) and the row pointers.  Both give the same address.
+struct GAddr {
+    const int32_t *slot;
+    const void *vpos;   // 8-bit (PB 1) or 16-bit (PB 2) positions
+};
+
+// The upstream gradient block Gk[a][b] of plan element e with vertices v;
+// PB: 0 slot map, 1 or 2 bytes per plan position.
+template <int D, int PB>
+__device__ __forceinline__ void vjp_gk(const MeshView &mv, const int32_t *__restrict__ porig,
+                                       const GAddr &ga, const double *__restrict__ G, int64_t e,
+                                       const int (&v)[D + 1], double (&Gk)[D + 1][D + 1]) {
+    constexpr int NL = D + 1;
+    if constexpr (PB == 0) {
+        const int64_t k = porig[e];
+#pragma unroll
+        for (int b = 0; b < NL; ++b)
+#pragma unroll
+            for (int a = 0; a < NL; ++a) Gk[a][b] = G[ga.slot[k * NL * NL + b * NL + a]];
+    } else {
+        using T = typename std::conditional<PB == 1, uint8_t, uint16_t>::type;
+        const T *pos = static_cast<const T *>(ga.vpos) + e * NL * NL;
+#pragma unroll
+        for (int a = 0; a < NL; ++a) {
+            const int64_t r0 = mv.rp[v[a]];
+#pragma unroll
+            for (int b = 0; b < NL; ++b) Gk[a][b] = G[r0 + pos[b * NL + a]];
+        }
+    }
+}
+
 // Loads of one element (internal number e) for the VJP: coordinates, the
-// upstream gradient block through the caller's slot map, nodal weights.
-template <int D, int OP>
+// upstream gradient block, nodal weights.
+template <int D, int OP, int PB>
 __device__ __forceinline__ void vjp_load(const MeshView &mv, const int32_t *__restrict__ porig,
-                                         const int32_t *__restrict__ slot,
-                                         const double *__restrict__ G, int64_t e,
+                                         const GAddr &ga, const double *__restrict__ G, int64_t e,
                                          double (&P)[D + 1][D], double (&Gk)[D + 1][D + 1],
                                          double (&wl)[D + 1]) {
     constexpr int NL = D + 1;
-    const int64_t k = porig[e];
-#pragma unroll
-    for (int b = 0; b < NL; ++b)
-#pragma unroll
-        for (int a = 0; a < NL; ++a) Gk[a][b] = G[slot[k * NL * NL + b * NL + a]];
+    int v[NL];
 #pragma unroll
     for (int b = 0; b < NL; ++b) {
-        const int v = mv.pme[e * NL + b];
+        v[b] = mv.pme[e * NL + b];
 #pragma unroll
-        for (int x = 0; x < D; ++x) P[b][x] = mv.q[x * mv.nq + v];
-        wl[b] = OP == FEM_OP_MASS_W ? mv.w[v] : 0.0;
+        for (int x = 0; x < D; ++x) P[b][x] = mv.q[x * mv.nq + v[b]];
+        wl[b] = OP == FEM_OP_MASS_W ? mv.w[v[b]] : 0.0;
     }
+    vjp_gk<D, PB>(mv, porig, ga, G, e, v, Gk);
 }
 
 // Lane-strided sums of one vertex's incidence terms, combined by shuffles in
@@ -309,9 +341,9 @@ __device__ __forceinline__ void vjp_store(const MeshView &mv, int64_t i, int j, 
     }
 }
 
-template <int D, int OP>
+template <int D, int OP, int PB>
 __global__ void __launch_bounds__(256)
-    k_vjp(MeshView mv, const int32_t *__restrict__ porig, const int32_t *__restrict__ slot,
+    k_vjp(MeshView mv, const int32_t *__restrict__ porig, GAddr ga,
           const double *__restrict__ G, double *__restrict__ dLdq, double *__restrict__ dLdw,
           int32_t *status) {
     constexpr int NL = D + 1;
@@ -328,12 +360,6 @@ __global__ void __launch_bounds__(256)
             const uint32_t ea = mv.inc_elem[t];
             const int64_t e = ea & 0x3fffffffu;
             const int al = int(ea >> 30);
-            const int64_t k = porig[e];
-            double Gk[NL][NL];
-#pragma unroll
-            for (int b = 0; b < NL; ++b)
-#pragma unroll
-                for (int a = 0; a < NL; ++a) Gk[a][b] = G[slot[k * NL * NL + b * NL + a]];
             int v[NL];
             double P[NL][D];
 #pragma unroll
@@ -342,6 +368,8 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
                 for (int x = 0; x < D; ++x) P[b][x] = mv.q[x * nq + v[b]];
             }
+            double Gk[NL][NL];
+            vjp_gk<D, PB>(mv, porig, ga, G, e, v, Gk);
             Elem<D> E;
             elem_geometry(P, E);
             if (E.det == 0.0) {
@@ -443,18 +471,17 @@ __global__ void __launch_bounds__(256)
 // Workspace VJP, element pass: one thread per element (plan order e) writes
 // the terms of its d+1 vertices to work[(e*(d+1) + a)*NW + ...], NW = d
 // (+1 for the weighted mass); zeros for a degenerate element.
-template <int D, int OP>
+template <int D, int OP, int PB>
 __global__ void __launch_bounds__(256)
-    k_vjp_elem(MeshView mv, int64_t nme, const int32_t *__restrict__ porig,
-               const int32_t *__restrict__ slot, const double *__restrict__ G,
-               double *__restrict__ work, int32_t *status) {
+    k_vjp_elem(MeshView mv, int64_t nme, const int32_t *__restrict__ porig, GAddr ga,
+               const double *__restrict__ G, double *__restrict__ work, int32_t *status) {
     constexpr int NL = D + 1;
     constexpr int NW = D + (OP == FEM_OP_MASS_W ? 1 : 0);
     const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     int bad = 0;
     if (e < nme) {
         double P[NL][D], Gk[NL][NL], wl[NL];
-        vjp_load<D, OP>(mv, porig, slot, G, e, P, Gk, wl);
+        vjp_load<D, OP, PB>(mv, porig, ga, G, e, P, Gk, wl);
         VjpGeom<D> V;
         double *out = work + e * NL * NW;
         if (!vjp_geometry<D>(P, V)) {
@@ -534,30 +561,59 @@ hipError_t launch_jvp(const fem_plan_s *p, int op, const MeshView &mv, const dou
     return hipGetLastError();
 }
 
-template <int D>
-hipError_t launch_vjp(const fem_plan_s *p, int op, const MeshView &mv, const int32_t *slot,
-                      const double *G, double *dLdq, double *dLdw, hipStream_t s) {
+// PB of a gradient addresser: the slot map, or the plan's positions
+int addr_kind(const fem_plan_s *p, const GAddr &ga) {
+    return ga.slot ? 0 : (p->vpos_bytes.load(std::memory_order_acquire) == 1 ? 1 : 2);
+}
+
+template <int D, int OP, int PB>
+void launch_vjp_t(const fem_plan_s *p, const MeshView &mv, const GAddr &ga, const double *G,
+                  double *dLdq, double *dLdw, hipStream_t s) {
     const unsigned grid = unsigned((p->nq * kVjpLanes + 255) / 256);
-    if (op == FEM_OP_MASS)
-        hipLaunchKernelGGL((k_vjp<D, FEM_OP_MASS>), dim3(grid), dim3(256), 0, s, mv, p->porig,
-                           slot, G, dLdq, dLdw, p->status);
-    else if (op == FEM_OP_MASS_W)
-        hipLaunchKernelGGL((k_vjp<D, FEM_OP_MASS_W>), dim3(grid), dim3(256), 0, s, mv, p->porig,
-                           slot, G, dLdq, dLdw, p->status);
-    else
-        hipLaunchKernelGGL((k_vjp<D, FEM_OP_STIFF>), dim3(grid), dim3(256), 0, s, mv, p->porig,
-                           slot, G, dLdq, dLdw, p->status);
-    return hipGetLastError();
+    hipLaunchKernelGGL((k_vjp<D, OP, PB>), dim3(grid), dim3(256), 0, s, mv, p->porig, ga, G,
+                       dLdq, dLdw, p->status);
 }
 
 template <int D, int OP>
-hipError_t launch_vjp_ws_t(const fem_plan_s *p, const MeshView &mv, const int32_t *slot,
+void launch_vjp_pb(const fem_plan_s *p, const MeshView &mv, const GAddr &ga, const double *G,
+                   double *dLdq, double *dLdw, hipStream_t s) {
+    switch (addr_kind(p, ga)) {
+    case 0: launch_vjp_t<D, OP, 0>(p, mv, ga, G, dLdq, dLdw, s); break;
+    case 1: launch_vjp_t<D, OP, 1>(p, mv, ga, G, dLdq, dLdw, s); break;
+    default: launch_vjp_t<D, OP, 2>(p, mv, ga, G, dLdq, dLdw, s); break;
+    }
+}
+
+template <int D>
+hipError_t launch_vjp(const fem_plan_s *p, int op, const MeshView &mv, const GAddr &ga,
+                      const double *G, double *dLdq, double *dLdw, hipStream_t s) {
+    if (op == FEM_OP_MASS)
+        launch_vjp_pb<D, FEM_OP_MASS>(p, mv, ga, G, dLdq, dLdw, s);
+    else if (op == FEM_OP_MASS_W)
+        launch_vjp_pb<D, FEM_OP_MASS_W>(p, mv, ga, G, dLdq, dLdw, s);
+    else
+        launch_vjp_pb<D, FEM_OP_STIFF>(p, mv, ga, G, dLdq, dLdw, s);
+    return hipGetLastError();
+}
+
+template <int D, int OP, int PB>
+void launch_vjp_elem_t(const fem_plan_s *p, const MeshView &mv, const GAddr &ga,
+                       const double *G, double *work, hipStream_t s) {
+    const unsigned ge = unsigned((p->nme + 255) / 256);
+    hipLaunchKernelGGL((k_vjp_elem<D, OP, PB>), dim3(ge), dim3(256), 0, s, mv, p->nme, p->porig,
+                       ga, G, work, p->status);
+}
+
+template <int D, int OP>
+hipError_t launch_vjp_ws_t(const fem_plan_s *p, const MeshView &mv, const GAddr &ga,
                            const double *G, double *work, double *dLdq, double *dLdw,
                            hipStream_t s) {
     if (p->nme > 0) {
-        const unsigned ge = unsigned((p->nme + 255) / 256);
-        hipLaunchKernelGGL((k_vjp_elem<D, OP>), dim3(ge), dim3(256), 0, s, mv, p->nme, p->porig,
-                           slot, G, work, p->status);
+        switch (addr_kind(p, ga)) {
+        case 0: launch_vjp_elem_t<D, OP, 0>(p, mv, ga, G, work, s); break;
+        case 1: launch_vjp_elem_t<D, OP, 1>(p, mv, ga, G, work, s); break;
+        default: launch_vjp_elem_t<D, OP, 2>(p, mv, ga, G, work, s); break;
+        }
     }
     const unsigned gv = unsigned((p->nq * kVjpLanes + 255) / 256);
     hipLaunchKernelGGL((k_vjp_gather<D, OP>), dim3(gv), dim3(256), 0, s, mv, work, dLdq, dLdw);
@@ -565,14 +621,41 @@ hipError_t launch_vjp_ws_t(const fem_plan_s *p, const MeshView &mv, const int32_
 }
 
 template <int D>
-hipError_t launch_vjp_ws(const fem_plan_s *p, int op, const MeshView &mv, const int32_t *slot,
+hipError_t launch_vjp_ws(const fem_plan_s *p, int op, const MeshView &mv, const GAddr &ga,
                          const double *G, double *work, double *dLdq, double *dLdw,
                          hipStream_t s) {
     if (op == FEM_OP_MASS)
-        return launch_vjp_ws_t<D, FEM_OP_MASS>(p, mv, slot, G, work, dLdq, dLdw, s);
+        return launch_vjp_ws_t<D, FEM_OP_MASS>(p, mv, ga, G, work, dLdq, dLdw, s);
     if (op == FEM_OP_MASS_W)
-        return launch_vjp_ws_t<D, FEM_OP_MASS_W>(p, mv, slot, G, work, dLdq, dLdw, s);
-    return launch_vjp_ws_t<D, FEM_OP_STIFF>(p, mv, slot, G, work, dLdq, dLdw, s);
+        return launch_vjp_ws_t<D, FEM_OP_MASS_W>(p, mv, ga, G, work, dLdq, dLdw, s);
+    return launch_vjp_ws_t<D, FEM_OP_STIFF>(p, mv, ga, G, work, dLdq, dLdw, s);
+}
+
+// The plan's per-element column positions, from the incidence records: the
+// incidence (vertex of local index a, element e) holds the positions of the
+// element's vertices b within that vertex's row.
+template <class T>
+__global__ void k_vjp_positions(const uint32_t *__restrict__ inc_elem,
+                                const uint64_t *__restrict__ inc_off, int64_t ninc, int NL,
+                                T *__restrict__ vpos) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= ninc) return;
+    const uint32_t ea = inc_elem[t];
+    const int64_t e = ea & 0x3fffffffu;
+    const int a = int(ea >> 30);
+    const uint64_t off = inc_off[t];
+    for (int b = 0; b < NL; ++b) vpos[e * NL * NL + b * NL + a] = T((off >> (16 * b)) & 0xffffu);
+}
+
+// The gradient addresser of a VJP call: the caller's map, or (slot null) the
+// plan's positions, which fem_plan_vjp_positions must have built.
+bool vjp_addr(const fem_plan_s *p, const int32_t *slot, GAddr *ga) {
+    ga->slot = slot;
+    ga->vpos = nullptr;
+    if (slot) return true;
+    if (p->vpos_bytes.load(std::memory_order_acquire) == 0) return false;
+    ga->vpos = p->vpos;
+    return true;
 }
 
 bool deriv_op(int32_t op) { return op == FEM_OP_MASS || op == FEM_OP_MASS_W || op == FEM_OP_STIFF; }
@@ -659,11 +742,13 @@ static fem_status fem_assemble_vjp_impl(fem_plan plan, int32_t op, const double 
     PhaseRange range("femasm: VJP");
     if (!plan || !deriv_op(op)) return FEM_ERR_ARG;
     if (plan->nq == 0) return FEM_OK;
-    if (!q || (plan->nnz > 0 && (!G || !slot)) || (op == FEM_OP_MASS_W && !w)) return FEM_ERR_ARG;
+    GAddr ga{slot, nullptr};
+    if (!q || (plan->nnz > 0 && (!G || !vjp_addr(plan, slot, &ga))) || (op == FEM_OP_MASS_W && !w))
+        return FEM_ERR_ARG;
     if (op != FEM_OP_MASS_W) dLdw = nullptr;
     const MeshView mv = deriv_view(plan, q, w, nullptr);
-    const hipError_t e = plan->d == 2 ? launch_vjp<2>(plan, op, mv, slot, G, dLdq, dLdw, stream)
-                                      : launch_vjp<3>(plan, op, mv, slot, G, dLdq, dLdw, stream);
+    const hipError_t e = plan->d == 2 ? launch_vjp<2>(plan, op, mv, ga, G, dLdq, dLdw, stream)
+                                      : launch_vjp<3>(plan, op, mv, ga, G, dLdq, dLdw, stream);
     return hip_status(e);
 }
 
@@ -672,6 +757,40 @@ extern "C" fem_status fem_assemble_vjp(fem_plan plan, int32_t op, const double *
                                        double *dLdw, hipStream_t stream) {
     return debug_check(fem_assemble_vjp_impl(plan, op, q, w, G, slot, dLdq, dLdw, stream),
                        stream, plan ? plan->status : nullptr);
+}
+
+extern "C" fem_status fem_plan_vjp_positions(fem_plan plan, hipStream_t stream) {
+    if (!plan) return FEM_ERR_ARG;
+    if (plan->vpos_bytes.load(std::memory_order_acquire) != 0) return FEM_OK;
+    std::lock_guard<std::mutex> lock(plan->vpos_mu);
+    if (plan->vpos_bytes.load(std::memory_order_acquire) != 0) return FEM_OK;
+    const int NL = plan->d + 1;
+    const int bytes = plan->max_row <= 256 ? 1 : 2;
+    const int64_t n = int64_t(NL) * NL * plan->nme, ninc = int64_t(NL) * plan->nme;
+    void *buf = nullptr;
+    if (n > 0) {
+        hipError_t e = hipMalloc(&buf, size_t(n) * bytes);
+        if (e != hipSuccess) return hip_status(e);
+        const unsigned grid = unsigned((ninc + 255) / 256);
+        if (bytes == 1)
+            hipLaunchKernelGGL(k_vjp_positions<uint8_t>, dim3(grid), dim3(256), 0, stream,
+                               plan->inc_elem, plan->inc_off, ninc, NL,
+                               static_cast<uint8_t *>(buf));
+        else
+            hipLaunchKernelGGL(k_vjp_positions<uint16_t>, dim3(grid), dim3(256), 0, stream,
+                               plan->inc_elem, plan->inc_off, ninc, NL,
+                               static_cast<uint16_t *>(buf));
+        e = hipGetLastError();
+        // complete before any stream may read it
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) {
+            (void)hipFree(buf);
+            return hip_status(e);
+        }
+    }
+    plan->vpos = buf;
+    plan->vpos_bytes.store(bytes, std::memory_order_release);
+    return FEM_OK;
 }
 
 extern "C" fem_status fem_vjp_work_bytes(fem_plan plan, int32_t op, int64_t *bytes) {
@@ -686,15 +805,17 @@ extern "C" fem_status fem_assemble_vjp_ws(fem_plan plan, int32_t op, const doubl
                                           double *dLdw, hipStream_t stream) {
     if (!plan || !deriv_op(op)) return FEM_ERR_ARG;
     if (plan->nq == 0) return FEM_OK;
-    if (!q || (plan->nnz > 0 && (!G || !slot)) || (op == FEM_OP_MASS_W && !w)) return FEM_ERR_ARG;
+    GAddr ga{slot, nullptr};
+    if (!q || (plan->nnz > 0 && (!G || !vjp_addr(plan, slot, &ga))) || (op == FEM_OP_MASS_W && !w))
+        return FEM_ERR_ARG;
     if (plan->nme > 0 && (!work || work_bytes < vjp_work_bytes(plan, op) ||
                           (reinterpret_cast<uintptr_t>(work) & 7u) != 0))
         return FEM_ERR_ARG;
     if (op != FEM_OP_MASS_W) dLdw = nullptr;
     const MeshView mv = deriv_view(plan, q, w, nullptr);
     const hipError_t e =
-        plan->d == 2 ? launch_vjp_ws<2>(plan, op, mv, slot, G, work, dLdq, dLdw, stream)
-                     : launch_vjp_ws<3>(plan, op, mv, slot, G, work, dLdq, dLdw, stream);
+        plan->d == 2 ? launch_vjp_ws<2>(plan, op, mv, ga, G, work, dLdq, dLdw, stream)
+                     : launch_vjp_ws<3>(plan, op, mv, ga, G, work, dLdq, dLdw, stream);
     return hip_status(e);
 }
 
@@ -704,7 +825,9 @@ extern "C" fem_status fem_assemble_vjp_noalloc(fem_plan plan, int32_t op, const 
                                                hipStream_t stream) {
     if (!plan || !deriv_op(op)) return FEM_ERR_ARG;
     if (plan->nq == 0) return FEM_OK;
-    if (!q || (plan->nnz > 0 && (!G || !slot)) || (op == FEM_OP_MASS_W && !w)) return FEM_ERR_ARG;
+    GAddr ga{slot, nullptr};
+    if (!q || (plan->nnz > 0 && (!G || !vjp_addr(plan, slot, &ga))) || (op == FEM_OP_MASS_W && !w))
+        return FEM_ERR_ARG;
     if (vjp_work_bytes(plan, op) > kVjpScratchBytes) return FEM_ERR_OVERFLOW;
     double *work = nullptr;
     if (plan->nme > 0) {
@@ -714,7 +837,7 @@ extern "C" fem_status fem_assemble_vjp_noalloc(fem_plan plan, int32_t op, const 
     if (op != FEM_OP_MASS_W) dLdw = nullptr;
     const MeshView mv = deriv_view(plan, q, w, nullptr);
     const hipError_t e =
-        plan->d == 2 ? launch_vjp_ws<2>(plan, op, mv, slot, G, work, dLdq, dLdw, stream)
-                     : launch_vjp_ws<3>(plan, op, mv, slot, G, work, dLdq, dLdw, stream);
+        plan->d == 2 ? launch_vjp_ws<2>(plan, op, mv, ga, G, work, dLdq, dLdw, stream)
+                     : launch_vjp_ws<3>(plan, op, mv, ga, G, work, dLdq, dLdw, stream);
     return hip_status(e);
 }

@@ -146,6 +146,13 @@ struct fem_plan_data {
     uint64_t *inc_off = nullptr;  // [(d+1)*nme] bits 16b..16b+15: position of local vertex b in the row
     int32_t *status = nullptr;    // [2] sticky error word, then a scratch word of the symbolic phase
     double *part = nullptr;       // [d*nq/256 + 1] row-block partial sums of fem_csr_bilinear
+    // [(d+1)^2*nme] per plan element e, at e*(d+1)^2 + b*(d+1) + a: the
+    // position of vertex b within the CSR row of vertex a -- 8-bit when no
+    // row has more than 256 entries, else 16-bit (vpos_bytes, 0 until
+    // fem_plan_vjp_positions builds it; published with release order)
+    void *vpos = nullptr;
+    std::atomic<int> vpos_bytes{0};
+    std::mutex vpos_mu;
     std::vector<int32_t> h_rp;    // host copy of rp (launch geometry)
     RowLaunch launch[4];          // indexed by M
     BlockPlan blk;                // block-kernel layout (scalar operators)

@@ -51,7 +51,7 @@ void parallel_ranges(int64_t n, F fn) {
 void free_plan_arrays(fem_plan_data *p) {
     if (p->layout_thread.joinable()) p->layout_thread.join();
     void *ptrs[] = {p->rp,       p->ci,      p->pme,    p->porig, p->inc_ptr,
-                    p->inc_elem, p->inc_off, p->status, p->part};
+                    p->inc_elem, p->inc_off, p->status, p->part, p->vpos};
     for (void *x : ptrs)
         if (x) (void)hipFree(x);
     p->rp = p->ci = p->pme = p->porig = p->inc_ptr = nullptr;
@@ -59,6 +59,8 @@ void free_plan_arrays(fem_plan_data *p) {
     p->inc_off = nullptr;
     p->status = nullptr;
     p->part = nullptr;
+    p->vpos = nullptr;
+    p->vpos_bytes.store(0);
     free_blocks(&p->blk);
     free_pairs(&p->pscal);
     free_pairs(&p->pvec);

@@ -54,6 +54,7 @@ _SIGS = {
     "fem_plan_info": ([P, C.POINTER(I32), C.POINTER(I64), C.POINTER(I64), C.POINTER(I32)], C.c_int),
     "fem_plan_pattern": ([P, I32, P, P, P], C.c_int),
     "fem_plan_slot_map": ([P, P, P], C.c_int),
+    "fem_plan_vjp_positions": ([P, P], C.c_int),
     "fem_assemble_numeric": ([P, I32, P, P, D, D, P, P], C.c_int),
     "fem_assemble_elasticity_nodal": ([P, P, P, P, P, P], C.c_int),
     "fem_assemble_general": ([P, P, P, P, P], C.c_int),
@@ -166,6 +167,10 @@ def fem_plan_pattern(plan: int, op: int, row_ptr: int, col_idx: int, stream=None
 
 def fem_plan_slot_map(plan: int, slot: int, stream=None):
     _check(load_library().fem_plan_slot_map(plan, slot, _stream(stream)), "fem_plan_slot_map")
+
+
+def fem_plan_vjp_positions(plan: int, stream=None):
+    _check(load_library().fem_plan_vjp_positions(plan, _stream(stream)), "fem_plan_vjp_positions")
 
 
 def fem_assemble_numeric(plan: int, op: int, q: int, w: int | None, lam: float, mu: float,
@@ -469,21 +474,23 @@ class Plan:
     def vjp(self, op, q, G, w=None, slot=None, want_w=True, stream=None, work=None):
         """Gradient of sum(G * A) with respect to q (d, nq) and, for MASS_W, w.
         With `work` (a device tensor of at least vjp_work_bytes(op) bytes) the
-        workspace form runs: the same values, each element evaluated once."""
+        workspace form runs: the same values, each element evaluated once.
+        Without `slot` the kernels address G through the plan's position
+        table (built on first use); with it, through that slot map."""
         if slot is None:
-            slot = self.slot_map(stream)
+            fem_plan_vjp_positions(self.handle, stream)
         q, w, G = (_dev_f64(x, self.device) for x in (q, w, G))
         gq = torch.empty(self.d, self.nq, dtype=torch.float64, device=self.device)
         gw = (torch.empty(self.nq, dtype=torch.float64, device=self.device)
               if (_op(op) == FEM_OP["MASS_W"] and want_w) else None)
         if work is None:
             fem_assemble_vjp(self.handle, _op(op), q.data_ptr(), _ptr(w), G.data_ptr(),
-                             slot.data_ptr(), gq.data_ptr(), _ptr(gw), stream)
+                             _ptr(slot), gq.data_ptr(), _ptr(gw), stream)
         else:
             if not work.is_cuda:
                 raise ValueError("work must be a device tensor")
             fem_assemble_vjp_ws(self.handle, _op(op), q.data_ptr(), _ptr(w), G.data_ptr(),
-                                slot.data_ptr(), work.data_ptr(),
+                                _ptr(slot), work.data_ptr(),
                                 work.numel() * work.element_size(), gq.data_ptr(), _ptr(gw),
                                 stream)
         return gq, gw

@@ -166,3 +166,55 @@ def test_vjp_workspace_errors_and_empty_mesh():
                       torch.zeros(0, dtype=torch.float64, device=DEV),
                       work=torch.empty(1, dtype=torch.float64, device=DEV))
     assert not torch.any(gq)
+
+
+def _fan2d(m):
+    t = 2 * np.pi * np.arange(m) / m
+    q = np.concatenate([[[0.0], [0.0]], np.stack([np.cos(t), np.sin(t)])], axis=1)
+    i = np.arange(m)
+    me = np.stack([np.zeros(m, int), 1 + i, 1 + (i + 1) % m]).astype(np.int32)
+    return mg.Mesh(2, q, me)
+
+
+POS_MESHES = dict(MESHES, fan2d_300=lambda: _fan2d(300))   # hub row of 301: 16-bit positions
+
+
+@pytest.mark.parametrize("name", sorted(POS_MESHES))
+@pytest.mark.parametrize("op", OPS)
+def test_vjp_position_table_matches_slot_map(name, op):
+    """The VJPs address the upstream gradient either through the caller's
+    slot map or, with slot NULL, through the plan's per-element position
+    table (8-bit, or 16-bit when a row passes 256 entries): same values bit
+    for bit, in both the per-vertex and the workspace form, and within the
+    bound of the oracle."""
+    mesh = POS_MESHES[name]()
+    rng, w, dq, dw, plan = _setup(mesh, 172)
+    wt = w if op == "MASS_W" else None
+    rp, ci = (x.cpu().numpy() for x in plan.pattern(op))
+    G = rng.standard_normal(len(ci))
+    Gt = torch.from_numpy(G).to(DEV)
+    q = torch.from_numpy(mesh.q).to(DEV)
+    slot = plan.slot_map()
+    # slot NULL before the table exists is refused
+    gq0 = torch.empty(mesh.d, mesh.nq, dtype=torch.float64, device=DEV)
+    with pytest.raises(femasm.FemError) as e:
+        femasm.fem_assemble_vjp(plan.handle, femasm.FEM_OP[op], q.data_ptr(),
+                                None if wt is None else torch.from_numpy(wt).to(DEV).data_ptr(),
+                                Gt.data_ptr(), None, gq0.data_ptr(), None, None)
+    assert e.value.name == "FEM_ERR_ARG"
+    work = torch.empty(plan.vjp_work_bytes(op) // 8 + 1, dtype=torch.float64, device=DEV)
+    ref = plan.vjp(op, mesh.q, G, wt, slot=slot)
+    ref_ws = plan.vjp(op, mesh.q, G, wt, slot=slot, work=work)
+    got = plan.vjp(op, mesh.q, G, wt)                 # builds the table, slot NULL
+    got_ws = plan.vjp(op, mesh.q, G, wt, work=work)
+    plan.sync_status()
+    for a, b, c in zip(ref, got, got_ws):
+        if a is None:
+            continue
+        assert torch.equal(a, b) and torch.equal(a, c), f"{name} {op}"
+    assert torch.equal(ref_ws[0], got_ws[0])
+    oq, ow, oqa, owa = oracle.vjp(mesh.q, mesh.me, op, rp, ci, G, w=wt)
+    assert_parity(got[0].cpu().numpy().ravel(), oq.ravel(), oqa.ravel(),
+                  what=f"VJP table {op} {name}")
+    femasm.fem_plan_vjp_positions(plan.handle)        # a second build is a no-op
+    assert torch.equal(plan.vjp(op, mesh.q, G, wt)[0], got[0])
