@@ -234,10 +234,10 @@ def extras(torch, femasm, mg, plan, q, stream, steps, mesh):
     fvw = lambda: femasm.fem_assemble_vjp_ws(plan.handle, 2, q.data_ptr(), None, G.data_ptr(),
                                              None, work.data_ptr(), wbytes,
                                              gq.data_ptr(), None, stream.cuda_stream)
-    _, pj = time_launches(fj, stream, 10, 2)
-    _, pv = time_launches(fv, stream, 10, 2)
-    _, pvs = time_launches(fvs, stream, 10, 2)
-    _, pvw = time_launches(fvw, stream, 10, 2)
+    _, pj = time_launches(fj, stream, 20, 5)
+    _, pv = time_launches(fv, stream, 10, 3)
+    _, pvs = time_launches(fvs, stream, 10, 3)
+    _, pvw = time_launches(fvw, stream, 10, 3)
     tj, tv = statistics.mean(pj) / 1e3, statistics.mean(pv) / 1e3
     tvs, tvw = statistics.mean(pvs) / 1e3, statistics.mean(pvw) / 1e3
     ab_j = 2 * 8 * 3 * plan.nq + 16 * plan.nme + 8 * nnz_s   # q, dq, me in; dA out
