@@ -250,6 +250,150 @@ __global__ __launch_bounds__(kPkThreads) void k_pk_mass(
     }
 }
 
+// Pipelined form of k_pk_mass, for the plans with a large C (the highest
+// degrees): the same sums in the same order, with three tiles in flight, so
+// that the gathers of the element factors, which depend on the items, no
+// longer wait a full memory latency at every tile.  What it holds for one
+// tile in flight: its item range, the item offsets of the thread's entries,
+// the items and, once gathered, their element factors (|det B_K|, or the
+// element value).
+struct PkTile {
+    int64_t t, i0;
+    int ni;
+    uint32_t r0[kPkPer], r1[kPkPer];   // raw item offsets of the entry and the next one
+    uint32_t x[kPkRegs];
+    double f[kPkRegs];
+};
+
+__global__ __launch_bounds__(kPkThreads) void k_pk_mass_pipe(
+    const int64_t *__restrict__ tile_item, const uint16_t *__restrict__ coff,
+    const uint32_t *__restrict__ item, const double *__restrict__ ctri, int ntri, int ebits,
+    int chunk, const double *__restrict__ vol, const double *__restrict__ ev, int64_t ntiles,
+    int64_t nnz, double *__restrict__ values) {
+    extern __shared__ double lds[];
+    double *sc = lds;                    // C, packed triangle
+    double *sp = lds + ntri;             // products of the current chunk
+    const int tid = threadIdx.x;
+    const uint32_t emask = (1u << ebits) - 1u;
+    for (int t = tid; t < ntri; t += kPkThreads) sc[t] = ctri[t];
+
+    // items (and entry offsets) of tile t
+    // (the entry offsets are loaded unconditionally, clamped, and only
+    // interpreted when the tile is summed: nothing here waits for a load)
+    auto fetch = [&](PkTile &T, int64_t t) {
+        T.t = t;
+        T.i0 = tile_item[t];
+        T.ni = int(tile_item[t + 1] - T.i0);
+#pragma unroll
+        for (int j = 0; j < kPkPer; ++j) {
+            const int64_t s = t * kPkTile + tid + kPkThreads * j;
+            T.r0[j] = coff[min(s, nnz - 1)];
+            T.r1[j] = coff[min(s + 1, nnz - 1)];
+        }
+        const int cn = min(chunk, T.ni);
+#pragma unroll
+        for (int r = 0; r < kPkRegs; ++r) {
+            const int u = tid + kPkThreads * r;
+            T.x[r] = u < cn ? item[T.i0 + u] : 0u;
+        }
+    };
+    // element factors of a fetched tile's first chunk
+    // (one load per item, its address chosen first: two loads into the same
+    // register on the two sides of a branch would make the compiler wait for
+    // every load in flight before the second)
+    const double *fsrc = ev ? ev : vol;
+    auto gather = [&](PkTile &T) {
+        const int cn = min(chunk, T.ni);
+#pragma unroll
+        for (int r = 0; r < kPkRegs; ++r) {
+            const int u = tid + kPkThreads * r;
+            const int64_t e = T.x[r] & emask;
+            const int64_t o = ev ? e * ntri + (T.x[r] >> ebits) : e;
+            T.f[r] = u < cn ? fsrc[o] : 0.0;
+        }
+    };
+
+    // Three tiles in flight: A (items and factors in registers), B (items;
+    // its factors are gathered while A is summed), C (items loaded while A is
+    // summed).  Each load has a whole tile's work to arrive.
+    const int64_t G = gridDim.x;
+    int64_t tile = blockIdx.x;
+    PkTile A, B, C;
+    if (tile >= ntiles) return;
+    fetch(A, tile);
+    gather(A);
+    fetch(B, min(tile + G, ntiles - 1));
+    // one tile: X current, Y next, Z the one after (the roles rotate over
+    // three unrolled steps, so no tile's registers are copied)
+    auto step = [&](PkTile &X, PkTile &Y, PkTile &Z) __attribute__((always_inline)) {
+        // the loads of the previous step (X's factors, Y's items) are in
+        __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0); expcnt, lgkmcnt unlimited
+        const int64_t ti0 = X.i0;
+        const int tni = X.ni;
+        // item range of each entry: [c0, c1), tile-relative
+        int c0[kPkPer], c1[kPkPer];
+#pragma unroll
+        for (int j = 0; j < kPkPer; ++j) {
+            const int l = tid + kPkThreads * j;
+            const int64_t s = tile * kPkTile + l;
+            c0[j] = s < nnz ? int(X.r0[j]) : 0;
+            c1[j] = s < nnz ? ((l + 1 < kPkTile && s + 1 < nnz) ? int(X.r1[j]) : tni) : 0;
+        }
+        __syncthreads();                 // sc ready; the previous tile is done with sp
+        {
+            const int cn = min(chunk, tni);
+#pragma unroll
+            for (int r = 0; r < kPkRegs; ++r) {
+                const int u = tid + kPkThreads * r;
+                if (u < cn) sp[u] = ev ? X.f[r] : X.f[r] * sc[X.x[r] >> ebits];
+            }
+        }
+        // (unconditional, the tile index clamped: the registers of a tile past
+        // the end are never used, and no branch merges them)
+        gather(Y);
+        fetch(Z, min(tile + 2 * G, ntiles - 1));
+        __syncthreads();
+        double acc[kPkPer];
+#pragma unroll
+        for (int j = 0; j < kPkPer; ++j) {
+            acc[j] = 0.0;
+            const int hi = min(c1[j], chunk);
+            for (int c = c0[j]; c < hi; ++c) acc[j] += sp[c];
+        }
+        for (int cb = chunk; cb < tni; cb += chunk) {     // tiles with more items than a chunk
+            const int cn = min(chunk, tni - cb);
+            __syncthreads();
+            for (int u = tid; u < cn; u += kPkThreads) {
+                const uint32_t xx = item[ti0 + cb + u];
+                sp[u] = ev ? ev[int64_t(xx & emask) * ntri + (xx >> ebits)]
+                           : vol[xx & emask] * sc[xx >> ebits];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < kPkPer; ++j) {
+                const int lo = max(c0[j], cb), hi = min(c1[j], cb + cn);
+                for (int c = lo; c < hi; ++c) acc[j] += sp[c - cb];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kPkPer; ++j) {
+            const int64_t s = tile * kPkTile + tid + kPkThreads * j;
+            if (s < nnz) values[s] = acc[j];
+        }
+    };
+    for (;;) {
+        if (tile >= ntiles) break;
+        step(A, B, C);
+        tile += G;
+        if (tile >= ntiles) break;
+        step(B, C, A);
+        tile += G;
+        if (tile >= ntiles) break;
+        step(C, A, B);
+        tile += G;
+    }
+}
+
 // Items per chunk: as many as fit next to C in kPkLdsBudget bytes of LDS
 // (a multiple of the workgroup size, between one per thread and kPkMaxChunk).
 constexpr size_t kPkLdsBudget = 40 * 1024;
@@ -260,24 +404,24 @@ inline int pk_chunk(int ntri) {
     return int(c);
 }
 
-int pk_grid(size_t lds, int64_t ntiles) {
-    static thread_local int cached = 0;
-    static thread_local size_t cached_lds = 0;
-    if (cached == 0 || cached_lds != lds) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_pk_mass),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+int pk_grid(const void *fn, size_t lds, int64_t ntiles) {
+    static thread_local int cached[2] = {0, 0};
+    static thread_local size_t cached_lds[2] = {0, 0};
+    const int ci = fn == reinterpret_cast<const void *>(&k_pk_mass) ? 0 : 1;
+    if (cached[ci] == 0 || cached_lds[ci] != lds) {
+        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         int n = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(&k_pk_mass),
-                                                         kPkThreads, lds) != hipSuccess || n < 1)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, kPkThreads, lds) != hipSuccess ||
+            n < 1)
             n = 1;
-        cached = n;
-        cached_lds = lds;
+        cached[ci] = n;
+        cached_lds[ci] = lds;
     }
     int dev = 0, cus = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (cus < 1) cus = 1;
-    return int(std::max<int64_t>(1, std::min<int64_t>(ntiles, int64_t(cached) * cus)));
+    return int(std::max<int64_t>(1, std::min<int64_t>(ntiles, int64_t(cached[ci]) * cus)));
 }
 
 }  // namespace
@@ -347,11 +491,24 @@ fem_status pk_build(int sdim, int d, int k, bool boundary, int64_t nq, int64_t n
 fem_status pk_sum(fem_pk_plan plan, double *values, hipStream_t stream) {
     const int chunk = pk_chunk(plan->ntri);
     const size_t lds = sizeof(double) * (size_t(plan->ntri) + size_t(chunk));
-    const int grid = pk_grid(lds, plan->ntiles);
-    hipLaunchKernelGGL(k_pk_mass, dim3(grid), dim3(kPkThreads), lds, stream, plan->tile_item,
-                       plan->coff, plan->item, plan->ctri, plan->ntri, plan->ebits, chunk,
-                       plan->boundary ? nullptr : plan->vol, plan->boundary ? plan->ev : nullptr,
-                       plan->ntiles, plan->nnz, values);
+    // Large C (3D P5 and P6: 1596 and 3570 packed entries) takes the
+    // pipelined kernel, the others the plain one (measured on 10^6 nodes:
+    // P5 0.41 ms instead of 0.46, P6 0.50 instead of 0.61; P1-P4 were slower
+    // pipelined, P1 0.40 instead of 0.30, P4 0.314 instead of 0.310)
+    const bool pipe = plan->ntri >= 1024;
+    const void *fn = pipe ? reinterpret_cast<const void *>(&k_pk_mass_pipe)
+                          : reinterpret_cast<const void *>(&k_pk_mass);
+    const int grid = pk_grid(fn, lds, plan->ntiles);
+    if (pipe)
+        hipLaunchKernelGGL(k_pk_mass_pipe, dim3(grid), dim3(kPkThreads), lds, stream,
+                           plan->tile_item, plan->coff, plan->item, plan->ctri, plan->ntri,
+                           plan->ebits, chunk, plan->boundary ? nullptr : plan->vol,
+                           plan->boundary ? plan->ev : nullptr, plan->ntiles, plan->nnz, values);
+    else
+        hipLaunchKernelGGL(k_pk_mass, dim3(grid), dim3(kPkThreads), lds, stream, plan->tile_item,
+                           plan->coff, plan->item, plan->ctri, plan->ntri, plan->ebits, chunk,
+                           plan->boundary ? nullptr : plan->vol,
+                           plan->boundary ? plan->ev : nullptr, plan->ntiles, plan->nnz, values);
     return hip_status(hipGetLastError());
 }
 
