@@ -106,13 +106,16 @@ __global__ void k_inc_elem(const uint32_t *__restrict__ sslot, int64_t n, int NL
     inc_elem[t] = uint32_t(pinv[k]) | (a << 30);
 }
 
-// Candidate u of row i: vertex b = u mod NL of the row's incidence u / NL.
-__device__ __forceinline__ uint32_t candidate(const int32_t *__restrict__ me, int64_t nme, int NL,
-                                              const uint32_t *__restrict__ sslot, int64_t t0,
+// Candidate u of row i: vertex b = u mod NL of the row's incidence u / NL,
+// read from the plan-order connectivity (an element's vertices are
+// contiguous there, and the elements around a vertex lie close together in
+// plan order; the caller's layout would cost d+1 scattered reads).
+__device__ __forceinline__ uint32_t candidate(const int32_t *__restrict__ pme, int NL,
+                                              const uint32_t *__restrict__ inc_elem, int64_t t0,
                                               int u) {
     const int s = u / NL, b = u - s * NL;
-    const int64_t k = sslot[t0 + s] / uint32_t(NL);
-    return uint32_t(me[int64_t(b) * nme + k]);
+    const int64_t q = inc_elem[t0 + s] & 0x3fffffffu;
+    return uint32_t(pme[q * NL + b]);
 }
 
 // One wavefront per row (rows with at most kRowCap candidates).  Count pass:
@@ -120,8 +123,8 @@ __device__ __forceinline__ uint32_t candidate(const int32_t *__restrict__ me, in
 // `longrows` for the workgroup pass.  Fill pass: ci and the 16-bit positions.
 template <bool FILL>
 __global__ void __launch_bounds__(kPatWG)
-    k_row_pattern(const int32_t *__restrict__ me, int64_t nme, int NL, int64_t nq,
-                  const int32_t *__restrict__ ip, const uint32_t *__restrict__ sslot,
+    k_row_pattern(const int32_t *__restrict__ pme, int NL, int64_t nq,
+                  const int32_t *__restrict__ ip, const uint32_t *__restrict__ inc_elem,
                   int64_t *__restrict__ rowlen, const int64_t *__restrict__ rp64,
                   int32_t *__restrict__ ci, uint16_t *__restrict__ pos16,
                   int32_t *__restrict__ longrows, int32_t *__restrict__ nlong) {
@@ -142,7 +145,7 @@ __global__ void __launch_bounds__(kPatWG)
 #pragma unroll
         for (int s = 0; s < kRowSlots; ++s) {
             const int u = lane + 64 * s;
-            c[s] = u < n ? candidate(me, nme, NL, sslot, t0, u) : 0xffffffffu;
+            c[s] = u < n ? candidate(pme, NL, inc_elem, t0, u) : 0xffffffffu;
             dup[s] = false;
         }
         // dup: an earlier candidate has the same vertex
@@ -199,8 +202,8 @@ __global__ void __launch_bounds__(kPatWG)
 // One workgroup per long row, its candidates in LDS (n <= kLongCap).
 template <bool FILL>
 __global__ void __launch_bounds__(kPatWG)
-    k_row_pattern_long(const int32_t *__restrict__ me, int64_t nme, int NL,
-                       const int32_t *__restrict__ ip, const uint32_t *__restrict__ sslot,
+    k_row_pattern_long(const int32_t *__restrict__ pme, int NL,
+                       const int32_t *__restrict__ ip, const uint32_t *__restrict__ inc_elem,
                        const int32_t *__restrict__ longrows, int64_t *__restrict__ rowlen,
                        const int64_t *__restrict__ rp64, int32_t *__restrict__ ci,
                        uint16_t *__restrict__ pos16, int32_t *__restrict__ flag) {
@@ -215,7 +218,7 @@ __global__ void __launch_bounds__(kPatWG)
         if (threadIdx.x == 0) atomicOr(flag, 2);
         return;
     }
-    for (int u = threadIdx.x; u < n; u += kPatWG) cand[u] = candidate(me, nme, NL, sslot, t0, u);
+    for (int u = threadIdx.x; u < n; u += kPatWG) cand[u] = candidate(pme, NL, inc_elem, t0, u);
     __syncthreads();
     int cnt = 0;
     for (int u = threadIdx.x; u < n; u += kPatWG) {
@@ -371,8 +374,8 @@ fem_status build_pattern_gpu(fem_plan_data *p, const int32_t *me, hipStream_t s)
     uint16_t *pos16 = reinterpret_cast<uint16_t *>(p->inc_off);
     const unsigned rgrid = unsigned(std::min<int64_t>(std::max<int64_t>(grid_for(nq, kPatWG / 64), 1), 8192));
     if (nq > 0) {
-        hipLaunchKernelGGL(k_row_pattern<false>, dim3(rgrid), dim3(kPatWG), 0, s, me, nme, NL, nq, ip,
-                           svals, rowlen, rp64, p->ci, pos16, longrows, nlong);
+        hipLaunchKernelGGL(k_row_pattern<false>, dim3(rgrid), dim3(kPatWG), 0, s, p->pme, NL, nq, ip,
+                           p->inc_elem, rowlen, rp64, p->ci, pos16, longrows, nlong);
         FEM_TRY(hipGetLastError());
     }
     int32_t hlong = 0;
@@ -385,7 +388,7 @@ fem_status build_pattern_gpu(fem_plan_data *p, const int32_t *me, hipStream_t s)
         (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_row_pattern_long<true>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, int(long_lds));
         hipLaunchKernelGGL(k_row_pattern_long<false>, dim3(unsigned(hlong)), dim3(kPatWG), long_lds, s,
-                           me, nme, NL, ip, svals, longrows, rowlen, rp64, p->ci, pos16, flag);
+                           p->pme, NL, ip, p->inc_elem, longrows, rowlen, rp64, p->ci, pos16, flag);
         FEM_TRY(hipGetLastError());
     }
     {
@@ -404,13 +407,13 @@ fem_status build_pattern_gpu(fem_plan_data *p, const int32_t *me, hipStream_t s)
     p->nnz = nnz;
     FEM_TRY(hipMalloc(reinterpret_cast<void **>(&p->ci), sizeof(int32_t) * std::max<int64_t>(nnz, 1)));
     if (nq > 0) {
-        hipLaunchKernelGGL(k_row_pattern<true>, dim3(rgrid), dim3(kPatWG), 0, s, me, nme, NL, nq, ip,
-                           svals, rowlen, rp64, p->ci, pos16, longrows, nlong);
+        hipLaunchKernelGGL(k_row_pattern<true>, dim3(rgrid), dim3(kPatWG), 0, s, p->pme, NL, nq, ip,
+                           p->inc_elem, rowlen, rp64, p->ci, pos16, longrows, nlong);
         FEM_TRY(hipGetLastError());
     }
     if (hlong > 0) {
         hipLaunchKernelGGL(k_row_pattern_long<true>, dim3(unsigned(hlong)), dim3(kPatWG), long_lds, s,
-                           me, nme, NL, ip, svals, longrows, rowlen, rp64, p->ci, pos16, flag);
+                           p->pme, NL, ip, p->inc_elem, longrows, rowlen, rp64, p->ci, pos16, flag);
         FEM_TRY(hipGetLastError());
     }
     hipLaunchKernelGGL(k_rp32, dim3(grid_for(nq + 1)), dim3(kPatWG), 0, s, rp64, nq + 1, p->rp);
