@@ -1,7 +1,8 @@
 """GPU parity of the pair kernel across its layout settings: rows per block
-(FEMASM_PAIR_ROWS / FEMASM_ELAS_ROWS, 16..128) and 64-pair tasks per
-wavefront (FEMASM_PAIR_SLOTS / FEMASM_ELAS_SLOTS, 1, 2 or 4), read when a
-plan is built.  Every setting must give the oracle's matrix: the settings
+(FEMASM_PAIR_ROWS / FEMASM_ELAS_ROWS, 16..128), 64-pair tasks per
+wavefront (FEMASM_PAIR_SLOTS / FEMASM_ELAS_SLOTS, 1, 2 or 4) and the 3D
+element caps (FEMASM_PAIR_ELEMS / FEMASM_ELAS_ELEMS), read when a plan is
+built.  Every setting must give the oracle's matrix: the settings
 change the blocking, the task deal and the descriptor's packed wavefront
 task starts, never the summation order of an entry."""
 import numpy as np
@@ -25,16 +26,21 @@ MESHES = {
     "square70": lambda: mg.jittered_square(70, 0.2, seed=12),
     "cube11_perm": lambda: mg.kuhn_cube(11, 0.15, seed=13, perm_seed=5),
 }
-KNOBS = [(16, 1), (56, 4), (128, 2), (128, 4)]
+# (rows, slots, 3D element cap or None for the default)
+KNOBS = [(16, 1, None), (56, 4, None), (128, 2, None), (128, 4, None), (64, 2, 100), (96, 4, 250)]
 
 
-@pytest.mark.parametrize("rows,slots", KNOBS, ids=[f"R{r}-s{s}" for r, s in KNOBS])
+@pytest.mark.parametrize("rows,slots,elems", KNOBS,
+                         ids=[f"R{r}-s{s}" + (f"-e{e}" if e else "") for r, s, e in KNOBS])
 @pytest.mark.parametrize("name", list(MESHES))
-def test_layout_settings_keep_parity(monkeypatch, name, rows, slots):
+def test_layout_settings_keep_parity(monkeypatch, name, rows, slots, elems):
     for var in ("FEMASM_PAIR_ROWS", "FEMASM_ELAS_ROWS"):
         monkeypatch.setenv(var, str(rows))
     for var in ("FEMASM_PAIR_SLOTS", "FEMASM_ELAS_SLOTS"):
         monkeypatch.setenv(var, str(slots))
+    if elems:
+        for var in ("FEMASM_PAIR_ELEMS", "FEMASM_ELAS_ELEMS"):
+            monkeypatch.setenv(var, str(elems))
     mesh = MESHES[name]()
     d = mesh.d
     print(f"layout {name} rows {rows} slots {slots}", flush=True)
@@ -42,6 +48,7 @@ def test_layout_settings_keep_parity(monkeypatch, name, rows, slots):
     q = torch.from_numpy(np.ascontiguousarray(mesh.q)).to(DEV)
     w = mg.lognormal_field(mesh.nq, 31)
     plan = femasm.Plan(me, mesh.nq)
+    assert plan.layouts() == 1, f"{name}: no block layouts"
     for op in ("MASS", "MASS_W", "STIFF", "ELAS"):
         wt = w if op == "MASS_W" else None
         rp, ci = plan.pattern(op)
