@@ -333,6 +333,7 @@ __device__ __forceinline__ void pair_run(const PairView &pv, double lam, double 
     constexpr bool kW = OP == FEM_OP_MASS_W || OP == kOpElasNodal || OP == kOpJvpMassW;
     constexpr bool kW2 = OP == kOpElasNodal || OP == kOpJvpMassW;
     constexpr bool kDQ = is_jvp(OP);
+    constexpr bool kScalarSum = !(OP == FEM_OP_ELAS || OP == kOpElasNodal || OP == kOpGeneral);
     constexpr int kDqOff = (kW ? 1 : 0) + (kW2 ? 1 : 0);   // tangents after w and w2
     extern __shared__ __align__(16) unsigned char smem[];
     double *crd = reinterpret_cast<double *>(smem);
@@ -526,7 +527,71 @@ __device__ __forceinline__ void pair_run(const PairView &pv, double lam, double 
         for (int s = 0; s < S; ++s) {
 #pragma unroll
             for (int t = 0; t < NX; ++t) X[s][t] = 0.0;
-            if (s < ns) {
+            if (s < ns && kScalarSum) {
+                // four list entries per step: their values are read together
+                // and added one after another in list (ascending element)
+                // order, so a long list (a diagonal pair's) waits for one LDS
+                // round trip per four entries instead of per entry
+                const uint16_t *lst = ent + eoff[s] + lane;
+                const int C = cnt[s], Cm = C - 1;
+                auto val = [&](uint32_t x) { return ev[int(x & 1023u) * NV + int((x >> 10) & 15u)]; };
+                uint32_t x0 = lst[0], x1 = lst[min(1, Cm) * 64], x2 = lst[min(2, Cm) * 64],
+                         x3 = lst[min(3, Cm) * 64];
+                double acc = 0.0;
+                int t = 0;
+                for (; t + 4 <= C; t += 4) {
+                    const double v0 = val(x0), v1 = val(x1), v2 = val(x2), v3 = val(x3);
+                    x0 = lst[min(t + 4, Cm) * 64];
+                    x1 = lst[min(t + 5, Cm) * 64];
+                    x2 = lst[min(t + 6, Cm) * 64];
+                    x3 = lst[min(t + 7, Cm) * 64];
+                    acc += v0;
+                    acc += v1;
+                    acc += v2;
+                    acc += v3;
+                }
+                if (t < C) acc += val(x0);
+                if (t + 1 < C) acc += val(x1);
+                if (t + 2 < C) acc += val(x2);
+                X[s][0] = acc;
+            } else if (s < ns && OP == FEM_OP_ELAS) {
+                // two list entries per step: both entries' rows of c-hat are
+                // read together, then each accumulator takes the first entry's
+                // product and the second's, in list order
+                const uint16_t *lst = ent + eoff[s] + lane;
+                const int C = cnt[s], Cm = C - 1;
+                auto rows = [&](uint32_t x, double *A, double *B) {
+                    const double *Ee = ev + int(x & 1023u) * NV;
+                    const int a = int((x >> 10) & 3u), b = int((x >> 12) & 3u);
+#pragma unroll
+                    for (int c = 0; c < D; ++c) {
+                        A[c] = Ee[a * D + c];
+                        B[c] = Ee[b * D + c];
+                    }
+                };
+                auto acc = [&](const double *A, const double *B) {
+#pragma unroll
+                    for (int l = 0; l < D; ++l)
+#pragma unroll
+                        for (int n = 0; n < D; ++n) X[s][l * D + n] = fma(A[l], B[n], X[s][l * D + n]);
+                };
+                uint32_t x0 = lst[0], x1 = lst[min(1, Cm) * 64];
+                int t = 0;
+                for (; t + 2 <= C; t += 2) {
+                    double A0[D], B0[D], A1[D], B1[D];
+                    rows(x0, A0, B0);
+                    rows(x1, A1, B1);
+                    x0 = lst[min(t + 2, Cm) * 64];
+                    x1 = lst[min(t + 3, Cm) * 64];
+                    acc(A0, B0);
+                    acc(A1, B1);
+                }
+                if (t < C) {
+                    double A0[D], B0[D];
+                    rows(x0, A0, B0);
+                    acc(A0, B0);
+                }
+            } else if (s < ns) {
                 const uint16_t *lst = ent + eoff[s] + lane;
                 const int C = cnt[s];
                 uint32_t x = lst[0];
