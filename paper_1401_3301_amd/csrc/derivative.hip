@@ -48,6 +48,7 @@ namespace {
 // 1.97 ms against 3.04 ms with four on the 128^3 cube; sixteen gain
 // nothing more.
 constexpr int kVjpLanes = 8;
+constexpr int kVjpElemWG = 256;   // threads (elements) per workgroup of k_vjp_elem
 
 template <int D, int OP>
 __global__ void __launch_bounds__(256) k_jvp(MeshView mv, const double *__restrict__ dq,
@@ -472,22 +473,28 @@ __global__ void __launch_bounds__(256)
 // the terms of its d+1 vertices to work[(e*(d+1) + a)*NW + ...], NW = d
 // (+1 for the weighted mass); zeros for a degenerate element.
 template <int D, int OP, int PB>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kVjpElemWG)
     k_vjp_elem(MeshView mv, int64_t nme, const int32_t *__restrict__ porig, GAddr ga,
                const double *__restrict__ G, double *__restrict__ work, int32_t *status) {
     constexpr int NL = D + 1;
     constexpr int NW = D + (OP == FEM_OP_MASS_W ? 1 : 0);
-    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    constexpr int NT = NL * NW;   // doubles per element
+    // the workgroup's terms are staged in LDS and written out as one
+    // contiguous run (a thread's own NT doubles would leave as NT stores
+    // whose lanes lie NT * 8 bytes apart)
+    __shared__ double stage[kVjpElemWG * NT];
+    const int64_t e0 = int64_t(blockIdx.x) * kVjpElemWG;
+    const int64_t e = e0 + threadIdx.x;
     int bad = 0;
     if (e < nme) {
         double P[NL][D], Gk[NL][NL], wl[NL];
         vjp_load<D, OP, PB>(mv, porig, ga, G, e, P, Gk, wl);
         VjpGeom<D> V;
-        double *out = work + e * NL * NW;
+        double *out = stage + threadIdx.x * NT;
         if (!vjp_geometry<D>(P, V)) {
             bad = 1;
 #pragma unroll
-            for (int u = 0; u < NL * NW; ++u) out[u] = 0.0;
+            for (int u = 0; u < NT; ++u) out[u] = 0.0;
         } else {
 #pragma unroll
             for (int al = 0; al < NL; ++al) {
@@ -499,6 +506,10 @@ __global__ void __launch_bounds__(256)
             }
         }
     }
+    __syncthreads();
+    const int64_t n = (nme - e0 < kVjpElemWG ? nme - e0 : kVjpElemWG) * NT;
+    double *dst = work + e0 * NT;
+    for (int64_t u = threadIdx.x; u < n; u += kVjpElemWG) dst[u] = stage[u];
     const unsigned long long any = __ballot(bad != 0);
     if (any != 0ull && (threadIdx.x & 63) == __ffsll((long long)any) - 1) atomicOr(status, bad);
 }
@@ -599,8 +610,8 @@ hipError_t launch_vjp(const fem_plan_s *p, int op, const MeshView &mv, const GAd
 template <int D, int OP, int PB>
 void launch_vjp_elem_t(const fem_plan_s *p, const MeshView &mv, const GAddr &ga,
                        const double *G, double *work, hipStream_t s) {
-    const unsigned ge = unsigned((p->nme + 255) / 256);
-    hipLaunchKernelGGL((k_vjp_elem<D, OP, PB>), dim3(ge), dim3(256), 0, s, mv, p->nme, p->porig,
+    const unsigned ge = unsigned((p->nme + kVjpElemWG - 1) / kVjpElemWG);
+    hipLaunchKernelGGL((k_vjp_elem<D, OP, PB>), dim3(ge), dim3(kVjpElemWG), 0, s, mv, p->nme, p->porig,
                        ga, G, work, p->status);
 }
 
