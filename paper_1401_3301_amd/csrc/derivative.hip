@@ -49,6 +49,7 @@ namespace {
 // nothing more.
 constexpr int kVjpLanes = 8;
 constexpr int kVjpElemWG = 256;   // threads (elements) per workgroup of k_vjp_elem
+constexpr int kGatherDepth = 4;    // incidences per lane in flight in k_vjp_gather
 
 template <int D, int OP>
 __global__ void __launch_bounds__(256) k_jvp(MeshView mv, const double *__restrict__ dq,
@@ -529,13 +530,31 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
     for (int x = 0; x < D; ++x) gq[x] = 0.0;
     if (i < mv.nq) {
-        for (int t = mv.inc_ptr[i] + j; t < mv.inc_ptr[i + 1]; t += kVjpLanes) {
-            const uint32_t ea = mv.inc_elem[t];
-            const int64_t e = ea & 0x3fffffffu;
-            const double *in = work + (e * NL + int(ea >> 30)) * NW;
+        const int t1 = mv.inc_ptr[i + 1];
+        // kGatherDepth of the lane's incidences per step: their words, then
+        // their records, are loaded together (past the lane's last incidence
+        // the loads repeat the step's first and the adds are skipped), and
+        // the terms are added in incidence order
+        for (int t = mv.inc_ptr[i] + j; t < t1; t += kGatherDepth * kVjpLanes) {
+            const double *in[kGatherDepth];
 #pragma unroll
-            for (int x = 0; x < D; ++x) gq[x] += in[x];
-            if constexpr (OP == FEM_OP_MASS_W) gw += in[D];
+            for (int u = 0; u < kGatherDepth; ++u) {
+                const int tu = t + u * kVjpLanes;
+                const uint32_t ea = mv.inc_elem[tu < t1 ? tu : t];
+                in[u] = work + (int64_t(ea & 0x3fffffffu) * NL + int(ea >> 30)) * NW;
+            }
+            double r[kGatherDepth][NW];
+#pragma unroll
+            for (int u = 0; u < kGatherDepth; ++u)
+#pragma unroll
+                for (int x = 0; x < NW; ++x) r[u][x] = in[u][x];
+#pragma unroll
+            for (int u = 0; u < kGatherDepth; ++u)
+                if (t + u * kVjpLanes < t1) {
+#pragma unroll
+                    for (int x = 0; x < D; ++x) gq[x] += r[u][x];
+                    if constexpr (OP == FEM_OP_MASS_W) gw += r[u][D];
+                }
         }
     }
     vjp_store<D>(mv, i, j, gq, gw, dLdq, dLdw);
