@@ -412,7 +412,10 @@ void fem_batch_destroy(fem_batch batch);
 typedef struct fem_pk_plan_s *fem_pk_plan;
 
 /* Symbolic phase of the P_k mass: validates me, builds the CSR pattern and
- * the per-entry contribution lists.  Synchronous.
+ * the per-entry contribution lists.  For k = 1 it also makes a P1 plan of the
+ * same mesh (as fem_assemble_symbolic, block layouts waited for) whose
+ * pattern it checks equal to its own; fem_pk_mass then runs the P1 mass
+ * kernels of that plan.  Synchronous.
  *   d    2 or 3;  k  1..6
  *   nq   number of P_k nodes;  nme  number of elements
  *   me   device, N*nme int32 (layout above)
@@ -434,10 +437,12 @@ fem_status fem_pk_pattern(fem_pk_plan plan, int32_t *row_ptr, int32_t *col_idx,
 
 /* CSR values of the P_k mass matrix for node coordinates q (device, d*nq
  * doubles) into values (device, nnz doubles, fully overwritten).  Two
- * kernels on `stream` (element volumes, then the entry sums); no host
- * synchronisation, no allocation.  A degenerate element (det B_K == 0)
- * contributes 0 and sets the plan's status word (fem_pk_sync_status).
- * Concurrent calls with one plan race on its volume work array. */
+ * kernels on `stream` (element volumes, then the entry sums), or for k = 1
+ * the P1 mass kernels of the plan's P1 plan (the same matrix: same pattern,
+ * each entry summed in ascending element number); no host synchronisation,
+ * no allocation.  A degenerate element (det B_K == 0) contributes 0 and sets
+ * the plan's status word (fem_pk_sync_status).  Concurrent calls with one
+ * plan race on its volume work array. */
 fem_status fem_pk_mass(fem_pk_plan plan, const double *q, double *values, hipStream_t stream);
 
 /* Synchronises `stream`, reads and clears the plan's status word:

@@ -49,6 +49,9 @@ struct fem_pk_data {
     double *vol = nullptr;          // [nme] |det B_K| (work array of the numeric phase)
     double *ev = nullptr;           // boundary plans: [nme*ntri] element matrices (work array)
     int32_t *status = nullptr;
+    // k = 1 (volume meshes): the P1 plan whose mass kernels serve fem_pk_mass
+    // (the P_k mass of degree 1 is the P1 mass), null if it could not be made
+    fem_plan p1 = nullptr;
 };
 
 namespace {
@@ -66,6 +69,8 @@ fem_status pk_upload(T **dst, const std::vector<T> &src) {
 }
 
 void pk_free(fem_pk_data *p) {
+    fem_plan_destroy(p->p1);
+    p->p1 = nullptr;
     void *ptrs[] = {p->rp,   p->ci,   p->gme, p->tile_item, p->coff,
                     p->item, p->ctri, p->vol, p->ev,        p->status};
     for (void *x : ptrs)
@@ -433,6 +438,41 @@ struct fem_pk_plan_s : femasm::fem_pk_data {};
 
 namespace {
 
+// The P1 plan of a degree-1 mesh, its block layouts built (waited for), and
+// its CSR pattern checked equal to the P_k plan's (rp, ci); null when any of
+// that fails (fem_pk_mass then keeps the P_k kernels).
+fem_plan pk_p1_plan(int d, int64_t nq, int64_t nme, const int32_t *me,
+                    const std::vector<int32_t> &rp, const std::vector<int32_t> &ci,
+                    hipStream_t stream) {
+    fem_plan q1 = nullptr;
+    if (fem_assemble_symbolic(d, nq, nme, me, stream, &q1) != FEM_OK) return nullptr;
+    int32_t state = 0;
+    int64_t nrows = 0, nnz = 0;
+    bool same = fem_plan_layouts(q1, 1, &state) == FEM_OK &&
+                fem_plan_query(q1, FEM_OP_MASS, &nrows, &nnz) == FEM_OK && nrows == nq &&
+                nnz == int64_t(ci.size()) && rp.size() == size_t(nq) + 1;
+    if (same) {
+        int32_t *drp = nullptr, *dci = nullptr;
+        std::vector<int32_t> hrp(rp.size()), hci(ci.size());
+        hipError_t e = hipMalloc(reinterpret_cast<void **>(&drp), sizeof(int32_t) * hrp.size());
+        if (e == hipSuccess)
+            e = hipMalloc(reinterpret_cast<void **>(&dci), sizeof(int32_t) * std::max<size_t>(1, hci.size()));
+        same = e == hipSuccess && fem_plan_pattern(q1, FEM_OP_MASS, drp, dci, stream) == FEM_OK &&
+               hipMemcpyAsync(hrp.data(), drp, sizeof(int32_t) * hrp.size(), hipMemcpyDeviceToHost,
+                              stream) == hipSuccess &&
+               hipMemcpyAsync(hci.data(), dci, sizeof(int32_t) * hci.size(), hipMemcpyDeviceToHost,
+                              stream) == hipSuccess &&
+               hipStreamSynchronize(stream) == hipSuccess && hrp == rp && hci == ci;
+        if (drp) (void)hipFree(drp);
+        if (dci) (void)hipFree(dci);
+    }
+    if (!same) {
+        fem_plan_destroy(q1);
+        return nullptr;
+    }
+    return q1;
+}
+
 // Plan over an N x nme connectivity of sdim-simplices (sdim = d for P_k
 // meshes, d - 1 for boundary facets) with d coordinates per node.
 fem_status pk_build(int sdim, int d, int k, bool boundary, int64_t nq, int64_t nme,
@@ -484,6 +524,7 @@ fem_status pk_build(int sdim, int d, int k, bool boundary, int64_t nq, int64_t n
         pk_free(p.get());
         return st;
     }
+    if (!boundary && k == 1 && nme > 0) p->p1 = pk_p1_plan(d, nq, nme, me, H.rp, H.ci, stream);
     *out = p.release();
     return FEM_OK;
 }
@@ -605,6 +646,8 @@ extern "C" fem_status fem_pk_mass(fem_pk_plan plan, const double *q, double *val
     if (!plan || plan->boundary || (plan->nme > 0 && !q) || (plan->nnz > 0 && !values))
         return FEM_ERR_ARG;
     if (plan->nnz == 0) return FEM_OK;
+    if (plan->p1)   // degree 1: the P1 mass kernels (same pattern, same summation order)
+        return fem_assemble_numeric(plan->p1, FEM_OP_MASS, q, nullptr, 0.0, 0.0, values, stream);
     if (plan->nme > 0) {
         const unsigned g = unsigned((plan->nme + 255) / 256);
         if (plan->d == 2)
@@ -621,6 +664,9 @@ extern "C" fem_status fem_pk_mass(fem_pk_plan plan, const double *q, double *val
 
 extern "C" fem_status fem_pk_sync_status(fem_pk_plan plan, hipStream_t stream) {
     if (!plan) return FEM_ERR_ARG;
+    // degree 1: the P1 plan's status word first (read and cleared)
+    const fem_status s1 = plan->p1 ? fem_plan_sync_status(plan->p1, stream) : FEM_OK;
+    if (s1 != FEM_OK && s1 != FEM_ERR_DEGENERATE) return s1;
     int32_t word = 0;
     hipError_t e = hipStreamSynchronize(stream);
     if (e == hipSuccess) e = hipMemcpy(&word, plan->status, sizeof(int32_t), hipMemcpyDeviceToHost);
@@ -629,7 +675,7 @@ extern "C" fem_status fem_pk_sync_status(fem_pk_plan plan, hipStream_t stream) {
         e = hipMemcpy(plan->status, &zero, sizeof(int32_t), hipMemcpyHostToDevice);
     }
     if (e != hipSuccess) return hip_status(e);
-    return word ? FEM_ERR_DEGENERATE : FEM_OK;
+    return word || s1 == FEM_ERR_DEGENERATE ? FEM_ERR_DEGENERATE : FEM_OK;
 }
 
 extern "C" void fem_pk_destroy(fem_pk_plan plan) {

@@ -98,7 +98,7 @@ def test_pk_empty_degenerate_and_errors():
     assert e.value.name == "FEM_ERR_ARG"
 
 
-@pytest.mark.parametrize("k,n", [(2, 50), (3, 33)])
+@pytest.mark.parametrize("k,n", [(1, 99), (2, 50), (3, 33)])
 def test_pk_full_size_sampled_rows(k, n):
     """About 1e6 P_k nodes (3D): sampled rows against the oracle."""
     m = mg.config_pk(k, n)["mesh"]
@@ -113,3 +113,24 @@ def test_pk_full_size_sampled_rows(k, n):
     assert_parity(got, ov, oav, what=f"P{k} full-size rows")
     # size-independent: sum of all entries = volume of the unit cube
     assert abs(v.sum() - 1.0) < 1e-10
+
+
+def test_pk_degree_one_is_the_p1_mass():
+    """For k = 1 fem_pk_mass runs the P1 mass kernels of a P1 plan of the same
+    mesh: the pattern and the values are those of Plan.numeric("MASS") bit for
+    bit, and a degenerate element is reported (then cleared) through
+    fem_pk_sync_status."""
+    for m in (mg.kuhn_cube(12, 0.15, seed=5, perm_seed=6), mg.jittered_square(30, 0.2, seed=7)):
+        plan, q, rp, ci, v = _run(m, 1)
+        p1 = femasm.Plan(torch.from_numpy(np.ascontiguousarray(m.me)).to(DEV), m.nq)
+        rp1, ci1 = p1.pattern("MASS")
+        assert np.array_equal(rp, rp1.cpu().numpy()) and np.array_equal(ci, ci1.cpu().numpy())
+        assert np.array_equal(v, p1.numeric("MASS", q).cpu().numpy()), f"d={m.d}"
+        qb = m.q.copy()
+        qb[:, m.me[1, 3]] = qb[:, m.me[0, 3]]
+        plan.mass(torch.from_numpy(qb).to(DEV))
+        with pytest.raises(femasm.FemError) as e:
+            plan.sync_status()
+        assert e.value.name == "FEM_ERR_DEGENERATE"
+        plan.sync_status()   # cleared
+        assert np.array_equal(plan.mass(q).cpu().numpy(), v)
