@@ -453,7 +453,25 @@ __device__ __forceinline__ void pair_run(const PairView &pv, double lam, double 
         if (bn >= 0) issue_coords(dn);
         // L3: output image of the previous block to HBM
         if (have_prev) {
-            for (int kk = tid; kk < M2 * dp.nacc; kk += kPairWG) {
+            int kk = tid;
+            if constexpr (M2 > 1) {
+                // elasticity: M2 values per CSR entry, so each thread runs
+                // many iterations; four at a time, their row lookups (two
+                // dependent LDS reads each) in flight together
+                for (; kk + 3 * kPairWG < M2 * dp.nacc; kk += 4 * kPairWG) {
+                    int r[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) r[u] = rowof[(kk + u * kPairWG) / M2];
+                    int4 ri[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) ri[u] = rinf[r[u]];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        pv.values[dp.vo + int64_t(M2) * ri[u].x + (kk + u * kPairWG - M2 * ri[u].z)] =
+                            outb[kk + u * kPairWG];
+                }
+            }
+            for (; kk < M2 * dp.nacc; kk += kPairWG) {
                 const int4 ri = rinf[rowof[kk / M2]];
                 pv.values[dp.vo + int64_t(M2) * ri.x + (kk - M2 * ri.z)] = outb[kk];
             }
