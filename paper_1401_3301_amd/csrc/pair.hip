@@ -512,7 +512,14 @@ __device__ __forceinline__ void pair_run(const PairView &pv, double lam, double 
         }
         const int dv_nnn = load_desc_vec(pv, bnnn, lane);
         __syncthreads();
-        // L7: element phase
+        // L7: element phase.  The phases end at barriers, so each lasts as
+        // long as its busiest wavefront: those with a second element pass
+        // here, and in the pair sums wavefront 0 (the longest task of every
+        // block, the one holding the diagonal pairs, goes to it).  They get
+        // the higher issue priority for the phase against the other
+        // workgroup's wavefronts on their SIMD.
+        const bool two_passes = kPairWG + wave * 64 < dc.ne;
+        if (two_passes) __builtin_amdgcn_s_setprio(2);
 #pragma unroll
         for (int u = 0; u < kElemSlots; ++u) {
             const int e = u * kPairWG + tid;
@@ -538,8 +545,10 @@ __device__ __forceinline__ void pair_run(const PairView &pv, double lam, double 
                 for (int t = 0; t < NV; ++t) ev[e * NV + t] = 0.0;
             }
         }
+        if (two_passes) __builtin_amdgcn_s_setprio(0);
         __syncthreads();
         // L10: pair sums
+        if (wave == 0) __builtin_amdgcn_s_setprio(3);
         double X[S][NX];
 #pragma unroll
         for (int s = 0; s < S; ++s) {
@@ -659,6 +668,7 @@ __device__ __forceinline__ void pair_run(const PairView &pv, double lam, double 
                 }
             }
         }
+        if (wave == 0) __builtin_amdgcn_s_setprio(0);
         __syncthreads();
         // L12: output image of the current block
 #pragma unroll
